@@ -1,0 +1,193 @@
+#!/usr/bin/env python3
+"""Benchmark of threshold / symmetric queries over bitmaps on one MI355X.
+
+Default workload ("large"): N = 256 uncompressed bitmaps of r = 2^26 bits
+(2 GiB), per-bitmap density log-uniform in [1e-4, 0.5].  One step runs the
+workload's query set once: thresholds 2, 16, 128, 255, the interval query
+2 <= count <= 10 and parity, each reading all 2 GiB.  Inputs are generated on
+the GPU before timing and stay resident in HBM.
+
+Prints one JSON line: logical input GB/s over the timed steps, the roofline of
+the dense counter kernel (algorithmic bytes per launch over its mean launch
+time, taken with HIP events on the library's stream), and the CPU oracle timed
+on a bounded sample of the same workload on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="large", choices=["large", "small"])
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target CPU time of the oracle baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def load_traffic(kernel_key: str):
+    """HBM bytes per launch measured by rocprofv3 counters (profiles/traffic.json),
+    or None if not measured for the current kernel build."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh).get(kernel_key)
+    except (OSError, ValueError):
+        return None
+    if not rec:
+        return None
+    src = os.path.join(ROOT, "paper_1402_4073_amd", "csrc", "tq_dense.hip")
+    import hashlib
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if rec.get("source_sha") != h:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(pool_rows, n, nwords, r_bits, queries, target_s):
+    """The oracle as it stands, on a contiguous column sample of every bitmap."""
+    import numpy as np
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    m = 2048
+    sample_host = None
+    while True:
+        cols = np.arange(m, dtype=np.uint64)
+        words = np.stack([r[:m].cpu().numpy().view(np.uint64) for r in pool_rows])
+        t0 = time.perf_counter()
+        for kind, arg in queries:
+            if kind == "threshold":
+                oracle.threshold_cols(words, cols, r_bits, arg)
+            else:
+                oracle.symmetric_cols(words, cols, r_bits, arg)
+        dt = time.perf_counter() - t0
+        sample_host = (m, dt)
+        if dt >= target_s or m >= nwords:
+            break
+        m = int(min(nwords, max(2 * m, m * target_s / max(dt, 1e-3) * 1.1)))
+    m, dt = sample_host
+    in_bytes = len(queries) * n * m * 8
+    return {"value": round(in_bytes / dt / 1e9, 4), "unit": "GB/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "%d of %d word columns of all %d bitmaps, %d queries, %.1f s"
+                      % (m, nwords, n, len(queries), dt)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import tqgen
+    import oracle
+    from paper_1402_4073_amd import binding as tq
+
+    dev = torch.device("cuda:0")
+    if args.workload == "large":
+        bs = tqgen.large_set(2)
+        thetas = tqgen.LARGE["thetas"]
+        lo, hi = tqgen.LARGE["interval"]
+        desc = ("large uncompressed: N=256 bitmaps, r=2^26 bits, density log-uniform "
+                "[1e-4,0.5]; thresholds 2,16,128,255 + interval 2..10 + parity")
+    else:
+        bs = tqgen.small_set(1)
+        thetas = tqgen.SMALL["thetas"]
+        lo, hi = 2, 10
+        desc = "small: N=16 bitmaps, r=2^20 bits, Bernoulli(0.05); thresholds 1,2,8,16 + interval + parity"
+    n, nw, r = bs.n, bs.nwords, bs.r_bits
+    pool = torch.empty((n, nw), dtype=torch.int64, device=dev)
+    tqgen.fill_gpu(bs, pool.view(-1))
+    rows = [pool[j] for j in range(n)]
+    out = torch.empty(nw, dtype=torch.int64, device=dev)
+    queries = [("threshold", t) for t in thetas]
+    queries += [("symmetric", oracle.truth_interval(n, lo, hi)), ("symmetric", oracle.truth_parity(n))]
+
+    ctx = tq.tq_create(0)
+    stream = torch.cuda.Stream(device=dev)
+    events = []
+
+    def one_step(record):
+        for kind, arg in queries:
+            if record:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+            if kind == "threshold":
+                tq.tq_threshold(ctx, rows, r, arg, out, stream)
+            else:
+                tq.tq_symmetric(ctx, rows, r, arg, out, stream)
+            if record:
+                e1.record(stream)
+                events.append((e0, e1))
+
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            one_step(False)
+        torch.cuda.synchronize()
+        if tq.tq_ctx_check(ctx, stream) != 0:
+            raise RuntimeError("device error during warmup")
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            one_step(True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+    st = tq.tq_ctx_check(ctx, stream)
+    if st != 0:
+        raise RuntimeError("device error: %s" % tq.status_string(st))
+    elapsed = t1 - t0
+    kernel_ms = [a.elapsed_time(b) for a, b in events]
+    mean_kernel_s = sum(kernel_ms) / len(kernel_ms) / 1e3
+    in_bytes_query = n * nw * 8
+    out_bytes_query = nw * 8
+    alg_bytes = in_bytes_query + out_bytes_query
+    achieved = alg_bytes / mean_kernel_s / 1e9
+    value = len(queries) * in_bytes_query * args.steps / elapsed / 1e9
+    kernel_key = "dense_kernel<K=%d>/%s" % (max(4, n.bit_length()), args.workload)
+    traffic = load_traffic(kernel_key)
+
+    rec = {
+        "metric": "input GB/s per threshold query (logical input bytes / wall time)",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64 bitwise",
+        "data": "synthetic (seeded counter-based generator, resident in HBM)",
+        "config": {"workload": desc, "n_bitmaps": n, "r_bits": r, "queries_per_step": len(queries),
+                   "input_bytes_per_query": in_bytes_query},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": kernel_key, "mean_launch_us": round(mean_kernel_s * 1e6, 2),
+                     "alg_bytes_per_launch": alg_bytes},
+        "per_query_ms": [round(sum(kernel_ms[i::len(queries)]) / args.steps, 4) for i in range(len(queries))],
+    }
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(rows, n, nw, r, queries, args.cpu_seconds)
+    tq.tq_destroy(ctx)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

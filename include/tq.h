@@ -1,0 +1,117 @@
+/*
+ * tq — threshold and symmetric queries over bitmaps on AMD Instinct MI355X.
+ *
+ * C ABI of libtq.so.  The operations follow the problem statement of Kaser &
+ * Lemire, "Threshold and Symmetric Functions over Bitmaps" (TR-14-001):
+ *
+ *   Given N bitmaps B_1..B_N over positions 0..r-1 and a threshold T, the
+ *   T-threshold bitmap has bit p set iff at least T of the inputs have bit p
+ *   set (Introduction, "Formulation"; section 2.3).  A symmetric function is
+ *   any map f from the per-position count c in [0, N] to {0, 1} (sections 2.2
+ *   and 4.2); bit p of its result is f(c(p)).
+ *
+ * Conventions shared by every call below.
+ *
+ *   Bitmap layout (section 2.1, uncompressed bitmaps): a bitmap of r bits is
+ *   ceil(r/64) little-endian uint64 words in device memory; position p is bit
+ *   (p mod 64) of word p div 64.  Input bits at positions >= r are ignored;
+ *   output bits at positions >= r are written as zero.  Input words must be
+ *   8-byte aligned; 16-byte alignment of every input and of the output lets
+ *   the library use 16-byte loads.
+ *
+ *   Inputs may repeat (the same pointer several times counts several times:
+ *   integer weights by replication, section 2.3).  The output must not
+ *   overlap any input.
+ *
+ *   Pointer arrays (`ptrs`) are HOST arrays of N DEVICE pointers.  The
+ *   library copies them (and truth tables) at call time; the caller may reuse
+ *   or free its host arrays as soon as the call returns.  Device buffers are
+ *   owned by the caller and must stay valid until the work queued on
+ *   `stream` has completed.  The library never frees or retains caller
+ *   memory.
+ *
+ *   Every call is asynchronous on `stream` (a hipStream_t; NULL is the
+ *   default stream).  Argument errors are detected on the host and returned
+ *   immediately, with nothing queued.  Errors that only the device can see
+ *   (a malformed compressed stream, an output capacity that is too small) are
+ *   recorded in the context's status word and returned by tq_ctx_check.
+ *
+ *   A context is not thread-safe: use one per host thread, or lock around it.
+ *
+ *   Status codes are the negative values of tq_status; no call throws.
+ */
+#ifndef TQ_H
+#define TQ_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TQ_API_VERSION 1
+
+/* Largest N accepted by the dense calls (the in-register counter has at most
+ * 16 bit planes). */
+#define TQ_MAX_INPUTS 65535u
+
+typedef enum tq_status {
+  TQ_OK = 0,
+  TQ_EINVAL = -1,     /* bad argument: NULL pointer, N == 0, N too large, misaligned or overlapping buffers */
+  TQ_ENOMEM = -2,     /* device or pinned host allocation failed */
+  TQ_EFORMAT = -3,    /* malformed run-length stream (device-detected) */
+  TQ_ECAPACITY = -4,  /* output capacity too small; the required length is reported */
+  TQ_EDEVICE = -5,    /* a HIP runtime call failed */
+  TQ_EBUSY = -6,      /* admission refused: the batch ring or workspace is full, retry later */
+  TQ_ENOTSUP = -7     /* the request is valid but not supported by this build */
+} tq_status;
+
+typedef struct tq_ctx tq_ctx;
+
+/* Create a context on HIP device `device` (the device is made current for
+ * the call).  *out receives the context, or NULL on failure. */
+tq_status tq_create(tq_ctx** out, int device);
+
+/* Destroy a context: waits for the work the context still tracks, then frees
+ * its device workspace and pinned staging memory.  NULL is accepted. */
+tq_status tq_destroy(tq_ctx* ctx);
+
+/* Static, human-readable name of a status code. */
+const char* tq_status_string(int status);
+
+/* Wait for `stream`, then return (and clear) the first device-detected error
+ * recorded by calls on this context, or TQ_EDEVICE if a HIP call failed. */
+tq_status tq_ctx_check(tq_ctx* ctx, hipStream_t stream);
+
+/*
+ * Threshold query (section 2.3, the function written there as
+ * theta(T, {B_1..B_N})):
+ *   d_out bit p = [ #{ j : bit p of ptrs[j] is set } >= theta ]   for p < r_bits,
+ *   d_out bit p = 0                                                for p >= r_bits.
+ * ptrs: host array of n device pointers, each to ceil(r_bits/64) words.
+ * n in [1, TQ_MAX_INPUTS].  theta may be any value: theta == 0 gives all ones
+ * on [0, r_bits) and theta > n gives all zeros.  r_bits == 0 writes nothing.
+ * d_out: ceil(r_bits/64) device words, overwritten.
+ */
+tq_status tq_threshold(tq_ctx* ctx, const uint64_t* const* ptrs, uint32_t n, uint64_t r_bits,
+                       uint32_t theta, uint64_t* d_out, hipStream_t stream);
+
+/*
+ * Symmetric query (section 2.2; counter methods take any map [0, N] -> {0,1},
+ * section 4.2):
+ *   d_out bit p = f(count(p)) for p < r_bits, 0 beyond.
+ * h_truth: HOST array of ceil((n+1)/64) words; bit c (bit c mod 64 of word
+ * c div 64) is f(c) for c in [0, n].  Bits above n are ignored.  Examples:
+ * parity (f(c) = c mod 2), the interval query 2 <= c <= 10, the delta
+ * function c == k, majority (c >= ceil(n/2)).
+ * Other arguments as for tq_threshold.
+ */
+tq_status tq_symmetric(tq_ctx* ctx, const uint64_t* const* ptrs, uint32_t n, uint64_t r_bits,
+                       const uint64_t* h_truth, uint64_t* d_out, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TQ_H */

@@ -1,0 +1,197 @@
+"""ctypes binding of libtq.so: argument marshalling only.
+
+Every function here has the name of the C entry point it forwards to and
+does nothing but convert Python/torch arguments into plain pointers and
+sizes.  All computation runs in the HIP kernels of libtq.so; if the library
+is not built this module raises on import instead of falling back to
+anything else.
+
+torch is imported first on purpose: PyTorch ships its own copy of the HIP
+runtime (same soname as /opt/rocm's), and libtq.so must bind to that copy so
+that torch-allocated device memory and torch streams are the library's too.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # noqa: F401  (must precede loading libtq.so)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtq.so")
+
+TQ_OK = 0
+TQ_EINVAL = -1
+TQ_ENOMEM = -2
+TQ_EFORMAT = -3
+TQ_ECAPACITY = -4
+TQ_EDEVICE = -5
+TQ_EBUSY = -6
+TQ_ENOTSUP = -7
+TQ_MAX_INPUTS = 65535
+
+_P = ctypes.c_void_p
+_U32 = ctypes.c_uint32
+_U64 = ctypes.c_uint64
+_INT = ctypes.c_int
+
+
+class TQError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__("%s: %s" % (where, status_string(status)))
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            "libtq.so is not built (%s); run __graft_entry__.build() or "
+            "python paper_1402_4073_amd/build.py" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "tq_create": (_INT, [ctypes.POINTER(_P), _INT]),
+        "tq_destroy": (_INT, [_P]),
+        "tq_status_string": (ctypes.c_char_p, [_INT]),
+        "tq_ctx_check": (_INT, [_P, _P]),
+        "tq_threshold": (_INT, [_P, _P, _U32, _U64, _U32, _P, _P]),
+        "tq_symmetric": (_INT, [_P, _P, _U32, _U64, _P, _P, _P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def lib() -> ctypes.CDLL:
+    return _lib
+
+
+def hip_runtimes_loaded() -> list:
+    """Distinct libamdhip64 files mapped into this process (must be one)."""
+    paths = set()
+    try:
+        with open("/proc/self/maps") as fh:
+            for line in fh:
+                if "libamdhip64" in line:
+                    paths.add(os.path.realpath(line.split()[-1]))
+    except OSError:
+        pass
+    return sorted(paths)
+
+
+def status_string(status: int) -> str:
+    return _lib.tq_status_string(status).decode()
+
+
+def _check(status: int, where: str) -> None:
+    if status != TQ_OK:
+        raise TQError(status, where)
+
+
+def _ptr(x) -> int:
+    """Device address of a tensor, or an int taken as an address."""
+    if isinstance(x, torch.Tensor):
+        return x.data_ptr()
+    return int(x)
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return int(stream)
+
+
+def ptr_array(inputs):
+    """Host array of device pointers (ctypes), from tensors or addresses."""
+    arr = (_U64 * max(1, len(inputs)))(*[_ptr(t) for t in inputs])
+    return arr
+
+
+def _u64_host(words):
+    arr = (_U64 * max(1, len(words)))(*[int(w) for w in words])
+    return arr
+
+
+def truth_words(truth) -> list:
+    """Pack a 0/1 truth table f[0..n] into 64-bit words (bit c = f(c))."""
+    vals = [int(v) & 1 for v in truth]
+    words = [0] * ((len(vals) + 63) // 64)
+    for c, v in enumerate(vals):
+        if v:
+            words[c // 64] |= 1 << (c % 64)
+    return words
+
+
+# ------------------------------------------------------------------ context
+def tq_create(device: int = 0) -> int:
+    h = _P()
+    _check(_lib.tq_create(ctypes.byref(h), device), "tq_create")
+    return h.value
+
+
+def tq_destroy(ctx: int) -> None:
+    _check(_lib.tq_destroy(ctx), "tq_destroy")
+
+
+def tq_ctx_check(ctx: int, stream=None) -> int:
+    """Return the status (0 or a negative tq_status) without raising."""
+    return _lib.tq_ctx_check(ctx, _stream(stream))
+
+
+# ------------------------------------------------------------------ queries
+def tq_threshold(ctx: int, inputs, r_bits: int, theta: int, out, stream=None) -> None:
+    ptrs = ptr_array(inputs)
+    _check(_lib.tq_threshold(ctx, ptrs, len(inputs), r_bits, theta, _ptr(out), _stream(stream)),
+           "tq_threshold")
+
+
+def tq_symmetric(ctx: int, inputs, r_bits: int, truth, out, stream=None) -> None:
+    """truth: sequence of 0/1 values f(0..n) (packed here into words)."""
+    ptrs = ptr_array(inputs)
+    tw = _u64_host(truth_words(truth))
+    _check(_lib.tq_symmetric(ctx, ptrs, len(inputs), r_bits, tw, _ptr(out), _stream(stream)),
+           "tq_symmetric")
+
+
+def raw_threshold(ctx: int, ptrs, n: int, r_bits: int, theta: int, out_ptr: int, stream=None) -> int:
+    """Unchecked call returning the status (for error-path tests)."""
+    return _lib.tq_threshold(ctx, ptrs, n, r_bits, theta, out_ptr, _stream(stream))
+
+
+class Context:
+    """Owns a tq context; thin convenience wrapper over the functions above."""
+
+    def __init__(self, device: int = 0):
+        self.handle = tq_create(device)
+
+    def close(self):
+        if self.handle:
+            tq_destroy(self.handle)
+            self.handle = 0
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def threshold(self, inputs, r_bits, theta, out, stream=None):
+        tq_threshold(self.handle, inputs, r_bits, theta, out, stream)
+
+    def symmetric(self, inputs, r_bits, truth, out, stream=None):
+        tq_symmetric(self.handle, inputs, r_bits, truth, out, stream)
+
+    def check(self, stream=None) -> int:
+        return tq_ctx_check(self.handle, stream)

@@ -1,0 +1,416 @@
+// Dense threshold / symmetric kernels for gfx950.
+//
+// One lane owns WPL consecutive 64-bit word columns.  For every input bitmap
+// it loads its WPL words (a wave reads 64*WPL*8 contiguous bytes per input)
+// and adds them into a bit-sliced vertical counter held in registers: plane k
+// holds bit k of the per-position count of 64*WPL positions.
+//
+// The counter is fed by a carry-save adder tree.  Sixteen inputs at a time
+// are reduced Harley-Seal style: full adders (sum = a^b^c, carry =
+// majority(a,b,c), each one v_bitop3_b32 per 32-bit half) fold pairs of
+// equal-weight bit vectors into the accumulator planes 0..3 and pass one
+// carry of weight 16 upward, which is rippled into planes 4..K-1 with half
+// adders.  This is the sideways-sum arrangement of full adders of section
+// 4.4.4 (about one full adder per input) run as a stream over the inputs,
+// with the live state being the K = O(log N) planes, as in the carry-save
+// vertical counter (CSvCkt) of the same section.
+//
+// The count is then compared with the query (section 4.4.4, comparison
+// against a constant): count > a is the OR, over the zero bits j of a, of
+// plane j ANDed with every plane above j where a has a one.  The bits of a
+// are the same for the whole grid, so the walk over them compiles to scalar
+// branches.  Symmetric functions use that comparator on interval ends, the
+// low plane for parity, or a per-bit table lookup for arbitrary truth tables.
+#include "tq_internal.h"
+
+namespace tq {
+namespace {
+
+template <int WPL>
+struct Vec {
+  uint64_t w[WPL];
+};
+
+typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t lo32(uint64_t x) { return (uint32_t)x; }
+__device__ __forceinline__ uint32_t hi32(uint64_t x) { return (uint32_t)(x >> 32); }
+__device__ __forceinline__ uint64_t join(uint32_t lo, uint32_t hi) {
+  return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+// three-input XOR and majority, one v_bitop3_b32 per 32-bit half
+__device__ __forceinline__ uint64_t xor3(uint64_t a, uint64_t b, uint64_t c) {
+  return join(__builtin_amdgcn_bitop3_b32(lo32(a), lo32(b), lo32(c), 0x96),
+              __builtin_amdgcn_bitop3_b32(hi32(a), hi32(b), hi32(c), 0x96));
+}
+__device__ __forceinline__ uint64_t maj3(uint64_t a, uint64_t b, uint64_t c) {
+  return join(__builtin_amdgcn_bitop3_b32(lo32(a), lo32(b), lo32(c), 0xE8),
+              __builtin_amdgcn_bitop3_b32(hi32(a), hi32(b), hi32(c), 0xE8));
+}
+
+// full adder: h <- h ^ a ^ b, c <- majority(h, a, b)
+template <int WPL>
+__device__ __forceinline__ void csa(Vec<WPL>& h, const Vec<WPL>& a, const Vec<WPL>& b, Vec<WPL>& c) {
+#pragma unroll
+  for (int i = 0; i < WPL; ++i) {
+    const uint64_t hh = h.w[i];
+    c.w[i] = maj3(hh, a.w[i], b.w[i]);
+    h.w[i] = xor3(hh, a.w[i], b.w[i]);
+  }
+}
+
+// Fold 2^L inputs of weight 1 into planes 0..L-1; return the carry of weight 2^L.
+template <int L, int K, int WPL>
+__device__ __forceinline__ Vec<WPL> fold(Vec<WPL> (&P)[K], const Vec<WPL>* x) {
+  Vec<WPL> c;
+  if constexpr (L == 1) {
+    csa<WPL>(P[0], x[0], x[1], c);
+  } else {
+    const Vec<WPL> a = fold<L - 1, K, WPL>(P, x);
+    const Vec<WPL> b = fold<L - 1, K, WPL>(P, x + (1 << (L - 1)));
+    csa<WPL>(P[L - 1], a, b, c);
+  }
+  return c;
+}
+
+constexpr int kBlockLog = 4;
+constexpr int kBlock = 1 << kBlockLog;  // inputs folded per step
+
+// add 16 input vectors to the counter
+template <int K, int WPL>
+__device__ __forceinline__ void add_block(Vec<WPL> (&P)[K], const Vec<WPL>* x) {
+  Vec<WPL> c = fold<kBlockLog, K, WPL>(P, x);
+#pragma unroll
+  for (int k = kBlockLog; k < K; ++k) {
+#pragma unroll
+    for (int i = 0; i < WPL; ++i) {
+      const uint64_t t = P[k].w[i] & c.w[i];
+      P[k].w[i] ^= c.w[i];
+      c.w[i] = t;
+    }
+  }
+}
+
+template <int WPL, bool Guard>
+__device__ __forceinline__ Vec<WPL> load_cols(const uint64_t* __restrict__ p, uint64_t w,
+                                             uint64_t nwords) {
+  Vec<WPL> v;
+  if constexpr (!Guard) {
+    if constexpr (WPL == 2) {
+      const u64x2 t = __builtin_nontemporal_load(reinterpret_cast<const u64x2*>(p + w));
+      v.w[0] = t[0];
+      v.w[1] = t[1];
+    } else {
+      v.w[0] = __builtin_nontemporal_load(p + w);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < WPL; ++i) v.w[i] = (w + i < nwords) ? p[w + i] : 0;
+  }
+  return v;
+}
+
+// stream inputs [i0, i1) into the counter
+template <int K, int WPL, bool Guard>
+__device__ __forceinline__ void accumulate(Vec<WPL> (&P)[K], const uint64_t* const* __restrict__ ptrs,
+                                           uint32_t i0, uint32_t i1, uint64_t w, uint64_t nwords) {
+  uint32_t i = i0;
+  for (; i + kBlock <= i1; i += kBlock) {
+    Vec<WPL> x[kBlock];
+#pragma unroll
+    for (int u = 0; u < kBlock; ++u) x[u] = load_cols<WPL, Guard>(ptrs[i + u], w, nwords);
+    add_block<K, WPL>(P, x);
+  }
+  if (i < i1) {
+    Vec<WPL> x[kBlock];
+#pragma unroll
+    for (int u = 0; u < kBlock; ++u) {
+      if (i + u < i1) {
+        x[u] = load_cols<WPL, Guard>(ptrs[i + u], w, nwords);
+      } else {
+#pragma unroll
+        for (int q = 0; q < WPL; ++q) x[u].w[q] = 0;
+      }
+    }
+    add_block<K, WPL>(P, x);
+  }
+}
+
+// count > a, for a < 2^K (a is grid-uniform)
+template <int K, int WPL>
+__device__ __forceinline__ Vec<WPL> greater_than(const Vec<WPL> (&P)[K], uint32_t a) {
+  Vec<WPL> pm, r;
+#pragma unroll
+  for (int i = 0; i < WPL; ++i) { pm.w[i] = ~(uint64_t)0; r.w[i] = 0; }
+#pragma unroll
+  for (int j = K - 1; j >= 0; --j) {
+    if ((a >> j) & 1u) {
+#pragma unroll
+      for (int i = 0; i < WPL; ++i) pm.w[i] &= P[j].w[i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < WPL; ++i) r.w[i] |= pm.w[i] & P[j].w[i];
+    }
+  }
+  return r;
+}
+
+// count >= x for any x (x == 0: everything; x > n: nothing)
+template <int K, int WPL>
+__device__ __forceinline__ Vec<WPL> at_least(const Vec<WPL> (&P)[K], uint32_t x, uint32_t n) {
+  Vec<WPL> r;
+  if (x == 0) {
+#pragma unroll
+    for (int i = 0; i < WPL; ++i) r.w[i] = ~(uint64_t)0;
+  } else if (x > n) {
+#pragma unroll
+    for (int i = 0; i < WPL; ++i) r.w[i] = 0;
+  } else {
+    r = greater_than<K, WPL>(P, x - 1);
+  }
+  return r;
+}
+
+template <int K, int WPL>
+__device__ __forceinline__ Vec<WPL> epilogue(const Vec<WPL> (&P)[K], const EpiParams& e, uint32_t n,
+                                            const uint32_t* lds_table) {
+  Vec<WPL> r;
+  if (e.kind == EPI_THRESH) {
+    r = at_least<K, WPL>(P, e.theta, n);
+  } else if (e.kind == EPI_PARITY) {
+    r = P[0];
+  } else if (e.kind == EPI_INTERVALS) {
+#pragma unroll
+    for (int i = 0; i < WPL; ++i) r.w[i] = 0;
+    for (int t = 0; t < e.nint; ++t) {
+      const Vec<WPL> a = at_least<K, WPL>(P, e.lo[t], n);
+      const Vec<WPL> b = at_least<K, WPL>(P, e.hi1[t], n);
+#pragma unroll
+      for (int i = 0; i < WPL; ++i) r.w[i] |= a.w[i] & ~b.w[i];
+    }
+  } else {
+    // generic truth table: rebuild each position's count from the planes
+#pragma unroll
+    for (int i = 0; i < WPL; ++i) {
+      uint64_t o = 0;
+      for (int b = 0; b < 64; ++b) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) c |= (uint32_t)((P[k].w[i] >> b) & 1) << k;
+        o |= (uint64_t)((lds_table[c >> 5] >> (c & 31)) & 1u) << b;
+      }
+      r.w[i] = o;
+    }
+  }
+  if (e.invert) {
+#pragma unroll
+    for (int i = 0; i < WPL; ++i) r.w[i] = ~r.w[i];
+  }
+  return r;
+}
+
+template <int S>
+constexpr int groups_per_block() {
+  return S >= 4 ? 1 : 4 / S;
+}
+
+// K: counter planes, WPL: words per lane, S: waves that split the inputs of
+// one column group.  A workgroup holds G column groups of S waves each.
+template <int K, int WPL, int S>
+__global__ __launch_bounds__(64 * S * groups_per_block<S>()) void dense_kernel(
+    const uint64_t* const* __restrict__ ptrs, uint32_t n, uint64_t nwords, uint64_t tail_mask,
+    uint64_t* __restrict__ out, EpiParams epi) {
+  constexpr int G = groups_per_block<S>();
+  extern __shared__ uint64_t lds[];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int g = wave / S;
+  const int s = wave - g * S;
+  const uint64_t base = ((uint64_t)blockIdx.x * G + g) * (64 * WPL);
+  const uint64_t w = base + (uint64_t)lane * WPL;
+
+  // truth table for the generic epilogue, staged once per workgroup
+  uint32_t* lds_table = reinterpret_cast<uint32_t*>(lds);
+  constexpr int red_slots = S / 2;
+  uint64_t* lds_red = lds;
+  if (epi.kind == EPI_TABLE) {
+    for (uint32_t t = threadIdx.x; t < epi.table_words; t += blockDim.x) lds_table[t] = epi.table[t];
+    lds_red = lds + (epi.table_words + 1) / 2;
+    __syncthreads();
+  }
+
+  const uint32_t per = (n + S - 1) / S;
+  const uint32_t i0 = (uint32_t)s * per < n ? (uint32_t)s * per : n;
+  const uint32_t i1 = i0 + per < n ? i0 + per : n;
+
+  Vec<WPL> P[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int i = 0; i < WPL; ++i) P[k].w[i] = 0;
+
+  if (base < nwords) {
+    if (base + 64 * WPL <= nwords)
+      accumulate<K, WPL, false>(P, ptrs, i0, i1, w, nwords);
+    else
+      accumulate<K, WPL, true>(P, ptrs, i0, i1, w, nwords);
+  }
+
+  if constexpr (S > 1) {
+    // tree-add the partial counts of the S waves of this column group
+#pragma unroll
+    for (int step = 1; step < S; step <<= 1) {
+      const int slot = s / (2 * step);
+      uint64_t* red = lds_red + (((size_t)g * red_slots + slot) * K) * WPL * 64;
+      if ((s % (2 * step)) == step) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+          for (int i = 0; i < WPL; ++i) red[(k * WPL + i) * 64 + lane] = P[k].w[i];
+      }
+      __syncthreads();
+      if ((s % (2 * step)) == 0 && s + step < S) {
+        Vec<WPL> c;
+#pragma unroll
+        for (int i = 0; i < WPL; ++i) c.w[i] = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+#pragma unroll
+          for (int i = 0; i < WPL; ++i) {
+            const uint64_t q = red[(k * WPL + i) * 64 + lane];
+            const uint64_t p = P[k].w[i];
+            P[k].w[i] = xor3(p, q, c.w[i]);
+            c.w[i] = maj3(p, q, c.w[i]);
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (s != 0) return;
+  }
+
+  if (base >= nwords) return;
+  const Vec<WPL> r = epilogue<K, WPL>(P, epi, n, lds_table);
+  if (base + 64 * WPL <= nwords) {
+    Vec<WPL> v = r;
+#pragma unroll
+    for (int i = 0; i < WPL; ++i)
+      if (w + i == nwords - 1) v.w[i] &= tail_mask;
+    if constexpr (WPL == 2) {
+      u64x2 t;
+      t[0] = v.w[0];
+      t[1] = v.w[1];
+      __builtin_nontemporal_store(t, reinterpret_cast<u64x2*>(out + w));
+    } else {
+      __builtin_nontemporal_store(v.w[0], out + w);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < WPL; ++i) {
+      if (w + i < nwords) out[w + i] = (w + i == nwords - 1) ? (r.w[i] & tail_mask) : r.w[i];
+    }
+  }
+}
+
+__global__ void fill_kernel(uint64_t* __restrict__ out, uint64_t nwords, uint64_t value,
+                            uint64_t tail_mask) {
+  for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nwords;
+       w += (uint64_t)gridDim.x * blockDim.x)
+    out[w] = (w == nwords - 1) ? (value & tail_mask) : value;
+}
+
+typedef void (*DenseFn)(const uint64_t* const*, uint32_t, uint64_t, uint64_t, uint64_t*, EpiParams);
+
+template <int K>
+DenseFn pick_ws(int wpl, int split) {
+  if (wpl == 2) {
+    switch (split) {
+      case 1: return dense_kernel<K, 2, 1>;
+      case 2: return dense_kernel<K, 2, 2>;
+      case 4: return dense_kernel<K, 2, 4>;
+      case 8: return dense_kernel<K, 2, 8>;
+    }
+  } else {
+    switch (split) {
+      case 1: return dense_kernel<K, 1, 1>;
+      case 2: return dense_kernel<K, 1, 2>;
+      case 4: return dense_kernel<K, 1, 4>;
+      case 8: return dense_kernel<K, 1, 8>;
+    }
+  }
+  return nullptr;
+}
+
+DenseFn pick(int K, int wpl, int split) {
+  switch (K) {
+    case 4: return pick_ws<4>(wpl, split);
+    case 5: return pick_ws<5>(wpl, split);
+    case 6: return pick_ws<6>(wpl, split);
+    case 7: return pick_ws<7>(wpl, split);
+    case 8: return pick_ws<8>(wpl, split);
+    case 9: return pick_ws<9>(wpl, split);
+    case 10: return pick_ws<10>(wpl, split);
+    case 11: return pick_ws<11>(wpl, split);
+    case 12: return pick_ws<12>(wpl, split);
+    case 13: return pick_ws<13>(wpl, split);
+    case 16: return pick_ws<16>(wpl, split);
+  }
+  return nullptr;
+}
+
+}  // namespace
+
+int dense_planes_for(uint32_t n) {
+  int k = bit_length(n);
+  if (k < 4) k = 4;
+  if (k > 13) k = 16;
+  return k;
+}
+
+DenseConfig choose_dense_config(uint32_t n, uint64_t nwords, bool aligned16, int num_cus) {
+  DenseConfig c;
+  c.K = dense_planes_for(n);
+  c.wpl = aligned16 ? 2 : 1;
+  // enough waves to keep every SIMD streaming: aim for >= 8 waves per CU
+  const uint64_t target_waves = (uint64_t)num_cus * 8;
+  uint64_t groups = (nwords + 64 * c.wpl - 1) / (64 * c.wpl);
+  if (c.wpl == 2 && groups < target_waves) {
+    c.wpl = 1;
+    groups = (nwords + 63) / 64;
+  }
+  c.split = 1;
+  while (c.split < 8 && groups * c.split < target_waves && n / (2 * c.split) >= (uint32_t)kBlock)
+    c.split *= 2;
+  return c;
+}
+
+hipError_t launch_dense(const DenseConfig& cfg, const uint64_t* const* d_ptrs, uint32_t n,
+                        uint64_t nwords, uint64_t tail_mask, uint64_t* d_out, const EpiParams& epi,
+                        hipStream_t stream) {
+  DenseFn fn = pick(cfg.K, cfg.wpl, cfg.split);
+  if (!fn) return hipErrorInvalidValue;
+  const int G = cfg.split >= 4 ? 1 : 4 / cfg.split;
+  const uint64_t cols_per_block = (uint64_t)64 * cfg.wpl * G;
+  const uint64_t blocks = (nwords + cols_per_block - 1) / cols_per_block;
+  if (blocks == 0) return hipSuccess;
+  if (blocks > 0x7FFFFFFFull) return hipErrorInvalidValue;
+  size_t lds = 0;
+  if (epi.kind == EPI_TABLE) lds += ((size_t)epi.table_words + 1) / 2 * 8;
+  if (cfg.split > 1) lds += (size_t)G * (cfg.split / 2) * cfg.K * cfg.wpl * 64 * 8;
+  hipLaunchKernelGGL(fn, dim3((uint32_t)blocks), dim3(64 * cfg.split * G), lds, stream, d_ptrs, n,
+                     nwords, tail_mask, d_out, epi);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(uint64_t* d_out, uint64_t nwords, uint64_t value, uint64_t tail_mask,
+                       hipStream_t stream) {
+  if (nwords == 0) return hipSuccess;
+  uint64_t blocks = (nwords + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(fill_kernel, dim3((uint32_t)blocks), dim3(256), 0, stream, d_out, nwords, value,
+                     tail_mask);
+  return hipGetLastError();
+}
+
+}  // namespace tq

@@ -1,0 +1,364 @@
+// Host side of libtq: context, staging cache, query planning, ABI entry points.
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+
+#include "tq_internal.h"
+
+namespace tq {
+
+tq_status record_hip(tq_ctx* ctx, hipError_t e) {
+  if (e == hipSuccess) return TQ_OK;
+  if (ctx && !ctx->sticky_host_error) ctx->sticky_host_error = (int)e;
+  return e == hipErrorOutOfMemory ? TQ_ENOMEM : TQ_EDEVICE;
+}
+
+// ------------------------------------------------------------ blob cache
+namespace {
+
+constexpr size_t kMaxBlobs = 64;
+
+uint64_t hash_words(const uint64_t* w, size_t n) {
+  uint64_t h = 0x84222325CBF29CE4ull ^ n;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= w[i];
+    h *= 0x100000001B3ull;
+    h ^= h >> 29;
+  }
+  return h;
+}
+
+hipError_t blob_wait_idle(Blob& b) {
+  for (auto& u : b.uses) {
+    hipError_t e = hipEventSynchronize(u.second);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+void blob_release(Blob& b) {
+  blob_wait_idle(b);
+  for (auto& u : b.uses) hipEventDestroy(u.second);
+  b.uses.clear();
+  if (b.copied) hipEventDestroy(b.copied);
+  b.copied = nullptr;
+  if (b.d) hipFree(b.d);
+  if (b.h_pinned) hipHostFree(b.h_pinned);
+  b.d = nullptr;
+  b.h_pinned = nullptr;
+  b.cap_words = 0;
+  b.valid = false;
+}
+
+}  // namespace
+
+const void* blob_get(tq_ctx* ctx, const uint64_t* words, size_t count, hipStream_t stream,
+                     Blob** which) {
+  const uint64_t h = hash_words(words, count);
+  for (auto& b : ctx->blobs) {
+    if (b.valid && b.hash == h && b.content.size() == count &&
+        memcmp(b.content.data(), words, count * 8) == 0) {
+      if (b.copy_stream != stream) {
+        hipError_t e = hipStreamWaitEvent(stream, b.copied, 0);
+        if (e != hipSuccess) { record_hip(ctx, e); return nullptr; }
+      }
+      b.lru = ++ctx->lru_clock;
+      *which = &b;
+      return b.d;
+    }
+  }
+  Blob* victim = nullptr;
+  if (ctx->blobs.size() < kMaxBlobs) {
+    ctx->blobs.emplace_back();
+    victim = &ctx->blobs.back();
+  } else {
+    victim = &ctx->blobs[0];
+    for (auto& b : ctx->blobs)
+      if (b.lru < victim->lru) victim = &b;
+  }
+  hipError_t e = blob_wait_idle(*victim);
+  if (e != hipSuccess) { record_hip(ctx, e); return nullptr; }
+  victim->valid = false;
+  if (victim->cap_words < count) {
+    if (victim->d) hipFree(victim->d);
+    if (victim->h_pinned) hipHostFree(victim->h_pinned);
+    victim->d = nullptr;
+    victim->h_pinned = nullptr;
+    size_t cap = std::max<size_t>(count, 512);
+    if ((e = hipMalloc(&victim->d, cap * 8)) != hipSuccess) { record_hip(ctx, e); victim->d = nullptr; return nullptr; }
+    if ((e = hipHostMalloc((void**)&victim->h_pinned, cap * 8, hipHostMallocDefault)) != hipSuccess) {
+      record_hip(ctx, e);
+      victim->h_pinned = nullptr;
+      return nullptr;
+    }
+    victim->cap_words = cap;
+  }
+  if (!victim->copied) {
+    if ((e = hipEventCreateWithFlags(&victim->copied, hipEventDisableTiming)) != hipSuccess) {
+      record_hip(ctx, e);
+      return nullptr;
+    }
+  }
+  memcpy(victim->h_pinned, words, count * 8);
+  if ((e = hipMemcpyAsync(victim->d, victim->h_pinned, count * 8, hipMemcpyHostToDevice, stream)) !=
+      hipSuccess) {
+    record_hip(ctx, e);
+    return nullptr;
+  }
+  if ((e = hipEventRecord(victim->copied, stream)) != hipSuccess) { record_hip(ctx, e); return nullptr; }
+  victim->copy_stream = stream;
+  victim->content.assign(words, words + count);
+  victim->hash = h;
+  victim->lru = ++ctx->lru_clock;
+  victim->valid = true;
+  *which = victim;
+  return victim->d;
+}
+
+void blob_used(tq_ctx* ctx, Blob* b, hipStream_t stream) {
+  for (auto& u : b->uses) {
+    if (u.first == stream) {
+      record_hip(ctx, hipEventRecord(u.second, stream));
+      return;
+    }
+  }
+  hipEvent_t ev = nullptr;
+  if (record_hip(ctx, hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != TQ_OK) return;
+  record_hip(ctx, hipEventRecord(ev, stream));
+  b->uses.emplace_back(stream, ev);
+}
+
+// --------------------------------------------------------------- planning
+static SymPlan constant_plan(bool one) {
+  SymPlan p{};
+  p.constant = true;
+  p.const_word = one ? ~(uint64_t)0 : 0;
+  return p;
+}
+
+SymPlan plan_threshold(uint32_t n, uint32_t theta) {
+  if (theta == 0) return constant_plan(true);
+  if (theta > n) return constant_plan(false);
+  SymPlan p{};
+  p.constant = false;
+  p.epi.kind = EPI_THRESH;
+  p.epi.theta = theta;
+  return p;
+}
+
+// Runs of ones of f over [0, n] as half-open [lo, hi1).
+static std::vector<std::pair<uint32_t, uint32_t>> runs_of(const std::vector<uint8_t>& f, uint8_t v) {
+  std::vector<std::pair<uint32_t, uint32_t>> r;
+  const uint32_t m = (uint32_t)f.size();
+  for (uint32_t c = 0; c < m;) {
+    if (f[c] != v) { ++c; continue; }
+    uint32_t d = c;
+    while (d < m && f[d] == v) ++d;
+    r.emplace_back(c, d);
+    c = d;
+  }
+  return r;
+}
+
+SymPlan plan_symmetric(uint32_t n, const uint64_t* truth) {
+  std::vector<uint8_t> f(n + 1);
+  for (uint32_t c = 0; c <= n; ++c) f[c] = (truth[c / 64] >> (c % 64)) & 1;
+  auto ones = runs_of(f, 1);
+  if (ones.empty()) return constant_plan(false);
+  if (ones.size() == 1 && ones[0].first == 0 && ones[0].second == n + 1) return constant_plan(true);
+  SymPlan p{};
+  p.constant = false;
+  // a single run reaching n is a threshold; a single run starting at 0 is its complement
+  if (ones.size() == 1 && ones[0].second == n + 1) {
+    p.epi.kind = EPI_THRESH;
+    p.epi.theta = ones[0].first;
+    return p;
+  }
+  if (ones.size() == 1 && ones[0].first == 0) {
+    p.epi.kind = EPI_THRESH;
+    p.epi.theta = ones[0].second;
+    p.epi.invert = 1;
+    return p;
+  }
+  bool parity = true, nparity = true;
+  for (uint32_t c = 0; c <= n; ++c) {
+    parity &= f[c] == (c & 1);
+    nparity &= f[c] != (c & 1);
+  }
+  if (parity || nparity) {
+    p.epi.kind = EPI_PARITY;
+    p.epi.invert = nparity ? 1 : 0;
+    return p;
+  }
+  auto zeros = runs_of(f, 0);
+  const bool use_zeros = zeros.size() < ones.size();
+  const auto& iv = use_zeros ? zeros : ones;
+  if ((int)iv.size() <= kMaxIntervals) {
+    p.epi.kind = EPI_INTERVALS;
+    p.epi.invert = use_zeros ? 1 : 0;
+    p.epi.nint = (int32_t)iv.size();
+    for (size_t t = 0; t < iv.size(); ++t) {
+      p.epi.lo[t] = iv[t].first;
+      p.epi.hi1[t] = iv[t].second;  // == n + 1 means no upper bound
+    }
+    return p;
+  }
+  p.epi.kind = EPI_TABLE;
+  // table sized for the counter's full range so any count indexes it
+  const uint32_t entries = 1u << dense_planes_for(n);
+  p.table.assign((entries + 31) / 32, 0);
+  for (uint32_t c = 0; c <= n; ++c)
+    if (f[c]) p.table[c / 32] |= 1u << (c % 32);
+  p.epi.table_words = (uint32_t)p.table.size();
+  return p;
+}
+
+}  // namespace tq
+
+using namespace tq;
+
+// ----------------------------------------------------------------- ABI
+extern "C" {
+
+const char* tq_status_string(int s) {
+  switch (s) {
+    case TQ_OK: return "TQ_OK";
+    case TQ_EINVAL: return "TQ_EINVAL: invalid argument";
+    case TQ_ENOMEM: return "TQ_ENOMEM: out of memory";
+    case TQ_EFORMAT: return "TQ_EFORMAT: malformed run-length stream";
+    case TQ_ECAPACITY: return "TQ_ECAPACITY: output capacity too small";
+    case TQ_EDEVICE: return "TQ_EDEVICE: HIP runtime error";
+    case TQ_EBUSY: return "TQ_EBUSY: admission refused, retry";
+    case TQ_ENOTSUP: return "TQ_ENOTSUP: not supported";
+  }
+  return "unknown tq status";
+}
+
+tq_status tq_create(tq_ctx** out, int device) {
+  if (!out) return TQ_EINVAL;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return TQ_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) return TQ_EDEVICE;
+  tq_ctx* c = new (std::nothrow) tq_ctx();
+  if (!c) return TQ_ENOMEM;
+  c->device = device;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+    c->num_cus = prop.multiProcessorCount;
+  if (hipMalloc((void**)&c->d_status, 256) != hipSuccess) {
+    delete c;
+    return TQ_ENOMEM;
+  }
+  if (hipMemset(c->d_status, 0, 256) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+    hipFree(c->d_status);
+    delete c;
+    return TQ_EDEVICE;
+  }
+  c->blobs.reserve(64);
+  *out = c;
+  return TQ_OK;
+}
+
+tq_status tq_destroy(tq_ctx* ctx) {
+  if (!ctx) return TQ_OK;
+  hipSetDevice(ctx->device);
+  for (auto& b : ctx->blobs) blob_release(b);
+  if (ctx->d_status) hipFree(ctx->d_status);
+  delete ctx;
+  return TQ_OK;
+}
+
+tq_status tq_ctx_check(tq_ctx* ctx, hipStream_t stream) {
+  if (!ctx) return TQ_EINVAL;
+  hipError_t e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return record_hip(ctx, e);
+  if (ctx->sticky_host_error) {
+    ctx->sticky_host_error = 0;
+    return TQ_EDEVICE;
+  }
+  int st = 0;
+  if ((e = hipMemcpy(&st, ctx->d_status, sizeof(int), hipMemcpyDeviceToHost)) != hipSuccess)
+    return record_hip(ctx, e);
+  if (st != 0) {
+    int zero = 0;
+    if ((e = hipMemcpy(ctx->d_status, &zero, sizeof(int), hipMemcpyHostToDevice)) != hipSuccess)
+      return record_hip(ctx, e);
+    return (tq_status)st;
+  }
+  return TQ_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Validate the pointer array and the output; returns whether every buffer is 16-byte aligned.
+tq_status check_dense_args(const uint64_t* const* ptrs, uint32_t n, uint64_t r_bits, const uint64_t* d_out,
+                           bool* aligned16) {
+  if (!ptrs || n == 0 || n > TQ_MAX_INPUTS) return TQ_EINVAL;
+  const uint64_t nw = words_for_bits(r_bits);
+  if (r_bits > 0 && !d_out) return TQ_EINVAL;
+  uintptr_t any = (uintptr_t)d_out;
+  const uintptr_t o0 = (uintptr_t)d_out, o1 = o0 + nw * 8;
+  for (uint32_t j = 0; j < n; ++j) {
+    const uintptr_t p = (uintptr_t)ptrs[j];
+    if (!p || (p & 7)) return TQ_EINVAL;
+    any |= p;
+    if (r_bits > 0 && p < o1 && o0 < p + nw * 8) return TQ_EINVAL;  // output overlaps an input
+  }
+  if ((uintptr_t)d_out & 7) return TQ_EINVAL;
+  *aligned16 = (any & 15) == 0;
+  return TQ_OK;
+}
+
+tq_status run_dense(tq_ctx* ctx, const uint64_t* const* ptrs, uint32_t n, uint64_t r_bits,
+                    const SymPlan& plan, uint64_t* d_out, hipStream_t stream, bool aligned16) {
+  const uint64_t nw = words_for_bits(r_bits);
+  const uint64_t tmask = tail_mask_for(r_bits);
+  if (nw == 0) return TQ_OK;
+  if (plan.constant) return record_hip(ctx, launch_fill(d_out, nw, plan.const_word, tmask, stream));
+  Blob* pb = nullptr;
+  const void* d_ptrs = blob_get(ctx, reinterpret_cast<const uint64_t*>(ptrs), n, stream, &pb);
+  if (!d_ptrs) return TQ_EDEVICE;
+  EpiParams epi = plan.epi;
+  Blob* tb = nullptr;
+  if (epi.kind == EPI_TABLE) {
+    std::vector<uint64_t> t64((plan.table.size() + 1) / 2, 0);
+    memcpy(t64.data(), plan.table.data(), plan.table.size() * 4);
+    const void* d_t = blob_get(ctx, t64.data(), t64.size(), stream, &tb);
+    if (!d_t) return TQ_EDEVICE;
+    epi.table = reinterpret_cast<const uint32_t*>(d_t);
+  }
+  const DenseConfig cfg = choose_dense_config(n, nw, aligned16, ctx->num_cus);
+  tq_status st = record_hip(ctx, launch_dense(cfg, reinterpret_cast<const uint64_t* const*>(d_ptrs), n, nw,
+                                              tmask, d_out, epi, stream));
+  blob_used(ctx, pb, stream);
+  if (tb) blob_used(ctx, tb, stream);
+  return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+tq_status tq_threshold(tq_ctx* ctx, const uint64_t* const* ptrs, uint32_t n, uint64_t r_bits,
+                       uint32_t theta, uint64_t* d_out, hipStream_t stream) {
+  if (!ctx) return TQ_EINVAL;
+  bool a16 = false;
+  tq_status st = check_dense_args(ptrs, n, r_bits, d_out, &a16);
+  if (st != TQ_OK) return st;
+  return run_dense(ctx, ptrs, n, r_bits, plan_threshold(n, theta), d_out, stream, a16);
+}
+
+tq_status tq_symmetric(tq_ctx* ctx, const uint64_t* const* ptrs, uint32_t n, uint64_t r_bits,
+                       const uint64_t* h_truth, uint64_t* d_out, hipStream_t stream) {
+  if (!ctx || !h_truth) return TQ_EINVAL;
+  bool a16 = false;
+  tq_status st = check_dense_args(ptrs, n, r_bits, d_out, &a16);
+  if (st != TQ_OK) return st;
+  return run_dense(ctx, ptrs, n, r_bits, plan_symmetric(n, h_truth), d_out, stream, a16);
+}
+
+}  // extern "C"

@@ -1,0 +1,119 @@
+// Internal declarations of libtq (host side).  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/tq.h"
+
+namespace tq {
+
+// ---------------------------------------------------------------- epilogue
+// How the per-position count c is turned into the output bit.  Compiled on
+// the host from the threshold or the truth table, evaluated on the bit
+// planes of the count in the kernel.
+enum EpiKind : int32_t {
+  EPI_THRESH = 0,     // c >= theta (compare against theta - 1)
+  EPI_INTERVALS = 1,  // OR of lo_i <= c <= hi_i
+  EPI_PARITY = 2,     // c odd
+  EPI_TABLE = 3,      // generic: f looked up per bit position from a table
+};
+
+constexpr int kMaxIntervals = 8;
+
+struct EpiParams {
+  int32_t kind;
+  int32_t invert;       // complement the result
+  uint32_t theta;       // EPI_THRESH: theta in [1, n]
+  int32_t nint;         // EPI_INTERVALS
+  uint32_t lo[kMaxIntervals];   // c >= lo   (0 means no lower bound)
+  uint32_t hi1[kMaxIntervals];  // c <  hi1  (> n means no upper bound)
+  const uint32_t* table;        // EPI_TABLE: bit c of the table is f(c)
+  uint32_t table_words;
+  uint32_t pad_;
+};
+
+// Plan of a symmetric function: a constant, or an epilogue.
+struct SymPlan {
+  bool constant;
+  uint64_t const_word;  // all ones or zero when constant
+  EpiParams epi;
+  std::vector<uint32_t> table;  // EPI_TABLE contents
+};
+
+SymPlan plan_threshold(uint32_t n, uint32_t theta);
+SymPlan plan_symmetric(uint32_t n, const uint64_t* truth);
+
+// --------------------------------------------------------- dense launches
+struct DenseConfig {
+  int K;     // bit planes of the counter: the count must fit, count <= n < 2^K
+  int wpl;   // 64-bit words per lane (1 or 2)
+  int split; // waves per workgroup sharing the same columns (inputs split among them)
+};
+
+int dense_planes_for(uint32_t n);
+
+DenseConfig choose_dense_config(uint32_t n, uint64_t nwords, bool aligned16, int num_cus);
+
+hipError_t launch_dense(const DenseConfig& cfg, const uint64_t* const* d_ptrs, uint32_t n,
+                        uint64_t nwords, uint64_t tail_mask, uint64_t* d_out,
+                        const EpiParams& epi, hipStream_t stream);
+
+hipError_t launch_fill(uint64_t* d_out, uint64_t nwords, uint64_t value, uint64_t tail_mask,
+                       hipStream_t stream);
+
+// -------------------------------------------------------------- blob cache
+// Small host arrays that kernels read (pointer arrays, truth tables) are
+// staged through pinned memory into device memory and cached by content, so
+// a repeated query does not copy them again.
+struct Blob {
+  std::vector<uint64_t> content;
+  uint64_t hash = 0;
+  void* d = nullptr;
+  uint64_t* h_pinned = nullptr;
+  size_t cap_words = 0;
+  hipEvent_t copied = nullptr;
+  hipStream_t copy_stream = nullptr;
+  std::vector<std::pair<hipStream_t, hipEvent_t>> uses;
+  uint64_t lru = 0;
+  bool valid = false;
+};
+
+}  // namespace tq
+
+struct tq_ctx {
+  int device = 0;
+  int num_cus = 256;
+  int* d_status = nullptr;     // first device-detected error (0 = none)
+  int sticky_host_error = 0;   // HIP failures seen by the host
+  std::vector<tq::Blob> blobs;
+  uint64_t lru_clock = 0;
+};
+
+namespace tq {
+
+// Returns a device copy of `words` (count words), staged on `stream`.
+// Returns nullptr on failure (ctx->sticky_host_error is set).
+const void* blob_get(tq_ctx* ctx, const uint64_t* words, size_t count, hipStream_t stream,
+                     Blob** which);
+// Records that work using the blob was queued on `stream`.
+void blob_used(tq_ctx* ctx, Blob* b, hipStream_t stream);
+
+inline uint64_t words_for_bits(uint64_t r) { return (r + 63) / 64; }
+inline uint64_t tail_mask_for(uint64_t r) {
+  uint64_t rem = r % 64;
+  return rem ? ((uint64_t)1 << rem) - 1 : ~(uint64_t)0;
+}
+inline int bit_length(uint64_t x) {
+  int k = 0;
+  while (x) { ++k; x >>= 1; }
+  return k;
+}
+
+tq_status record_hip(tq_ctx* ctx, hipError_t e);
+
+}  // namespace tq

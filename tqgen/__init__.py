@@ -387,3 +387,58 @@ def serving_queries(seed: int = 5, count: int | None = None, pool: int | None = 
         t += -math.log(1.0 - unit_double(k, 3)) / rate_qps
         out.append(ServingQuery(tuple(members), theta, t))
     return out
+
+
+# --------------------------------------------------------- device filling
+# The same bit processes as above, generated on the GPU by tqgen/gen.hip.
+_gen_lib = None
+
+
+def _gpu_lib():
+    global _gen_lib
+    if _gen_lib is None:
+        import ctypes
+        import os
+        import torch  # noqa: F401  (binds the library to torch's HIP runtime)
+        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtqgen.so")
+        if not os.path.exists(path):
+            raise RuntimeError("libtqgen.so is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(path)
+        P, U32, U64 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64
+        L.tqgen_bernoulli_pool.argtypes = [P, U64, U64, U32, P, P, P]
+        L.tqgen_markov_pool.argtypes = [P, U64, U64, U32, P, P, P, P, P]
+        L.tqgen_bernoulli_pool.restype = ctypes.c_int
+        L.tqgen_markov_pool.restype = ctypes.c_int
+        _gen_lib = L
+    return _gen_lib
+
+
+def fill_gpu(bset, pool, stride_words: int | None = None, first: int = 0, count: int | None = None):
+    """Generate bitmaps [first, first+count) of a BernoulliSet or MarkovSet
+    into the int64 CUDA tensor `pool` (bitmap first+i at word i*stride)."""
+    import torch
+    count = bset.n - first if count is None else count
+    stride = bset.nwords if stride_words is None else stride_words
+    assert pool.dtype == torch.int64 and pool.is_cuda and pool.is_contiguous()
+    assert pool.numel() >= (count - 1) * stride + bset.nwords if count else True
+    dev = pool.device
+    keys = torch.from_numpy(bset.keys_array()[first:first + count].view(np.int64)).to(dev)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    L = _gpu_lib()
+    if isinstance(bset, BernoulliSet):
+        thr = torch.from_numpy(bset.thr_array()[first:first + count].view(np.int64)).to(dev)
+        rc = L.tqgen_bernoulli_pool(pool.data_ptr(), stride, bset.nwords, count, keys.data_ptr(),
+                                    thr.data_ptr(), stream)
+        keep = (keys, thr)
+    else:
+        A = torch.from_numpy(bset.a_array()[first:first + count].view(np.int64)).to(dev)
+        S = torch.from_numpy(bset.s_array()[first:first + count].view(np.int64)).to(dev)
+        I = torch.from_numpy(bset.init_array()[first:first + count].view(np.int32)).to(dev)
+        rc = L.tqgen_markov_pool(pool.data_ptr(), stride, bset.nwords, count, keys.data_ptr(),
+                                 A.data_ptr(), S.data_ptr(), I.data_ptr(), stream)
+        keep = (keys, A, S, I)
+    if rc != 0:
+        raise RuntimeError("tqgen kernel launch failed: %d" % rc)
+    torch.cuda.current_stream(dev).synchronize()
+    del keep
+    return pool
