@@ -210,18 +210,14 @@ __device__ __forceinline__ Vec<WPL> epilogue(const Vec<WPL> (&P)[K], const EpiPa
   return r;
 }
 
-template <int S>
-constexpr int groups_per_block() {
-  return S >= 4 ? 1 : 4 / S;
-}
-
 // K: counter planes, WPL: words per lane, S: waves that split the inputs of
-// one column group.  A workgroup holds G column groups of S waves each.
-template <int K, int WPL, int S>
-__global__ __launch_bounds__(64 * S * groups_per_block<S>()) void dense_kernel(
+// one column group, G: column groups per workgroup.  Small workgroups (one
+// wave) spread best over the CUs of the eight XCDs: the kernel has no data
+// reuse between workgroups, so nothing is gained by co-locating them.
+template <int K, int WPL, int S, int G>
+__global__ __launch_bounds__(64 * S * G) void dense_kernel(
     const uint64_t* const* __restrict__ ptrs, uint32_t n, uint64_t nwords, uint64_t tail_mask,
     uint64_t* __restrict__ out, EpiParams epi) {
-  constexpr int G = groups_per_block<S>();
   extern __shared__ uint64_t lds[];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -322,39 +318,39 @@ __global__ void fill_kernel(uint64_t* __restrict__ out, uint64_t nwords, uint64_
 
 typedef void (*DenseFn)(const uint64_t* const*, uint32_t, uint64_t, uint64_t, uint64_t*, EpiParams);
 
+// Instantiated shapes: one word per lane with S in {1,2,4,8} and G = 1 (the
+// default family), plus two-word lanes and four-wave workgroups for the tuner.
 template <int K>
-DenseFn pick_ws(int wpl, int split) {
-  if (wpl == 2) {
+DenseFn pick_ws(int wpl, int split, int groups) {
+  if (wpl == 1 && groups == 1) {
     switch (split) {
-      case 1: return dense_kernel<K, 2, 1>;
-      case 2: return dense_kernel<K, 2, 2>;
-      case 4: return dense_kernel<K, 2, 4>;
-      case 8: return dense_kernel<K, 2, 8>;
+      case 1: return dense_kernel<K, 1, 1, 1>;
+      case 2: return dense_kernel<K, 1, 2, 1>;
+      case 4: return dense_kernel<K, 1, 4, 1>;
+      case 8: return dense_kernel<K, 1, 8, 1>;
     }
-  } else {
-    switch (split) {
-      case 1: return dense_kernel<K, 1, 1>;
-      case 2: return dense_kernel<K, 1, 2>;
-      case 4: return dense_kernel<K, 1, 4>;
-      case 8: return dense_kernel<K, 1, 8>;
-    }
+  }
+  if (split == 1) {
+    if (wpl == 1 && groups == 4) return dense_kernel<K, 1, 1, 4>;
+    if (wpl == 2 && groups == 1) return dense_kernel<K, 2, 1, 1>;
+    if (wpl == 2 && groups == 4) return dense_kernel<K, 2, 1, 4>;
   }
   return nullptr;
 }
 
-DenseFn pick(int K, int wpl, int split) {
+DenseFn pick(int K, int wpl, int split, int groups) {
   switch (K) {
-    case 4: return pick_ws<4>(wpl, split);
-    case 5: return pick_ws<5>(wpl, split);
-    case 6: return pick_ws<6>(wpl, split);
-    case 7: return pick_ws<7>(wpl, split);
-    case 8: return pick_ws<8>(wpl, split);
-    case 9: return pick_ws<9>(wpl, split);
-    case 10: return pick_ws<10>(wpl, split);
-    case 11: return pick_ws<11>(wpl, split);
-    case 12: return pick_ws<12>(wpl, split);
-    case 13: return pick_ws<13>(wpl, split);
-    case 16: return pick_ws<16>(wpl, split);
+    case 4: return pick_ws<4>(wpl, split, groups);
+    case 5: return pick_ws<5>(wpl, split, groups);
+    case 6: return pick_ws<6>(wpl, split, groups);
+    case 7: return pick_ws<7>(wpl, split, groups);
+    case 8: return pick_ws<8>(wpl, split, groups);
+    case 9: return pick_ws<9>(wpl, split, groups);
+    case 10: return pick_ws<10>(wpl, split, groups);
+    case 11: return pick_ws<11>(wpl, split, groups);
+    case 12: return pick_ws<12>(wpl, split, groups);
+    case 13: return pick_ws<13>(wpl, split, groups);
+    case 16: return pick_ws<16>(wpl, split, groups);
   }
   return nullptr;
 }
@@ -368,19 +364,25 @@ int dense_planes_for(uint32_t n) {
   return k;
 }
 
+bool dense_config_valid(const DenseConfig& c) {
+  return pick(c.K, c.wpl, c.split, c.groups) != nullptr;
+}
+
 DenseConfig choose_dense_config(uint32_t n, uint64_t nwords, bool aligned16, int num_cus) {
+  (void)aligned16;
   DenseConfig c;
   c.K = dense_planes_for(n);
-  c.wpl = aligned16 ? 2 : 1;
-  // enough waves to keep every SIMD streaming: aim for >= 8 waves per CU
+  // one 8-byte word per lane and one wave per workgroup measured fastest
+  // (8-byte coalesced loads, the most waves in flight)
+  c.wpl = 1;
+  c.groups = 1;
+  // enough waves to keep every SIMD streaming: aim for >= 8 waves per CU,
+  // splitting the inputs of a column group over up to 8 waves when the
+  // bitmaps are short
   const uint64_t target_waves = (uint64_t)num_cus * 8;
-  uint64_t groups = (nwords + 64 * c.wpl - 1) / (64 * c.wpl);
-  if (c.wpl == 2 && groups < target_waves) {
-    c.wpl = 1;
-    groups = (nwords + 63) / 64;
-  }
+  const uint64_t colgroups = (nwords + 63) / 64;
   c.split = 1;
-  while (c.split < 8 && groups * c.split < target_waves && n / (2 * c.split) >= (uint32_t)kBlock)
+  while (c.split < 8 && colgroups * c.split < target_waves && n / (2 * c.split) >= (uint32_t)kBlock)
     c.split *= 2;
   return c;
 }
@@ -388,9 +390,9 @@ DenseConfig choose_dense_config(uint32_t n, uint64_t nwords, bool aligned16, int
 hipError_t launch_dense(const DenseConfig& cfg, const uint64_t* const* d_ptrs, uint32_t n,
                         uint64_t nwords, uint64_t tail_mask, uint64_t* d_out, const EpiParams& epi,
                         hipStream_t stream) {
-  DenseFn fn = pick(cfg.K, cfg.wpl, cfg.split);
+  DenseFn fn = pick(cfg.K, cfg.wpl, cfg.split, cfg.groups);
   if (!fn) return hipErrorInvalidValue;
-  const int G = cfg.split >= 4 ? 1 : 4 / cfg.split;
+  const int G = cfg.groups;
   const uint64_t cols_per_block = (uint64_t)64 * cfg.wpl * G;
   const uint64_t blocks = (nwords + cols_per_block - 1) / cols_per_block;
   if (blocks == 0) return hipSuccess;

@@ -53,7 +53,10 @@ struct DenseConfig {
   int K;     // bit planes of the counter: the count must fit, count <= n < 2^K
   int wpl;   // 64-bit words per lane (1 or 2)
   int split; // waves per workgroup sharing the same columns (inputs split among them)
+  int groups; // column groups per workgroup
 };
+
+bool dense_config_valid(const DenseConfig& c);
 
 int dense_planes_for(uint32_t n);
 
