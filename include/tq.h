@@ -110,6 +110,93 @@ tq_status tq_threshold(tq_ctx* ctx, const uint64_t* const* ptrs, uint32_t n, uin
 tq_status tq_symmetric(tq_ctx* ctx, const uint64_t* const* ptrs, uint32_t n, uint64_t r_bits,
                        const uint64_t* h_truth, uint64_t* d_out, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Run-length-encoded bitmaps (section 2.1, word-aligned RLE with markers that
+ * carry both a fill-run length and a dirty-word count, as in EWAH).
+ *
+ * Stream layout: a sequence of 64-bit marker words, each followed by its
+ * literal words.  Marker bit 0 = fill value, bits 1..32 = number of fill
+ * words, bits 33..63 = number of literal words that follow.  The fill and
+ * literal counts of all markers add up to exactly ceil(r/64) words.  Any
+ * such stream is accepted as input; outputs are canonical: a marker starts at
+ * word 0 and at every clean word (all zeros or all ones) whose predecessor is
+ * dirty or the other fill, covers the maximal run of equal clean words there
+ * and then the maximal run of dirty words; clean words are never literals.
+ * The tail word is encoded with its bits >= r cleared.
+ *
+ * Checkpoint index: for every TQ_RLE_INDEX_STRIDE uncompressed words, two
+ * uint64: the stream offset of the marker whose run covers word
+ * c * TQ_RLE_INDEX_STRIDE, and the uncompressed word at which that marker's
+ * run starts.  tq_rle_index_words(r) words in device memory.  It makes tiles
+ * of the bitmap directly addressable (the paper notes RLE offers no random
+ * access, section 1 "Lower Bound"; auxiliary skip structures, section 4.3).
+ * ---------------------------------------------------------------------- */
+#define TQ_RLE_INDEX_STRIDE 512
+/* Largest N accepted by the compressed-input calls. */
+#define TQ_RLE_MAX_INPUTS 8192u
+
+typedef struct tq_rle {
+  const uint64_t* words; /* device stream */
+  uint64_t n_words;      /* stream length in words */
+  const uint64_t* index; /* device checkpoint index, or NULL (then built into the context's workspace) */
+} tq_rle;
+
+/* Largest canonical encoding of an r-bit bitmap: ceil(r/64) + 1 words. */
+uint64_t tq_rle_max_words(uint64_t r_bits);
+
+/* Words of a checkpoint index: 2 * ceil(ceil(r/64) / TQ_RLE_INDEX_STRIDE). */
+uint64_t tq_rle_index_words(uint64_t r_bits);
+
+/*
+ * Canonical encoding of the dense bitmap d_dense (ceil(r/64) words; bits
+ * >= r ignored) into d_out (capacity out_cap words).  The encoded length is
+ * written to *d_out_len (a device uint64).  If it exceeds out_cap, nothing
+ * beyond out_cap is written and TQ_ECAPACITY is recorded for tq_ctx_check
+ * (the required length is still in *d_out_len).  d_index (nullable) receives
+ * the checkpoint index of the encoded stream.  Uses the context's workspace:
+ * calls on one context that use workspace must be ordered (one stream, or
+ * synchronised by the caller).
+ */
+tq_status tq_rle_encode(tq_ctx* ctx, const uint64_t* d_dense, uint64_t r_bits, uint64_t* d_out,
+                        uint64_t out_cap, uint64_t* d_out_len, uint64_t* d_index, hipStream_t stream);
+
+/* Build the checkpoint index of a stream (validating it: TQ_EFORMAT is
+ * recorded if the stream does not cover exactly ceil(r/64) words). */
+tq_status tq_rle_build_index(tq_ctx* ctx, const uint64_t* d_words, uint64_t n_words, uint64_t r_bits,
+                             uint64_t* d_index, hipStream_t stream);
+
+/* Decode one stream into ceil(r/64) dense words (bits >= r zero). */
+tq_status tq_rle_decode(tq_ctx* ctx, const tq_rle* input, uint64_t r_bits, uint64_t* d_dense,
+                        hipStream_t stream);
+
+/*
+ * Threshold over compressed inputs (section 2.3 for the function; section
+ * 4.1, RBMrg, for the run cases: where k inputs are 1-fills, theta - k <= 0
+ * gives ones, theta - k greater than the number of dirty inputs gives zeros,
+ * and otherwise a (theta - k)-threshold over the dirty words decides).
+ * inputs: HOST array of n tq_rle descriptors (device streams).  The result is
+ * written as a canonical stream into d_out (capacity out_cap_words), its
+ * length into *d_out_len (device).  TQ_ECAPACITY as for tq_rle_encode;
+ * TQ_EFORMAT is recorded if an input is malformed.  n in [1,
+ * TQ_RLE_MAX_INPUTS].  Uses the context's workspace (see tq_rle_encode).
+ */
+tq_status tq_threshold_rle(tq_ctx* ctx, const tq_rle* inputs, uint32_t n, uint64_t r_bits, uint32_t theta,
+                           uint64_t* d_out, uint64_t out_cap_words, uint64_t* d_out_len, hipStream_t stream);
+
+/* Same query with the result written as a dense bitmap (ceil(r/64) words). */
+tq_status tq_threshold_rle_dense(tq_ctx* ctx, const tq_rle* inputs, uint32_t n, uint64_t r_bits,
+                                 uint32_t theta, uint64_t* d_out, hipStream_t stream);
+
+/*
+ * Hybrid query: n_rle compressed inputs plus n_dense uncompressed inputs
+ * (host array of device pointers), each input stored in whichever form is
+ * smaller; the threshold counts all n_rle + n_dense of them.  Dense output.
+ * n_rle + n_dense in [1, TQ_RLE_MAX_INPUTS].
+ */
+tq_status tq_threshold_hybrid(tq_ctx* ctx, const tq_rle* rle_inputs, uint32_t n_rle,
+                              const uint64_t* const* dense_ptrs, uint32_t n_dense, uint64_t r_bits,
+                              uint32_t theta, uint64_t* d_out, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

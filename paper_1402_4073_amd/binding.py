@@ -55,6 +55,14 @@ def _load():
         "tq_ctx_check": (_INT, [_P, _P]),
         "tq_threshold": (_INT, [_P, _P, _U32, _U64, _U32, _P, _P]),
         "tq_symmetric": (_INT, [_P, _P, _U32, _U64, _P, _P, _P]),
+        "tq_rle_max_words": (_U64, [_U64]),
+        "tq_rle_index_words": (_U64, [_U64]),
+        "tq_rle_encode": (_INT, [_P, _P, _U64, _P, _U64, _P, _P, _P]),
+        "tq_rle_build_index": (_INT, [_P, _P, _U64, _U64, _P, _P]),
+        "tq_rle_decode": (_INT, [_P, _P, _U64, _P, _P]),
+        "tq_threshold_rle": (_INT, [_P, _P, _U32, _U64, _U32, _P, _U64, _P, _P]),
+        "tq_threshold_rle_dense": (_INT, [_P, _P, _U32, _U64, _U32, _P, _P]),
+        "tq_threshold_hybrid": (_INT, [_P, _P, _U32, _P, _U32, _U64, _U32, _P, _P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -162,6 +170,103 @@ def tq_symmetric(ctx: int, inputs, r_bits: int, truth, out, stream=None) -> None
 def raw_threshold(ctx: int, ptrs, n: int, r_bits: int, theta: int, out_ptr: int, stream=None) -> int:
     """Unchecked call returning the status (for error-path tests)."""
     return _lib.tq_threshold(ctx, ptrs, n, r_bits, theta, out_ptr, _stream(stream))
+
+
+# ------------------------------------------------------------------- RLE
+TQ_RLE_INDEX_STRIDE = 512
+TQ_RLE_MAX_INPUTS = 8192
+
+
+class TqRle(ctypes.Structure):
+    _fields_ = [("words", _U64), ("n_words", _U64), ("index", _U64)]
+
+
+def rle_array(inputs):
+    """Host array of tq_rle from (words, n_words, index) triples; index may be None."""
+    arr = (TqRle * max(1, len(inputs)))()
+    for i, (w, nw, idx) in enumerate(inputs):
+        arr[i].words = _ptr(w)
+        arr[i].n_words = int(nw)
+        arr[i].index = 0 if idx is None else _ptr(idx)
+    return arr
+
+
+def tq_rle_max_words(r_bits: int) -> int:
+    return int(_lib.tq_rle_max_words(r_bits))
+
+
+def tq_rle_index_words(r_bits: int) -> int:
+    return int(_lib.tq_rle_index_words(r_bits))
+
+
+def tq_rle_encode(ctx: int, dense, r_bits: int, out, out_cap: int, out_len, index=None, stream=None) -> None:
+    _check(_lib.tq_rle_encode(ctx, _ptr(dense), r_bits, _ptr(out) if out is not None else 0, out_cap,
+                              _ptr(out_len), 0 if index is None else _ptr(index), _stream(stream)),
+           "tq_rle_encode")
+
+
+def tq_rle_build_index(ctx: int, words, n_words: int, r_bits: int, index, stream=None) -> None:
+    _check(_lib.tq_rle_build_index(ctx, _ptr(words), n_words, r_bits, _ptr(index), _stream(stream)),
+           "tq_rle_build_index")
+
+
+def tq_rle_decode(ctx: int, rle, r_bits: int, dense, stream=None) -> None:
+    """rle: (words, n_words, index-or-None)."""
+    arr = rle_array([rle])
+    _check(_lib.tq_rle_decode(ctx, arr, r_bits, _ptr(dense), _stream(stream)), "tq_rle_decode")
+
+
+def tq_threshold_rle(ctx: int, inputs, r_bits: int, theta: int, out, out_cap: int, out_len, stream=None) -> None:
+    arr = rle_array(inputs)
+    _check(_lib.tq_threshold_rle(ctx, arr, len(inputs), r_bits, theta, _ptr(out) if out is not None else 0,
+                                 out_cap, _ptr(out_len), _stream(stream)), "tq_threshold_rle")
+
+
+def tq_threshold_rle_dense(ctx: int, inputs, r_bits: int, theta: int, out, stream=None) -> None:
+    arr = rle_array(inputs)
+    _check(_lib.tq_threshold_rle_dense(ctx, arr, len(inputs), r_bits, theta, _ptr(out), _stream(stream)),
+           "tq_threshold_rle_dense")
+
+
+def tq_threshold_hybrid(ctx: int, rle_inputs, dense_inputs, r_bits: int, theta: int, out, stream=None) -> None:
+    arr = rle_array(rle_inputs)
+    ptrs = ptr_array(dense_inputs)
+    _check(_lib.tq_threshold_hybrid(ctx, arr, len(rle_inputs), ptrs, len(dense_inputs), r_bits, theta, _ptr(out),
+                                    _stream(stream)), "tq_threshold_hybrid")
+
+
+def raw_threshold_rle(ctx: int, inputs, r_bits: int, theta: int, out_ptr: int, out_cap: int, out_len_ptr: int,
+                      stream=None) -> int:
+    arr = rle_array(inputs)
+    return _lib.tq_threshold_rle(ctx, arr, len(inputs), r_bits, theta, out_ptr, out_cap, out_len_ptr,
+                                 _stream(stream))
+
+
+def encode_pool(ctx: int, dense_rows, r_bits: int, stream=None):
+    """Encode dense device bitmaps into one compact device pool of canonical
+    streams with their checkpoint indexes (two passes: lengths, then data).
+    Returns (pool, offsets, lengths, index_pool)."""
+    n = len(dense_rows)
+    dev = dense_rows[0].device
+    lens = torch.zeros(n, dtype=torch.int64, device=dev)
+    for j, row in enumerate(dense_rows):
+        tq_rle_encode(ctx, row, r_bits, None, 0, lens[j:j + 1], None, stream)
+    # the first pass records "capacity too small" on purpose: clear it
+    tq_ctx_check(ctx, stream)
+    hl = lens.cpu().tolist()
+    offs = [0]
+    for L in hl:
+        offs.append(offs[-1] + ((L + 1) & ~1))   # keep every stream 16-byte aligned
+    pool = torch.zeros(max(offs[-1], 1), dtype=torch.int64, device=dev)
+    iw = tq_rle_index_words(r_bits)
+    index_pool = torch.zeros((n, max(iw, 1)), dtype=torch.int64, device=dev)
+    lens2 = torch.zeros(n, dtype=torch.int64, device=dev)
+    for j, row in enumerate(dense_rows):
+        tq_rle_encode(ctx, row, r_bits, pool[offs[j]:], hl[j], lens2[j:j + 1], index_pool[j], stream)
+    st = tq_ctx_check(ctx, stream)
+    if st != TQ_OK:
+        raise TQError(st, "encode_pool")
+    return pool, offs[:-1], hl, index_pool
 
 
 class Context:

@@ -11,11 +11,11 @@
 // equal-weight bit vectors into the accumulator planes 0..3 and pass one
 // carry of weight 16 upward, which is rippled into planes 4..K-1 with half
 // adders.  This is the sideways-sum arrangement of full adders of section
-// 4.4.4 (about one full adder per input) run as a stream over the inputs,
+// 4.4.3 (about one full adder per input) run as a stream over the inputs,
 // with the live state being the K = O(log N) planes, as in the carry-save
-// vertical counter (CSvCkt) of the same section.
+// vertical counter (CSvCkt) of section 4.5.1.
 //
-// The count is then compared with the query (section 4.4.4, comparison
+// The count is then compared with the query (section 4.4.2, comparison
 // against a constant): count > a is the OR, over the zero bits j of a, of
 // plane j ANDed with every plane above j where a has a one.  The bits of a
 // are the same for the whole grid, so the walk over them compiles to scalar

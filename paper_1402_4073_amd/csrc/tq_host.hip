@@ -264,7 +264,9 @@ tq_status tq_create(tq_ctx** out, int device) {
 tq_status tq_destroy(tq_ctx* ctx) {
   if (!ctx) return TQ_OK;
   hipSetDevice(ctx->device);
+  hipDeviceSynchronize();
   for (auto& b : ctx->blobs) blob_release(b);
+  if (ctx->ws) hipFree(ctx->ws);
   if (ctx->d_status) hipFree(ctx->d_status);
   delete ctx;
   return TQ_OK;

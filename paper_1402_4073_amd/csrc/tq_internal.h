@@ -69,6 +69,26 @@ hipError_t launch_dense(const DenseConfig& cfg, const uint64_t* const* d_ptrs, u
 hipError_t launch_fill(uint64_t* d_out, uint64_t nwords, uint64_t value, uint64_t tail_mask,
                        hipStream_t stream);
 
+// -------------------------------------------------------------------- RLE
+// Device-side description of one compressed input (3 words, staged as a blob).
+struct RleDesc {
+  const uint64_t* words;
+  uint64_t len;
+  const uint64_t* index;
+};
+
+size_t rle_tile_lds_bytes(int K);
+hipError_t launch_rle_tile(const RleDesc* d_descs, uint32_t n_rle, const uint64_t* const* d_dense,
+                           uint32_t n_dense, uint64_t nwords, uint64_t tail_mask, uint32_t theta,
+                           uint64_t* d_out, int* d_status, hipStream_t stream);
+size_t rle_encode_workspace_bytes(uint64_t nwords);
+hipError_t launch_rle_encode(const uint64_t* d_dense, uint64_t nwords, uint64_t tail_mask, uint64_t* d_out,
+                             uint64_t cap, uint64_t* d_out_len, uint64_t* d_index, void* workspace,
+                             int* d_status, hipStream_t stream);
+hipError_t launch_build_index(const uint64_t* d_words, uint64_t len, uint64_t nwords, uint64_t* d_index,
+                              int* d_status, hipStream_t stream);
+hipError_t launch_set_u64(uint64_t* d_dst, uint64_t value, hipStream_t stream);
+
 // -------------------------------------------------------------- blob cache
 // Small host arrays that kernels read (pointer arrays, truth tables) are
 // staged through pinned memory into device memory and cached by content, so
@@ -95,6 +115,8 @@ struct tq_ctx {
   int sticky_host_error = 0;   // HIP failures seen by the host
   std::vector<tq::Blob> blobs;
   uint64_t lru_clock = 0;
+  void* ws = nullptr;          // grow-only device workspace (RLE paths)
+  size_t ws_bytes = 0;
 };
 
 namespace tq {
@@ -118,5 +140,8 @@ inline int bit_length(uint64_t x) {
 }
 
 tq_status record_hip(tq_ctx* ctx, hipError_t e);
+
+// Device workspace of at least `bytes` (grown with a device synchronisation).
+void* workspace(tq_ctx* ctx, size_t bytes);
 
 }  // namespace tq

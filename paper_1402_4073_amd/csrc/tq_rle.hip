@@ -1,0 +1,518 @@
+// Run-length-encoded inputs and outputs (word-aligned RLE, section 2.1).
+//
+// Stream format: a sequence of marker words, each followed by its literal
+// words.  Marker: bit 0 = fill value, bits 1..32 = number of fill words,
+// bits 33..63 = number of literal (dirty) words that follow.
+//
+// Threshold over RLE inputs, one workgroup per tile of kTile words:
+//
+//  1. Every input is entered at the tile through its checkpoint index (one
+//     entry per kTile uncompressed words: stream offset and start word of the
+//     marker covering the checkpoint) and its markers are walked, one lane per
+//     input.  Fill runs of ones add 1 to k (per column) and literal runs add 1
+//     to d, both through a difference array in LDS; no literal word is read.
+//  2. After a prefix sum, every column knows k (inputs that are a 1-fill there)
+//     and d (inputs that are dirty there).  These are the cases of RBMrg
+//     (section 4.1): theta - k <= 0 means the column is all ones, theta - k > d
+//     means all zeros, and only in between do the dirty words matter, as a
+//     (theta - k)-threshold over them.
+//  3. The markers are walked again and only the literal words of undecided
+//     columns are read and added into a bit-sliced counter per column kept in
+//     LDS.  Lanes of different inputs may hit the same column, so the addition
+//     ripples with atomic XOR: the old value that atomicXor returns gives the
+//     exact carry of that addition whatever the interleaving.
+//  4. One thread per column compares its counter with its own theta - k
+//     (subtract-and-sign style, bit by bit with a per-lane mask), adds any
+//     uncompressed inputs first (hybrid queries), and writes the dense word.
+//
+// The dense result is then encoded canonically: each word is classified
+// (zero fill, ones fill, dirty), a marker starts at word 0 and at each clean
+// word after a dirty word or a different fill, and one scan of the packed pair
+// (markers, dirty words) before each word gives every output position.
+#include "tq_internal.h"
+
+namespace tq {
+namespace {
+
+constexpr int kTile = TQ_RLE_INDEX_STRIDE;  // words per tile == checkpoint stride
+constexpr int kTileThreads = 512;
+constexpr int kEncBlock = 256;
+constexpr int kEncPerThread = 4;
+constexpr int kEncWords = kEncBlock * kEncPerThread;
+
+__device__ __forceinline__ void set_status(int* status, int code) { atomicCAS(status, 0, code); }
+
+__device__ __forceinline__ uint64_t valid_mask_dev(uint64_t w, uint64_t nwords, uint64_t tail_mask) {
+  return w == nwords - 1 ? tail_mask : ~(uint64_t)0;
+}
+
+// --------------------------------------------------------- block scans
+// inclusive scan of one value per thread over a 512-thread block (8 waves)
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_scan(T v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    T o = __shfl_up(v, off, 64);
+    if (lane >= off) v += o;
+  }
+  return v;
+}
+
+template <typename T, int WAVES>
+__device__ __forceinline__ T block_exclusive_scan(T v, T* wave_tot, T* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  T inc = wave_inclusive_scan(v);
+  if (lane == 63) wave_tot[wave] = inc;
+  __syncthreads();
+  if (wave == 0) {
+    T t = lane < WAVES ? wave_tot[lane] : (T)0;
+    T ti = wave_inclusive_scan(t);
+    if (lane < WAVES) wave_tot[lane] = ti - t;
+    if (lane == WAVES - 1) *total = ti;
+  }
+  __syncthreads();
+  T r = inc - v + wave_tot[wave];
+  __syncthreads();
+  return r;
+}
+
+// ------------------------------------------------------------ tile kernel
+struct Walk {
+  uint64_t pos, w;
+};
+
+// Enter stream j at the checkpoint of tile `tile`; returns false on a bad entry.
+__device__ __forceinline__ bool seek(const RleDesc& d, uint64_t tile, uint64_t t0, Walk& wk) {
+  wk.pos = d.index[2 * tile];
+  wk.w = d.index[2 * tile + 1];
+  return wk.pos < d.len && wk.w <= t0;
+}
+
+template <int K>
+__device__ __forceinline__ void ripple_lds(uint64_t* planes, int col, uint64_t x) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const uint64_t old = atomicXor((unsigned long long*)&planes[k * kTile + col], (unsigned long long)x);
+    x &= old;
+    if (!x) break;
+  }
+}
+
+__device__ __forceinline__ void unpack_kd(int32_t v, int& k, int& d) {
+  k = v & 0xFFFF;
+  d = (v >> 16) & 0xFFFF;
+}
+
+// count > a per lane (a differs between lanes)
+template <int K>
+__device__ __forceinline__ uint64_t greater_than_lane(const uint64_t (&P)[K], uint32_t a) {
+  uint64_t pm = ~(uint64_t)0, r = 0;
+#pragma unroll
+  for (int j = K - 1; j >= 0; --j) {
+    const uint64_t m = 0 - (uint64_t)((a >> j) & 1u);  // all ones where a has a one
+    r |= pm & P[j] & ~m;
+    pm &= P[j] | ~m;
+  }
+  return r;
+}
+
+template <int K>
+__global__ __launch_bounds__(kTileThreads) void rle_tile_kernel(
+    const RleDesc* __restrict__ descs, uint32_t n_rle, const uint64_t* const* __restrict__ dense,
+    uint32_t n_dense, uint64_t nwords, uint64_t tail_mask, uint32_t theta, uint64_t* __restrict__ out,
+    int* __restrict__ status) {
+  extern __shared__ uint64_t lds[];
+  uint64_t* planes = lds;                                         // K x kTile
+  int32_t* kd = reinterpret_cast<int32_t*>(lds + K * kTile);      // kTile + 1 packed (k | d << 16)
+  __shared__ int32_t wave_tot[kTileThreads / 64];
+  __shared__ int32_t total;
+
+  const uint64_t tile = blockIdx.x;
+  const uint64_t t0 = tile * kTile;
+  const uint64_t t1 = t0 + kTile < nwords ? t0 + kTile : nwords;
+  const int tid = threadIdx.x;
+
+  for (int i = tid; i < K * kTile; i += kTileThreads) planes[i] = 0;
+  for (int i = tid; i <= kTile; i += kTileThreads) kd[i] = 0;
+  __syncthreads();
+
+  // 1. markers only: difference array of (ones fills) + 65536 * (dirty)
+  for (uint32_t j = tid; j < n_rle; j += kTileThreads) {
+    const RleDesc dsc = descs[j];
+    Walk wk;
+    if (!seek(dsc, tile, t0, wk)) { set_status(status, TQ_EFORMAT); continue; }
+    while (wk.w < t1) {
+      if (wk.pos >= dsc.len) { set_status(status, TQ_EFORMAT); break; }
+      const uint64_t m = dsc.words[wk.pos];
+      const uint64_t run = (m >> 1) & 0xFFFFFFFFull, lits = m >> 33;
+      const uint64_t w1 = wk.w + run, w2 = w1 + lits;
+      if (w2 > nwords || lits > dsc.len - wk.pos - 1) { set_status(status, TQ_EFORMAT); break; }
+      if ((m & 1) && run) {
+        const uint64_t a = wk.w > t0 ? wk.w : t0, b = w1 < t1 ? w1 : t1;
+        if (a < b) {
+          atomicAdd(&kd[a - t0], 1);
+          atomicAdd(&kd[b - t0], -1);
+        }
+      }
+      if (lits) {
+        const uint64_t a = w1 > t0 ? w1 : t0, b = w2 < t1 ? w2 : t1;
+        if (a < b) {
+          atomicAdd(&kd[a - t0], 65536);
+          atomicAdd(&kd[b - t0], -65536);
+        }
+      }
+      wk.pos += 1 + lits;
+      wk.w = w2;
+    }
+  }
+  __syncthreads();
+
+  // 2. prefix sum: kd[c] = k + 65536 * d for column c
+  {
+    const int32_t v = tid < kTile ? kd[tid] : 0;
+    const int32_t ex = block_exclusive_scan<int32_t, kTileThreads / 64>(v, wave_tot, &total);
+    if (tid < kTile) kd[tid] = ex + v;
+  }
+  __syncthreads();
+
+  // 3. literal words of undecided columns into the per-column LDS counters
+  for (uint32_t j = tid; j < n_rle; j += kTileThreads) {
+    const RleDesc dsc = descs[j];
+    Walk wk;
+    if (!seek(dsc, tile, t0, wk)) continue;
+    while (wk.w < t1) {
+      if (wk.pos >= dsc.len) break;
+      const uint64_t m = dsc.words[wk.pos];
+      const uint64_t run = (m >> 1) & 0xFFFFFFFFull, lits = m >> 33;
+      const uint64_t w1 = wk.w + run, w2 = w1 + lits;
+      if (w2 > nwords || lits > dsc.len - wk.pos - 1) break;
+      if (lits) {
+        const uint64_t a = w1 > t0 ? w1 : t0, b = w2 < t1 ? w2 : t1;
+        for (uint64_t col = a; col < b; ++col) {
+          const int c = (int)(col - t0);
+          int k, d;
+          unpack_kd(kd[c], k, d);
+          const int tp = (int)theta - k;
+          if (tp >= 1 && tp <= d + (int)n_dense)
+            ripple_lds<K>(planes, c, dsc.words[wk.pos + 1 + (col - w1)]);
+        }
+      }
+      wk.pos += 1 + lits;
+      wk.w = w2;
+    }
+  }
+  __syncthreads();
+
+  // 4. one column per thread: decide, or count and compare
+  const int c = tid;
+  if (c < (int)(t1 - t0)) {
+    int k, d;
+    unpack_kd(kd[c], k, d);
+    const int tp = (int)theta - k;
+    uint64_t res;
+    if (tp <= 0) {
+      res = ~(uint64_t)0;
+    } else if (tp > d + (int)n_dense) {
+      res = 0;
+    } else {
+      uint64_t P[K];
+#pragma unroll
+      for (int q = 0; q < K; ++q) P[q] = planes[q * kTile + c];
+      const uint64_t col = t0 + c;
+      for (uint32_t i = 0; i < n_dense; ++i) {
+        uint64_t x = dense[i][col];
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+          const uint64_t t = P[q] & x;
+          P[q] ^= x;
+          x = t;
+        }
+      }
+      res = greater_than_lane<K>(P, (uint32_t)(tp - 1));
+    }
+    out[t0 + c] = res & valid_mask_dev(t0 + c, nwords, tail_mask);
+  }
+}
+
+// ------------------------------------------------------------- encoder
+// kind: 0 zero fill, 1 ones fill, 2 dirty
+__device__ __forceinline__ int word_kind(uint64_t x) {
+  return x == 0 ? 0 : (x == ~(uint64_t)0 ? 1 : 2);
+}
+
+struct EncArgs {
+  const uint64_t* dense;
+  uint64_t nwords;
+  uint64_t tail_mask;
+  uint64_t* block_sums;   // per block: (markers << 32) | dirty
+  uint32_t* seg_start;    // per marker: first word
+  uint32_t* seg_d0;       // per marker: dirty words before it
+  uint32_t* chk_marker;   // per checkpoint: marker covering it
+  uint64_t* totals;       // [0] = (markers << 32) | dirty
+  uint64_t* out;
+  uint64_t cap;
+  uint64_t* out_len;
+  uint64_t* index;        // optional: 2 words per checkpoint
+  int* status;
+};
+
+__device__ __forceinline__ uint64_t enc_word(const EncArgs& a, uint64_t w) {
+  return a.dense[w] & valid_mask_dev(w, a.nwords, a.tail_mask);
+}
+
+// packed contribution of word w: (is a marker start) << 32 | (is dirty)
+__device__ __forceinline__ uint64_t enc_contrib(const EncArgs& a, uint64_t w, int* kind_out) {
+  const int kc = word_kind(enc_word(a, w));
+  *kind_out = kc;
+  uint64_t start;
+  if (w == 0) {
+    start = 1;
+  } else if (kc == 2) {
+    start = 0;
+  } else {
+    const int kp = word_kind(enc_word(a, w - 1));
+    start = (kp == 2 || kp != kc) ? 1 : 0;
+  }
+  return (start << 32) | (kc == 2 ? 1u : 0u);
+}
+
+__global__ __launch_bounds__(kEncBlock) void enc_reduce_kernel(EncArgs a) {
+  __shared__ uint64_t wave_tot[kEncBlock / 64];
+  __shared__ uint64_t total;
+  const uint64_t base = (uint64_t)blockIdx.x * kEncWords + (uint64_t)threadIdx.x * kEncPerThread;
+  uint64_t s = 0;
+  int kind;
+#pragma unroll
+  for (int q = 0; q < kEncPerThread; ++q)
+    if (base + q < a.nwords) s += enc_contrib(a, base + q, &kind);
+  block_exclusive_scan<uint64_t, kEncBlock / 64>(s, wave_tot, &total);
+  if (threadIdx.x == 0) a.block_sums[blockIdx.x] = total;
+}
+
+// exclusive scan of the block sums (one workgroup), totals and output length
+__global__ __launch_bounds__(1024) void enc_scan_kernel(EncArgs a, uint64_t nblocks) {
+  __shared__ uint64_t wave_tot[16];
+  __shared__ uint64_t total;
+  uint64_t carry = 0;
+  for (uint64_t b0 = 0; b0 < nblocks; b0 += 1024) {
+    const uint64_t b = b0 + threadIdx.x;
+    const uint64_t v = b < nblocks ? a.block_sums[b] : 0;
+    const uint64_t ex = block_exclusive_scan<uint64_t, 16>(v, wave_tot, &total);
+    if (b < nblocks) a.block_sums[b] = ex + carry;
+    carry += total;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    a.totals[0] = carry;
+    const uint64_t len = (carry >> 32) + (carry & 0xFFFFFFFFull);
+    *a.out_len = len;
+    if (len > a.cap) set_status(a.status, TQ_ECAPACITY);
+  }
+}
+
+__global__ __launch_bounds__(kEncBlock) void enc_scatter_kernel(EncArgs a) {
+  __shared__ uint64_t wave_tot[kEncBlock / 64];
+  __shared__ uint64_t total;
+  const uint64_t base = (uint64_t)blockIdx.x * kEncWords + (uint64_t)threadIdx.x * kEncPerThread;
+  uint64_t c[kEncPerThread];
+  int kinds[kEncPerThread];
+  uint64_t s = 0;
+#pragma unroll
+  for (int q = 0; q < kEncPerThread; ++q) {
+    c[q] = base + q < a.nwords ? enc_contrib(a, base + q, &kinds[q]) : 0;
+    s += c[q];
+  }
+  uint64_t pre = block_exclusive_scan<uint64_t, kEncBlock / 64>(s, wave_tot, &total) + a.block_sums[blockIdx.x];
+#pragma unroll
+  for (int q = 0; q < kEncPerThread; ++q) {
+    const uint64_t w = base + q;
+    if (w >= a.nwords) break;
+    const uint64_t ms = pre >> 32, ds = pre & 0xFFFFFFFFull;
+    const uint64_t st = c[q] >> 32;
+    if (st) {
+      a.seg_start[ms] = (uint32_t)w;
+      a.seg_d0[ms] = (uint32_t)ds;
+    }
+    if (w % kTile == 0) a.chk_marker[w / kTile] = (uint32_t)(ms + st - 1);
+    if (kinds[q] == 2) {
+      const uint64_t pos = ms + ds + st;
+      if (pos < a.cap) a.out[pos] = enc_word(a, w);
+    }
+    pre += c[q];
+  }
+}
+
+__global__ void enc_marker_kernel(EncArgs a) {
+  const uint64_t tot = a.totals[0];
+  const uint64_t M = tot >> 32, D = tot & 0xFFFFFFFFull;
+  for (uint64_t m = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; m < M;
+       m += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t s = a.seg_start[m];
+    const uint64_t s1 = m + 1 < M ? a.seg_start[m + 1] : a.nwords;
+    const uint64_t d0 = a.seg_d0[m];
+    const uint64_t d1 = m + 1 < M ? a.seg_d0[m + 1] : D;
+    const uint64_t lits = d1 - d0;
+    const uint64_t run = s1 - s - lits;
+    const uint64_t fill = word_kind(enc_word(a, s)) == 1 ? 1 : 0;
+    const uint64_t pos = m + d0;
+    if (pos < a.cap) a.out[pos] = fill | (run << 1) | (lits << 33);
+  }
+}
+
+__global__ void enc_index_kernel(EncArgs a, uint64_t nchk) {
+  for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nchk;
+       c += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t m = a.chk_marker[c];
+    a.index[2 * c] = m + a.seg_d0[m];
+    a.index[2 * c + 1] = a.seg_start[m];
+  }
+}
+
+// ------------------------------------------------------ index building
+// One wave per stream walks its marker chain.  The stream is pulled in
+// 256-word chunks (four words per lane, coalesced); each marker is read with
+// readlane from the chunk, so the walk itself is scalar work.
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int lane) {
+  const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+  const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+  return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+__global__ __launch_bounds__(64) void build_index_kernel(const uint64_t* __restrict__ s, uint64_t len,
+                                                         uint64_t nwords, uint64_t* __restrict__ index,
+                                                         int* __restrict__ status) {
+  const int lane = threadIdx.x;
+  const uint64_t nchk = (nwords + kTile - 1) / kTile;
+  uint64_t base = ~(uint64_t)0;
+  uint64_t chunk[4] = {0, 0, 0, 0};
+  uint64_t pos = 0, w = 0, c = 0;
+  bool bad = false;
+  while (pos < len) {
+    if (base == ~(uint64_t)0 || pos >= base + 256) {
+      base = pos;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint64_t p = base + (uint64_t)q * 64 + lane;
+        chunk[q] = p < len ? s[p] : 0;
+      }
+    }
+    const uint64_t off = pos - base;
+    const int q = (int)(off >> 6);
+    const int ln = (int)(off & 63);
+    uint64_t m;
+    if (q == 0) m = readlane64(chunk[0], ln);
+    else if (q == 1) m = readlane64(chunk[1], ln);
+    else if (q == 2) m = readlane64(chunk[2], ln);
+    else m = readlane64(chunk[3], ln);
+    const uint64_t run = (m >> 1) & 0xFFFFFFFFull, lits = m >> 33;
+    const uint64_t end = w + run + lits;
+    if (end > nwords || lits > len - pos - 1) { bad = true; break; }
+    while (c < nchk && c * kTile < end) {
+      if (lane == 0) {
+        index[2 * c] = pos;
+        index[2 * c + 1] = w;
+      }
+      ++c;
+    }
+    pos += 1 + lits;
+    w = end;
+  }
+  if (bad || w != nwords || pos != len) {
+    if (lane == 0) set_status(status, TQ_EFORMAT);
+  }
+}
+
+uint32_t grid_cap(uint64_t want, uint32_t cap) {
+  if (want == 0) return 1;
+  return want > cap ? cap : (uint32_t)want;
+}
+
+typedef void (*TileFn)(const RleDesc*, uint32_t, const uint64_t* const*, uint32_t, uint64_t, uint64_t,
+                       uint32_t, uint64_t*, int*);
+
+TileFn pick_tile(int K) {
+  switch (K) {
+    case 4: return rle_tile_kernel<4>;
+    case 5: return rle_tile_kernel<5>;
+    case 6: return rle_tile_kernel<6>;
+    case 7: return rle_tile_kernel<7>;
+    case 8: return rle_tile_kernel<8>;
+    case 9: return rle_tile_kernel<9>;
+    case 10: return rle_tile_kernel<10>;
+    case 11: return rle_tile_kernel<11>;
+    case 12: return rle_tile_kernel<12>;
+    case 13: return rle_tile_kernel<13>;
+    case 16: return rle_tile_kernel<16>;
+  }
+  return nullptr;
+}
+
+}  // namespace
+
+size_t rle_tile_lds_bytes(int K) { return (size_t)K * kTile * 8 + (size_t)(kTile + 2) * 4; }
+
+hipError_t launch_rle_tile(const RleDesc* d_descs, uint32_t n_rle, const uint64_t* const* d_dense,
+                           uint32_t n_dense, uint64_t nwords, uint64_t tail_mask, uint32_t theta,
+                           uint64_t* d_out, int* d_status, hipStream_t stream) {
+  const int K = dense_planes_for(n_rle + n_dense);
+  TileFn fn = pick_tile(K);
+  if (!fn) return hipErrorInvalidValue;
+  const uint64_t tiles = (nwords + kTile - 1) / kTile;
+  if (tiles == 0) return hipSuccess;
+  const size_t lds = rle_tile_lds_bytes(K);
+  static bool attr_set[17] = {false};
+  if (!attr_set[K]) {
+    hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)lds);
+    attr_set[K] = true;
+  }
+  hipLaunchKernelGGL(fn, dim3((uint32_t)tiles), dim3(kTileThreads), lds, stream, d_descs, n_rle, d_dense,
+                     n_dense, nwords, tail_mask, theta, d_out, d_status);
+  return hipGetLastError();
+}
+
+size_t rle_encode_workspace_bytes(uint64_t nwords) {
+  const uint64_t nblocks = (nwords + kEncWords - 1) / kEncWords;
+  const uint64_t nchk = (nwords + kTile - 1) / kTile;
+  return 256 + nblocks * 8 + nwords * 8 + nchk * 4 + 256;
+}
+
+hipError_t launch_rle_encode(const uint64_t* d_dense, uint64_t nwords, uint64_t tail_mask, uint64_t* d_out,
+                             uint64_t cap, uint64_t* d_out_len, uint64_t* d_index, void* workspace,
+                             int* d_status, hipStream_t stream) {
+  const uint64_t nblocks = (nwords + kEncWords - 1) / kEncWords;
+  const uint64_t nchk = (nwords + kTile - 1) / kTile;
+  char* ws = static_cast<char*>(workspace);
+  EncArgs a;
+  a.dense = d_dense;
+  a.nwords = nwords;
+  a.tail_mask = tail_mask;
+  a.totals = reinterpret_cast<uint64_t*>(ws);
+  a.block_sums = reinterpret_cast<uint64_t*>(ws + 256);
+  a.seg_start = reinterpret_cast<uint32_t*>(ws + 256 + nblocks * 8);
+  a.seg_d0 = a.seg_start + nwords;
+  a.chk_marker = a.seg_d0 + nwords;
+  a.out = d_out;
+  a.cap = cap;
+  a.out_len = d_out_len;
+  a.index = d_index;
+  a.status = d_status;
+  hipLaunchKernelGGL(enc_reduce_kernel, dim3((uint32_t)nblocks), dim3(kEncBlock), 0, stream, a);
+  hipLaunchKernelGGL(enc_scan_kernel, dim3(1), dim3(1024), 0, stream, a, nblocks);
+  hipLaunchKernelGGL(enc_scatter_kernel, dim3((uint32_t)nblocks), dim3(kEncBlock), 0, stream, a);
+  hipLaunchKernelGGL(enc_marker_kernel, dim3(grid_cap((nwords + 255) / 256, 65536)), dim3(256), 0, stream, a);
+  if (d_index)
+    hipLaunchKernelGGL(enc_index_kernel, dim3(grid_cap((nchk + 255) / 256, 65536)), dim3(256), 0, stream, a,
+                       nchk);
+  return hipGetLastError();
+}
+
+hipError_t launch_build_index(const uint64_t* d_words, uint64_t len, uint64_t nwords, uint64_t* d_index,
+                              int* d_status, hipStream_t stream) {
+  hipLaunchKernelGGL(build_index_kernel, dim3(1), dim3(64), 0, stream, d_words, len, nwords, d_index,
+                     d_status);
+  return hipGetLastError();
+}
+
+}  // namespace tq

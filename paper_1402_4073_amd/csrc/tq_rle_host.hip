@@ -1,0 +1,224 @@
+// Host side of the run-length-encoded calls: validation, index provisioning,
+// workspace, and the kernel sequence of each call.
+#include <string.h>
+
+#include <vector>
+
+#include "tq_internal.h"
+
+namespace tq {
+
+namespace {
+
+__global__ void set_u64_kernel(uint64_t* dst, uint64_t v) { *dst = v; }
+
+uint64_t index_entries(uint64_t nwords) { return (nwords + TQ_RLE_INDEX_STRIDE - 1) / TQ_RLE_INDEX_STRIDE; }
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+hipError_t launch_set_u64(uint64_t* d_dst, uint64_t value, hipStream_t stream) {
+  hipLaunchKernelGGL(set_u64_kernel, dim3(1), dim3(1), 0, stream, d_dst, value);
+  return hipGetLastError();
+}
+
+void* workspace(tq_ctx* ctx, size_t bytes) {
+  if (bytes <= ctx->ws_bytes && ctx->ws) return ctx->ws;
+  // the old buffer may still be read by queued work
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) { record_hip(ctx, e); return nullptr; }
+  if (ctx->ws) hipFree(ctx->ws);
+  ctx->ws = nullptr;
+  ctx->ws_bytes = 0;
+  size_t want = align256(bytes + bytes / 4);
+  if ((e = hipMalloc(&ctx->ws, want)) != hipSuccess) {
+    record_hip(ctx, e);
+    ctx->ws = nullptr;
+    return nullptr;
+  }
+  ctx->ws_bytes = want;
+  return ctx->ws;
+}
+
+namespace {
+
+// Validate compressed inputs; counts those without an index.
+tq_status check_rle_inputs(const tq_rle* inputs, uint32_t n, uint64_t nwords, uint32_t* missing_index) {
+  *missing_index = 0;
+  for (uint32_t j = 0; j < n; ++j) {
+    const tq_rle& x = inputs[j];
+    if (nwords > 0 && (!x.words || x.n_words == 0)) return TQ_EINVAL;
+    if (((uintptr_t)x.words & 7) || ((uintptr_t)x.index & 7)) return TQ_EINVAL;
+    if (!x.index) ++*missing_index;
+  }
+  return TQ_OK;
+}
+
+// Bytes of workspace needed for the indexes the caller did not supply.
+tq_status missing_index_bytes(const tq_rle* inputs, uint32_t n_rle, uint64_t nw, size_t* bytes) {
+  uint32_t missing = 0;
+  tq_status st = check_rle_inputs(inputs, n_rle, nw, &missing);
+  *bytes = align256((size_t)missing * index_entries(nw) * 16);
+  return st;
+}
+
+// Common part of the compressed-input queries: tile kernel into d_dense_out.
+// idx_area: workspace for the indexes the caller did not supply (sized with
+// missing_index_bytes), allocated by the caller before any pointer into the
+// workspace is taken.
+tq_status run_rle_tiles(tq_ctx* ctx, const tq_rle* inputs, uint32_t n_rle, const uint64_t* const* dense_ptrs,
+                        uint32_t n_dense, uint64_t r_bits, uint32_t theta, uint64_t* d_dense_out,
+                        uint64_t* idx_area, hipStream_t stream) {
+  const uint64_t nw = words_for_bits(r_bits);
+  const uint64_t tmask = tail_mask_for(r_bits);
+  const uint32_t n = n_rle + n_dense;
+  if (theta == 0 || theta > n)
+    return record_hip(ctx, launch_fill(d_dense_out, nw, theta == 0 ? ~(uint64_t)0 : 0, tmask, stream));
+  std::vector<uint64_t> desc(3 * (size_t)(n_rle ? n_rle : 1), 0);
+  const uint64_t nchk = index_entries(nw);
+  uint32_t built = 0;
+  tq_status st = TQ_OK;
+  for (uint32_t j = 0; j < n_rle; ++j) {
+    const uint64_t* index = inputs[j].index;
+    if (!index) {
+      if (!idx_area) return TQ_EINVAL;
+      uint64_t* dst = idx_area + (size_t)built * nchk * 2;
+      st = record_hip(ctx, launch_build_index(inputs[j].words, inputs[j].n_words, nw, dst, ctx->d_status, stream));
+      if (st != TQ_OK) return st;
+      index = dst;
+      ++built;
+    }
+    desc[3 * j] = (uint64_t)(uintptr_t)inputs[j].words;
+    desc[3 * j + 1] = inputs[j].n_words;
+    desc[3 * j + 2] = (uint64_t)(uintptr_t)index;
+  }
+  Blob* bd = nullptr;
+  const void* d_desc = blob_get(ctx, desc.data(), desc.size(), stream, &bd);
+  if (!d_desc) return TQ_EDEVICE;
+  Blob* bp = nullptr;
+  const void* d_dense = nullptr;
+  if (n_dense) {
+    d_dense = blob_get(ctx, reinterpret_cast<const uint64_t*>(dense_ptrs), n_dense, stream, &bp);
+    if (!d_dense) return TQ_EDEVICE;
+  }
+  st = record_hip(ctx, launch_rle_tile(reinterpret_cast<const RleDesc*>(d_desc), n_rle,
+                                       reinterpret_cast<const uint64_t* const*>(d_dense), n_dense, nw, tmask,
+                                       theta, d_dense_out, ctx->d_status, stream));
+  blob_used(ctx, bd, stream);
+  if (bp) blob_used(ctx, bp, stream);
+  return st;
+}
+
+// Query with a dense result written to d_out; workspace holds only built indexes.
+tq_status rle_query_dense(tq_ctx* ctx, const tq_rle* inputs, uint32_t n_rle, const uint64_t* const* dense_ptrs,
+                          uint32_t n_dense, uint64_t r_bits, uint32_t theta, uint64_t* d_out, hipStream_t stream) {
+  const uint64_t nw = words_for_bits(r_bits);
+  size_t idx_bytes = 0;
+  tq_status st = missing_index_bytes(inputs, n_rle, nw, &idx_bytes);
+  if (st != TQ_OK) return st;
+  uint64_t* idx_area = nullptr;
+  if (idx_bytes) {
+    idx_area = static_cast<uint64_t*>(workspace(ctx, idx_bytes));
+    if (!idx_area) return TQ_ENOMEM;
+  }
+  return run_rle_tiles(ctx, inputs, n_rle, dense_ptrs, n_dense, r_bits, theta, d_out, idx_area, stream);
+}
+
+}  // namespace
+
+}  // namespace tq
+
+using namespace tq;
+
+extern "C" {
+
+uint64_t tq_rle_max_words(uint64_t r_bits) { return words_for_bits(r_bits) + 1; }
+
+uint64_t tq_rle_index_words(uint64_t r_bits) { return 2 * index_entries(words_for_bits(r_bits)); }
+
+tq_status tq_rle_encode(tq_ctx* ctx, const uint64_t* d_dense, uint64_t r_bits, uint64_t* d_out, uint64_t out_cap,
+                        uint64_t* d_out_len, uint64_t* d_index, hipStream_t stream) {
+  if (!ctx || !d_out_len) return TQ_EINVAL;
+  const uint64_t nw = words_for_bits(r_bits);
+  if (nw >= (1ull << 31)) return TQ_EINVAL;
+  if (nw == 0) return record_hip(ctx, launch_set_u64(d_out_len, 0, stream));
+  if (!d_dense || (!d_out && out_cap > 0)) return TQ_EINVAL;
+  if (((uintptr_t)d_dense & 7) || ((uintptr_t)d_out & 7) || ((uintptr_t)d_index & 7)) return TQ_EINVAL;
+  void* ws = workspace(ctx, rle_encode_workspace_bytes(nw));
+  if (!ws) return TQ_ENOMEM;
+  return record_hip(ctx, launch_rle_encode(d_dense, nw, tail_mask_for(r_bits), d_out, out_cap, d_out_len, d_index,
+                                           ws, ctx->d_status, stream));
+}
+
+tq_status tq_rle_build_index(tq_ctx* ctx, const uint64_t* d_words, uint64_t n_words, uint64_t r_bits,
+                             uint64_t* d_index, hipStream_t stream) {
+  if (!ctx || !d_index || !d_words || n_words == 0) return TQ_EINVAL;
+  const uint64_t nw = words_for_bits(r_bits);
+  if (nw == 0 || nw >= (1ull << 31)) return TQ_EINVAL;
+  if (((uintptr_t)d_words & 7) || ((uintptr_t)d_index & 7)) return TQ_EINVAL;
+  return record_hip(ctx, launch_build_index(d_words, n_words, nw, d_index, ctx->d_status, stream));
+}
+
+tq_status tq_rle_decode(tq_ctx* ctx, const tq_rle* input, uint64_t r_bits, uint64_t* d_dense, hipStream_t stream) {
+  if (!ctx || !input || !d_dense) return TQ_EINVAL;
+  const uint64_t nw = words_for_bits(r_bits);
+  if (nw >= (1ull << 31)) return TQ_EINVAL;
+  if (nw == 0) return TQ_OK;
+  if ((uintptr_t)d_dense & 7) return TQ_EINVAL;
+  // the 1-threshold of a single input is the input itself
+  return rle_query_dense(ctx, input, 1, nullptr, 0, r_bits, 1, d_dense, stream);
+}
+
+tq_status tq_threshold_rle_dense(tq_ctx* ctx, const tq_rle* inputs, uint32_t n, uint64_t r_bits, uint32_t theta,
+                                 uint64_t* d_out, hipStream_t stream) {
+  if (!ctx || !inputs || n == 0 || n > TQ_RLE_MAX_INPUTS) return TQ_EINVAL;
+  const uint64_t nw = words_for_bits(r_bits);
+  if (nw >= (1ull << 31)) return TQ_EINVAL;
+  if (nw == 0) return TQ_OK;
+  if (!d_out || ((uintptr_t)d_out & 7)) return TQ_EINVAL;
+  return rle_query_dense(ctx, inputs, n, nullptr, 0, r_bits, theta, d_out, stream);
+}
+
+tq_status tq_threshold_hybrid(tq_ctx* ctx, const tq_rle* rle_inputs, uint32_t n_rle, const uint64_t* const* dense_ptrs,
+                              uint32_t n_dense, uint64_t r_bits, uint32_t theta, uint64_t* d_out, hipStream_t stream) {
+  if (!ctx || (n_rle && !rle_inputs) || (n_dense && !dense_ptrs)) return TQ_EINVAL;
+  const uint64_t n = (uint64_t)n_rle + n_dense;
+  if (n == 0 || n > TQ_RLE_MAX_INPUTS) return TQ_EINVAL;
+  const uint64_t nw = words_for_bits(r_bits);
+  if (nw >= (1ull << 31)) return TQ_EINVAL;
+  if (nw == 0) return TQ_OK;
+  if (!d_out || ((uintptr_t)d_out & 7)) return TQ_EINVAL;
+  for (uint32_t j = 0; j < n_dense; ++j) {
+    const uintptr_t p = (uintptr_t)dense_ptrs[j];
+    if (!p || (p & 7)) return TQ_EINVAL;
+    if (p < (uintptr_t)(d_out + nw) && (uintptr_t)d_out < p + nw * 8) return TQ_EINVAL;
+  }
+  return rle_query_dense(ctx, rle_inputs, n_rle, dense_ptrs, n_dense, r_bits, theta, d_out, stream);
+}
+
+tq_status tq_threshold_rle(tq_ctx* ctx, const tq_rle* inputs, uint32_t n, uint64_t r_bits, uint32_t theta,
+                           uint64_t* d_out, uint64_t out_cap_words, uint64_t* d_out_len, hipStream_t stream) {
+  if (!ctx || !inputs || n == 0 || n > TQ_RLE_MAX_INPUTS || !d_out_len) return TQ_EINVAL;
+  const uint64_t nw = words_for_bits(r_bits);
+  if (nw >= (1ull << 31)) return TQ_EINVAL;
+  if (nw == 0) return record_hip(ctx, launch_set_u64(d_out_len, 0, stream));
+  if ((!d_out && out_cap_words) || ((uintptr_t)d_out & 7)) return TQ_EINVAL;
+  // workspace: [dense result | encoder scratch | built indexes], sized once
+  // before any pointer into it is taken
+  const size_t dense_bytes = align256(nw * 8);
+  const size_t enc_bytes = align256(rle_encode_workspace_bytes(nw));
+  size_t idx_bytes = 0;
+  tq_status st = missing_index_bytes(inputs, n, nw, &idx_bytes);
+  if (st != TQ_OK) return st;
+  char* ws = static_cast<char*>(workspace(ctx, dense_bytes + enc_bytes + idx_bytes));
+  if (!ws) return TQ_ENOMEM;
+  uint64_t* dense = reinterpret_cast<uint64_t*>(ws);
+  uint64_t* idx_area = idx_bytes ? reinterpret_cast<uint64_t*>(ws + dense_bytes + enc_bytes) : nullptr;
+  st = run_rle_tiles(ctx, inputs, n, nullptr, 0, r_bits, theta, dense, idx_area, stream);
+  if (st != TQ_OK) return st;
+  return record_hip(ctx, launch_rle_encode(dense, nw, tail_mask_for(r_bits), d_out, out_cap_words, d_out_len,
+                                           nullptr, ws + dense_bytes, ctx->d_status, stream));
+}
+
+}  // extern "C"

@@ -3,8 +3,8 @@
 Each test checks the oracle against something fixed by the paper or by
 mathematics: the exhaustive-combination fixture (every input combination
 appears at a known position, so the count is popcount of the position), the
-Looped recurrence of section 4.4.6 evaluated with whole-bitmap AND/OR, the
-sorting view of section 4.4.2 (the T-th largest input bit is the threshold),
+Looped recurrence of section 4.5 evaluated with whole-bitmap AND/OR, the
+sorting view of section 4.4.1 (the T-th largest input bit is the threshold),
 library reductions (OR, AND, XOR), and identities of section 2.3.
 """
 import os
@@ -84,7 +84,7 @@ def test_exhaustive_ragged_tail(orc):
 
 # ------------------------------------------------ independent algorithms
 def looped(bitmaps, theta):
-    """Looped recurrence (section 4.4.6): C_j holds the j-threshold of the
+    """Looped recurrence (section 4.5): C_j holds the j-threshold of the
     inputs seen so far; adding input b turns C_j into C_j OR (C_{j-1} AND b)."""
     n = len(bitmaps)
     if theta == 0:

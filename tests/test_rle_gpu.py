@@ -1,0 +1,295 @@
+"""Run-length-encoded path on the GPU against the CPU oracle.
+
+The GPU encoder must produce the oracle's canonical stream byte for byte;
+threshold queries over compressed inputs must produce the oracle's canonical
+encoding of the oracle's threshold; dense-output and hybrid queries must
+equal the oracle's dense threshold.  At the full RLE configuration (N=512,
+r=2^28) outputs are checked on sampled columns and against the uncompressed
+path on the same inputs.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import tqgen
+from gpuhelp import dev_pool, empty_words, to_dev, to_host
+from paper_1402_4073_amd import binding as tq
+
+pytestmark = pytest.mark.gpu
+
+STRIDE = tq.TQ_RLE_INDEX_STRIDE
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = tq.tq_create(0)
+    yield c
+    tq.tq_destroy(c)
+
+
+def mk(fill, run, lits):
+    return (fill & 1) | (run << 1) | (lits << 33)
+
+
+def expected_index(stream, r_bits):
+    """Checkpoint index by its definition: for checkpoint c, the marker whose
+    run covers word c*STRIDE (stream offset, start word)."""
+    nw = (r_bits + 63) // 64
+    nchk = (nw + STRIDE - 1) // STRIDE
+    idx = np.zeros(2 * nchk, dtype=np.uint64)
+    pos, w, c = 0, 0, 0
+    s = [int(x) for x in stream]
+    while pos < len(s):
+        m = s[pos]
+        run, lits = (m >> 1) & 0xFFFFFFFF, m >> 33
+        end = w + run + lits
+        while c < nchk and c * STRIDE < end:
+            idx[2 * c], idx[2 * c + 1] = pos, w
+            c += 1
+        pos += 1 + lits
+        w = end
+    return idx
+
+
+def markov_bitmaps(seed, n, r, ones, zeros):
+    ms = tqgen.markov_fixed(seed, n, r, ones, zeros)
+    return [ms.words(j) for j in range(n)]
+
+
+def special_bitmaps(r):
+    nw = (r + 63) // 64
+    out = []
+    out.append(np.zeros(nw, dtype=np.uint64))
+    out.append(np.full(nw, np.uint64(0xFFFFFFFFFFFFFFFF)))
+    alt = np.zeros(nw, dtype=np.uint64)
+    alt[1::2] = np.uint64(0xFFFFFFFFFFFFFFFF)
+    out.append(alt)                                  # alternating fills
+    d0 = np.full(nw, np.uint64(0xFFFFFFFFFFFFFFFF))
+    d0[0] = 12345                                    # dirty first word
+    out.append(d0)
+    dc = np.zeros(nw, dtype=np.uint64)
+    dc[::2] = np.uint64(0x00FF00FF00FF00FF)          # dirty / clean alternating
+    out.append(dc)
+    return out
+
+
+def gpu_encode(ctx, dense_np, r):
+    d = to_dev(dense_np)
+    cap = tq.tq_rle_max_words(r)
+    out = empty_words(cap)
+    ln = torch.zeros(1, dtype=torch.int64, device="cuda")
+    idx = torch.zeros(max(1, tq.tq_rle_index_words(r)), dtype=torch.int64, device="cuda")
+    tq.tq_rle_encode(ctx, d, r, out, cap, ln, idx)
+    assert tq.tq_ctx_check(ctx) == 0
+    L = int(ln.item())
+    return to_host(out)[:L], to_host(idx)
+
+
+# ------------------------------------------------------------------ encoder
+@pytest.mark.parametrize("r", [64, 65, 1000, 64 * 512, 64 * 512 + 1, 64 * 3000 + 17, 1 << 20])
+def test_encoder_matches_oracle(ctx, r):
+    cases = special_bitmaps(r) + markov_bitmaps(r, 4, r, 50.0, 900.0) + markov_bitmaps(r + 1, 2, r, 2.0, 3.0)
+    for k, dense in enumerate(cases):
+        got, idx = gpu_encode(ctx, dense, r)
+        want = oracle.rle_encode(dense, r)
+        assert np.array_equal(got, want), k
+        assert np.array_equal(idx, expected_index(want, r)), k
+
+
+def test_encoder_capacity(ctx):
+    r = 64 * 100
+    dense = markov_bitmaps(7, 1, r, 3.0, 5.0)[0]
+    want = oracle.rle_encode(dense, r)
+    d = to_dev(dense)
+    out = empty_words(len(want))
+    ln = torch.zeros(1, dtype=torch.int64, device="cuda")
+    cap = len(want) - 3
+    tq.tq_rle_encode(ctx, d, r, out, cap, ln)
+    assert tq.tq_ctx_check(ctx) == tq.TQ_ECAPACITY
+    assert int(ln.item()) == len(want)                # required length reported
+    got = to_host(out)
+    assert np.all(got[cap:] == np.uint64(0x5A5A5A5A5A5A5A5A))   # nothing past the capacity
+    assert tq.tq_ctx_check(ctx) == 0                  # status cleared
+
+
+# -------------------------------------------------------------- index build
+def test_build_index_canonical_and_not(ctx):
+    r = 64 * 2000 + 9
+    for dense in markov_bitmaps(11, 3, r, 40.0, 700.0):
+        s = oracle.rle_encode(dense, r)
+        d = to_dev(s)
+        idx = torch.zeros(tq.tq_rle_index_words(r), dtype=torch.int64, device="cuda")
+        tq.tq_rle_build_index(ctx, d, len(s), r, idx)
+        assert tq.tq_ctx_check(ctx) == 0
+        assert np.array_equal(to_host(idx), expected_index(s, r))
+    # non-canonical: split runs, clean literals, empty markers
+    r = 64 * 1300
+    parts = [mk(0, 300, 0), mk(0, 300, 2), 5, 0, mk(0, 0, 0), mk(1, 100, 0), mk(1, 0, 1), 7,
+             mk(0, 597, 0)]
+    s = np.array(parts, dtype=np.uint64)
+    idx = torch.zeros(tq.tq_rle_index_words(r), dtype=torch.int64, device="cuda")
+    tq.tq_rle_build_index(ctx, to_dev(s), len(s), r, idx)
+    assert tq.tq_ctx_check(ctx) == 0
+    assert np.array_equal(to_host(idx), expected_index(s, r))
+
+
+def test_build_index_rejects_malformed(ctx):
+    r = 64 * 1000
+    for parts in ([mk(0, 999, 0)], [mk(0, 1001, 0)], [mk(0, 998, 3), 1, 2, 3], [mk(0, 990, 5), 1, 2]):
+        s = np.array(parts, dtype=np.uint64)
+        idx = torch.zeros(tq.tq_rle_index_words(r), dtype=torch.int64, device="cuda")
+        tq.tq_rle_build_index(ctx, to_dev(s), len(s), r, idx)
+        assert tq.tq_ctx_check(ctx) == tq.TQ_EFORMAT, parts
+
+
+# ------------------------------------------------------------------- decode
+def test_decode(ctx):
+    r = 64 * 1500 + 33
+    for dense in special_bitmaps(r) + markov_bitmaps(13, 3, r, 30.0, 400.0):
+        s = oracle.rle_encode(dense, r)
+        d = to_dev(s)
+        out = empty_words((r + 63) // 64)
+        tq.tq_rle_decode(ctx, (d, len(s), None), r, out)
+        assert tq.tq_ctx_check(ctx) == 0
+        assert np.array_equal(to_host(out), oracle.rle_decode(s, r))
+
+
+def test_decode_rejects_malformed(ctx):
+    r = 64 * 1000
+    s = np.array([mk(0, 998, 3), 1, 2, 3], dtype=np.uint64)
+    idx = np.zeros(tq.tq_rle_index_words(r), dtype=np.uint64)   # claims every tile starts at marker 0
+    out = empty_words(1000)
+    tq.tq_rle_decode(ctx, (to_dev(s), len(s), to_dev(idx)), r, out)
+    assert tq.tq_ctx_check(ctx) == tq.TQ_EFORMAT
+
+
+# ---------------------------------------------------------------- threshold
+def rle_inputs(ctx, dense_list, r, with_index=True, use_oracle_encoding=False):
+    keep, inputs = [], []
+    for dense in dense_list:
+        if use_oracle_encoding:
+            s = oracle.rle_encode(dense, r)
+            idx = expected_index(s, r) if with_index else None
+        else:
+            s, idx = gpu_encode(ctx, dense, r)
+            idx = idx if with_index else None
+        ds = to_dev(s)
+        di = to_dev(idx) if idx is not None else None
+        keep += [ds, di]
+        inputs.append((ds, len(s), di))
+    return inputs, keep
+
+
+@pytest.mark.parametrize("n,r", [(1, 64 * 600), (5, 64 * 1100 + 3), (37, 64 * 2050), (200, 64 * 1025 + 63)])
+def test_threshold_rle_matches_oracle(ctx, n, r):
+    rng = np.random.default_rng(n)
+    dense = markov_bitmaps(100 + n, n, r, float(rng.integers(20, 200)), float(rng.integers(100, 3000)))
+    dense[0] = special_bitmaps(r)[int(rng.integers(0, 5))]
+    for variant in ("gpu-encoded", "oracle-encoded", "no-index"):
+        inputs, keep = rle_inputs(ctx, dense, r, with_index=(variant != "no-index"),
+                                  use_oracle_encoding=(variant == "oracle-encoded"))
+        for theta in sorted({0, 1, 2, max(1, n // 3), n, n + 1}):
+            want_dense = oracle.threshold(dense, r, theta)
+            want = oracle.rle_encode(want_dense, r)
+            cap = tq.tq_rle_max_words(r)
+            out = empty_words(cap)
+            ln = torch.zeros(1, dtype=torch.int64, device="cuda")
+            tq.tq_threshold_rle(ctx, inputs, r, theta, out, cap, ln)
+            assert tq.tq_ctx_check(ctx) == 0
+            L = int(ln.item())
+            assert L == len(want), (variant, theta)
+            assert np.array_equal(to_host(out)[:L], want), (variant, theta)
+            dout = empty_words((r + 63) // 64)
+            tq.tq_threshold_rle_dense(ctx, inputs, r, theta, dout)
+            assert tq.tq_ctx_check(ctx) == 0
+            assert np.array_equal(to_host(dout), want_dense), (variant, theta)
+
+
+def test_threshold_rle_noncanonical_inputs(ctx):
+    r = 64 * 1300
+    a = np.array([mk(0, 300, 0), mk(0, 300, 2), 5, 0, mk(0, 0, 0), mk(1, 100, 0), mk(1, 0, 1), 7,
+                  mk(0, 597, 0)], dtype=np.uint64)
+    b = oracle.rle_encode(markov_bitmaps(3, 1, r, 10.0, 10.0)[0], r)
+    c = np.array([mk(1, 1300, 0)], dtype=np.uint64)
+    dense = [oracle.rle_decode(x, r) for x in (a, b, c)]
+    inputs = [(to_dev(x), len(x), None) for x in (a, b, c)]
+    for theta in (1, 2, 3):
+        out = empty_words((r + 63) // 64)
+        tq.tq_threshold_rle_dense(ctx, inputs, r, theta, out)
+        assert tq.tq_ctx_check(ctx) == 0
+        assert np.array_equal(to_host(out), oracle.threshold(dense, r, theta))
+
+
+def test_threshold_rle_capacity_and_format(ctx):
+    r = 64 * 700
+    dense = markov_bitmaps(21, 6, r, 5.0, 9.0)
+    inputs, keep = rle_inputs(ctx, dense, r)
+    want = oracle.rle_encode(oracle.threshold(dense, r, 3), r)
+    out = empty_words(len(want))
+    ln = torch.zeros(1, dtype=torch.int64, device="cuda")
+    tq.tq_threshold_rle(ctx, inputs, r, 3, out, len(want) - 1, ln)
+    assert tq.tq_ctx_check(ctx) == tq.TQ_ECAPACITY
+    assert int(ln.item()) == len(want)
+    bad = np.array([mk(0, 600, 0)], dtype=np.uint64)            # covers too few words
+    inputs2 = inputs[:2] + [(to_dev(bad), 1, None)]
+    tq.tq_threshold_rle(ctx, inputs2, r, 2, out, len(want), ln)
+    assert tq.tq_ctx_check(ctx) == tq.TQ_EFORMAT
+    # host-side argument errors
+    assert tq.raw_threshold_rle(ctx, [], r, 1, out.data_ptr(), 10, ln.data_ptr()) == tq.TQ_EINVAL
+    assert tq.raw_threshold_rle(ctx, inputs, r, 1, out.data_ptr(), 10, 0) == tq.TQ_EINVAL
+
+
+@pytest.mark.parametrize("n_rle,n_dense", [(3, 2), (0, 4), (20, 20), (1, 0)])
+def test_hybrid(ctx, n_rle, n_dense):
+    r = 64 * 1700 + 5
+    dense_all = markov_bitmaps(300 + n_rle, n_rle + n_dense, r, 60.0, 500.0)
+    inputs, keep = rle_inputs(ctx, dense_all[:n_rle], r)
+    pool = dev_pool(dense_all[n_rle:]) if n_dense else None
+    drows = [pool[j] for j in range(n_dense)] if n_dense else []
+    n = n_rle + n_dense
+    for theta in sorted({1, 2, max(1, n // 2), n}):
+        out = empty_words((r + 63) // 64)
+        tq.tq_threshold_hybrid(ctx, inputs, drows, r, theta, out)
+        assert tq.tq_ctx_check(ctx) == 0
+        assert np.array_equal(to_host(out), oracle.threshold(dense_all, r, theta)), theta
+
+
+# ------------------------------------------------------- full configuration
+def test_rle_config_full_size(ctx):
+    """N=512 Markov bitmaps of r=2^28 bits (ones-runs mean 64, zeros-runs mean
+    4096), encoded on the GPU; thresholds 2, 64, 256 checked on sampled words
+    against the oracle and in full against the uncompressed kernel."""
+    ms = tqgen.rle_set(3)
+    n, nw, r = ms.n, ms.nwords, ms.r_bits
+    dense = torch.empty((n, nw), dtype=torch.int64, device="cuda")
+    chunk = 64
+    for j0 in range(0, n, chunk):
+        tqgen.fill_gpu(ms, dense[j0:j0 + chunk].reshape(-1), first=j0, count=min(chunk, n - j0))
+    rows = [dense[j] for j in range(n)]
+    pool, offs, lens, index_pool = tq.encode_pool(ctx, rows, r)
+    inputs = [(pool[offs[j]:], lens[j], index_pool[j]) for j in range(n)]
+    rng = np.random.default_rng(5)
+    cols = np.unique(np.concatenate([[0, nw - 1], rng.integers(0, nw, 48)])).astype(np.int64)
+    words = np.stack([np.concatenate([ms.words(j, int(c), int(c) + 1) for c in cols]) for j in range(n)])
+    # the GPU-encoded inputs decode back to the generator's words at the sampled columns
+    for j in (0, n - 1):
+        dec = torch.empty(nw, dtype=torch.int64, device="cuda")
+        tq.tq_rle_decode(ctx, inputs[j], r, dec)
+        assert tq.tq_ctx_check(ctx) == 0
+        assert np.array_equal(to_host(dec)[cols], words[j])
+    cap = tq.tq_rle_max_words(r)
+    out = torch.empty(cap, dtype=torch.int64, device="cuda")
+    ln = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ref = torch.empty(nw, dtype=torch.int64, device="cuda")
+    for theta in (2, 64, 256):
+        tq.tq_threshold_rle(ctx, inputs, r, theta, out, cap, ln)
+        assert tq.tq_ctx_check(ctx) == 0
+        L = int(ln.item())
+        stream = to_host(out)[:L]
+        got = oracle.rle_decode(stream, r)                       # valid, exact coverage
+        assert np.array_equal(oracle.rle_encode(got, r), stream)  # canonical
+        assert np.array_equal(got[cols], oracle.threshold_cols(words, cols, r, theta)), theta
+        tq.tq_threshold(ctx, rows, r, theta, ref)                # uncompressed path, same inputs
+        assert tq.tq_ctx_check(ctx) == 0
+        assert np.array_equal(got, to_host(ref)), theta
