@@ -197,6 +197,69 @@ tq_status tq_threshold_hybrid(tq_ctx* ctx, const tq_rle* rle_inputs, uint32_t n_
                               const uint64_t* const* dense_ptrs, uint32_t n_dense, uint64_t r_bits,
                               uint32_t theta, uint64_t* d_out, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Batched queries: many threshold / symmetric queries of uneven N, r and
+ * theta served by one persistent kernel launch, replayed from a graph.
+ * ---------------------------------------------------------------------- */
+typedef enum tq_query_kind { TQ_QUERY_THRESHOLD = 0, TQ_QUERY_SYMMETRIC = 1 } tq_query_kind;
+
+typedef struct tq_query {
+  uint32_t kind;                /* tq_query_kind */
+  uint32_t n;                   /* number of inputs, [1, TQ_MAX_INPUTS] */
+  const uint64_t* const* ptrs;  /* HOST array of n device pointers (copied at submission) */
+  uint64_t r_bits;
+  uint32_t theta;               /* TQ_QUERY_THRESHOLD */
+  uint32_t pad;
+  const uint64_t* h_truth;      /* TQ_QUERY_SYMMETRIC: host truth table as for tq_symmetric (copied) */
+  uint64_t* d_out;              /* ceil(r_bits/64) device words */
+  uint64_t user_tag;            /* returned in the query's record */
+} tq_query;
+
+typedef struct tq_query_record {
+  uint64_t user_tag;
+  int32_t status;               /* TQ_OK once done */
+  uint32_t done;                /* 1 once the query's output is complete and visible */
+  uint64_t t_start_ns;          /* device clock when the first work item of the query started */
+  uint64_t t_end_ns;            /* device clock when its last work item finished */
+} tq_query_record;
+
+typedef struct tq_batch tq_batch;
+
+/* Flags of tq_batch_submit. */
+#define TQ_BATCH_NO_GRAPH 1u    /* launch directly instead of replaying the slot's graph */
+
+/* Largest batch: queries and total pointer entries (sum of n). */
+#define TQ_BATCH_MAX_QUERIES 8192u
+#define TQ_BATCH_MAX_POINTERS 2097152u
+
+/*
+ * Submit `count` queries as one batch on `stream`.  Each query has the
+ * semantics of tq_threshold or tq_symmetric (sections 2.2-2.3); results are
+ * bit-identical to those calls.  Queries with n > 1 are split into work items
+ * of similar byte counts that a persistent kernel serves from one queue.
+ * Admission: a context holds a fixed number of batch slots; when none is free
+ * the call returns TQ_EBUSY and queues nothing (retry after releasing a
+ * batch).  count in [1, TQ_BATCH_MAX_QUERIES]; sum of n at most
+ * TQ_BATCH_MAX_POINTERS; a symmetric function that needs a lookup table
+ * (more than 8 runs of ones and of zeros in f) returns TQ_ENOTSUP.  All
+ * pointer arrays and truth tables are copied; *out receives the batch.
+ */
+tq_status tq_batch_submit(tq_ctx* ctx, const tq_query* queries, uint32_t count, uint32_t flags,
+                          hipStream_t stream, tq_batch** out);
+
+/* Number of queries of the batch whose output is complete (non-blocking;
+ * completion flags are written by the device into pinned host memory). */
+tq_status tq_batch_poll(tq_batch* batch, uint32_t* ndone);
+
+/* Block until the whole batch has completed. */
+tq_status tq_batch_wait(tq_batch* batch);
+
+/* Copy the batch's per-query records (count entries, submission order). */
+tq_status tq_batch_records(tq_batch* batch, tq_query_record* out);
+
+/* Wait for the batch, free its slot and the handle. */
+tq_status tq_batch_release(tq_batch* batch);
+
 #ifdef __cplusplus
 }
 #endif

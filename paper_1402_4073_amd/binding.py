@@ -63,6 +63,11 @@ def _load():
         "tq_threshold_rle": (_INT, [_P, _P, _U32, _U64, _U32, _P, _U64, _P, _P]),
         "tq_threshold_rle_dense": (_INT, [_P, _P, _U32, _U64, _U32, _P, _P]),
         "tq_threshold_hybrid": (_INT, [_P, _P, _U32, _P, _U32, _U64, _U32, _P, _P]),
+        "tq_batch_submit": (_INT, [_P, _P, _U32, _U32, _P, ctypes.POINTER(_P)]),
+        "tq_batch_poll": (_INT, [_P, ctypes.POINTER(_U32)]),
+        "tq_batch_wait": (_INT, [_P]),
+        "tq_batch_records": (_INT, [_P, _P]),
+        "tq_batch_release": (_INT, [_P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -267,6 +272,87 @@ def encode_pool(ctx: int, dense_rows, r_bits: int, stream=None):
     if st != TQ_OK:
         raise TQError(st, "encode_pool")
     return pool, offs[:-1], hl, index_pool
+
+
+# ------------------------------------------------------------------ batch
+TQ_QUERY_THRESHOLD = 0
+TQ_QUERY_SYMMETRIC = 1
+TQ_BATCH_NO_GRAPH = 1
+TQ_BATCH_MAX_QUERIES = 8192
+TQ_BATCH_MAX_POINTERS = 2097152
+
+
+class TqQuery(ctypes.Structure):
+    _fields_ = [("kind", _U32), ("n", _U32), ("ptrs", _U64), ("r_bits", _U64), ("theta", _U32),
+                ("pad", _U32), ("h_truth", _U64), ("d_out", _U64), ("user_tag", _U64)]
+
+
+class TqQueryRecord(ctypes.Structure):
+    _fields_ = [("user_tag", _U64), ("status", ctypes.c_int32), ("done", _U32),
+                ("t_start_ns", _U64), ("t_end_ns", _U64)]
+
+
+class BatchQueries:
+    """Host-side tq_query array plus the pointer arrays and truth tables it
+    points to (kept alive until submission has copied them)."""
+
+    def __init__(self, specs):
+        """specs: list of dicts with keys inputs, r_bits, out, and theta or truth, optional tag."""
+        self.keep = []
+        self.arr = (TqQuery * max(1, len(specs)))()
+        for i, sp in enumerate(specs):
+            q = self.arr[i]
+            ptrs = ptr_array(sp["inputs"])
+            self.keep.append(ptrs)
+            q.n = len(sp["inputs"])
+            q.ptrs = ctypes.addressof(ptrs)
+            q.r_bits = int(sp["r_bits"])
+            q.d_out = _ptr(sp["out"])
+            q.user_tag = int(sp.get("tag", i))
+            if "truth" in sp:
+                tw = _u64_host(truth_words(sp["truth"]))
+                self.keep.append(tw)
+                q.kind = TQ_QUERY_SYMMETRIC
+                q.h_truth = ctypes.addressof(tw)
+            else:
+                q.kind = TQ_QUERY_THRESHOLD
+                q.theta = int(sp["theta"])
+        self.count = len(specs)
+
+
+def tq_batch_submit(ctx: int, queries: "BatchQueries", flags: int = 0, stream=None) -> int:
+    """Returns the batch handle; raises TQError (status TQ_EBUSY when no slot is free)."""
+    h = _P()
+    _check(_lib.tq_batch_submit(ctx, queries.arr, queries.count, flags, _stream(stream), ctypes.byref(h)),
+           "tq_batch_submit")
+    return h.value
+
+
+def raw_batch_submit(ctx: int, queries: "BatchQueries", flags: int = 0, stream=None):
+    """Unchecked submission: (status, handle)."""
+    h = _P()
+    st = _lib.tq_batch_submit(ctx, queries.arr, queries.count, flags, _stream(stream), ctypes.byref(h))
+    return st, h.value
+
+
+def tq_batch_poll(batch: int) -> int:
+    d = _U32()
+    _check(_lib.tq_batch_poll(batch, ctypes.byref(d)), "tq_batch_poll")
+    return d.value
+
+
+def tq_batch_wait(batch: int) -> None:
+    _check(_lib.tq_batch_wait(batch), "tq_batch_wait")
+
+
+def tq_batch_records(batch: int, count: int):
+    arr = (TqQueryRecord * max(1, count))()
+    _check(_lib.tq_batch_records(batch, arr), "tq_batch_records")
+    return [(r.user_tag, r.status, r.done, r.t_start_ns, r.t_end_ns) for r in arr[:count]]
+
+
+def tq_batch_release(batch: int) -> None:
+    _check(_lib.tq_batch_release(batch), "tq_batch_release")
 
 
 class Context:

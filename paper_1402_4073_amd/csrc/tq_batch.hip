@@ -1,0 +1,487 @@
+// Batched queries: one persistent kernel serves many threshold / symmetric
+// queries of uneven N, r and theta.
+//
+// A batch is uploaded as one packed buffer (header, query descriptors, the
+// first work item of each query, and all pointer arrays).  The work of query
+// q is cut into items of `groups` column groups (64 words each); item sizes
+// grow as N shrinks so that every item streams about the same number of
+// bytes.  Waves pop items from one atomic counter in increasing order, find
+// the query of an item with a cursor that only moves forward, run the same
+// register-resident carry-save counter as the single-query kernel on each
+// column group and write the output words.  The wave that finishes a query's
+// last item writes the query's device timestamps and a done flag into
+// coherent pinned host memory, so the host sees completions without waiting
+// for the whole launch.
+//
+// Per context there are a few batch slots with fixed capacity (queries and
+// pointer entries).  A submission that finds no free slot is refused with
+// TQ_EBUSY: the memory a batch can hold in flight is bounded up front.  Each
+// slot owns a graph built once (copy of the packed buffer, a reset kernel,
+// the persistent kernel); a submission updates the copy size and replays it.
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "tq_csa.hpp"
+
+namespace tq {
+namespace {
+
+using namespace csa;
+
+struct BatchHeader {
+  uint32_t nq;
+  uint32_t total_items;
+  uint32_t next;         // work counter
+  uint32_t pad0;
+  uint64_t off_queries;  // byte offsets inside the packed buffer
+  uint64_t off_item_begin;
+  uint64_t off_ptrs;
+  uint64_t pad1[3];
+};
+
+struct BatchQuery {
+  uint64_t ptrs;        // device address of this query's pointer array
+  uint64_t out;
+  uint64_t nwords;
+  uint64_t tail_mask;
+  uint32_t n;
+  uint32_t K;
+  uint32_t groups;      // 64-word column groups per item
+  uint32_t items;
+  uint32_t item_begin;
+  uint32_t constant;    // 0: compute, 1: all ones, 2: all zeros
+  EpiParams epi;
+};
+
+struct BatchRecord {    // in pinned host memory, one per query
+  uint64_t t_start;
+  uint64_t t_end;
+  uint32_t done;
+  int32_t status;
+  uint64_t pad;
+};
+
+constexpr uint32_t kSlotQueries = 8192;
+constexpr uint64_t kSlotPtrs = 1u << 21;
+constexpr int kSlots = 4;
+constexpr int kBatchWavesPerCU = 24;
+
+__global__ void batch_reset_kernel(BatchHeader* hdr, uint32_t* qdone, uint32_t* qstarted) {
+  const uint32_t nq = hdr->nq;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nq; i += gridDim.x * blockDim.x) {
+    qdone[i] = 0;
+    qstarted[i] = 0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) hdr->next = 0;
+}
+
+template <int K>
+__device__ __forceinline__ void store_word(const BatchQuery& Q, uint64_t w, uint64_t v) {
+  uint64_t* out = reinterpret_cast<uint64_t*>(Q.out);
+  if (w < Q.nwords) out[w] = (w == Q.nwords - 1) ? (v & Q.tail_mask) : v;
+}
+
+// N >= 16: one column group (64 words) per wave, 16 inputs folded per step
+template <int K>
+__device__ __forceinline__ void run_group(const BatchQuery& Q, const uint64_t* const* ptrs, uint64_t base) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t w = base + lane;
+  Vec<1> r;
+  if (Q.constant) {
+    r.w[0] = Q.constant == 1 ? ~(uint64_t)0 : 0;
+  } else {
+    Vec<1> P[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) P[k].w[0] = 0;
+    if (base + 64 <= Q.nwords)
+      accumulate<K, 1, false>(P, ptrs, 0, Q.n, w, Q.nwords);
+    else
+      accumulate<K, 1, true>(P, ptrs, 0, Q.n, w, Q.nwords);
+    r = epilogue<K, 1>(P, Q.epi, Q.n, nullptr);
+  }
+  store_word<K>(Q, w, r.w[0]);
+}
+
+// N <= 15: four interleaved column groups per wave (lane l owns words
+// base + 64g + l), four inputs folded per step, so that a wave keeps as many
+// loads in flight as with larger N
+constexpr int kSmallGroups = 4;
+
+__device__ __forceinline__ void run_small(const BatchQuery& Q, const uint64_t* const* ptrs, uint64_t base) {
+  const int lane = threadIdx.x & 63;
+  Vec<kSmallGroups> r;
+  if (Q.constant) {
+#pragma unroll
+    for (int g = 0; g < kSmallGroups; ++g) r.w[g] = Q.constant == 1 ? ~(uint64_t)0 : 0;
+  } else {
+    Vec<kSmallGroups> P[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int g = 0; g < kSmallGroups; ++g) P[k].w[g] = 0;
+    for (uint32_t i = 0; i < Q.n; i += 4) {
+      Vec<kSmallGroups> x[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const bool live = i + u < Q.n;
+        const uint64_t* p = live ? ptrs[i + u] : nullptr;
+#pragma unroll
+        for (int g = 0; g < kSmallGroups; ++g) {
+          const uint64_t w = base + (uint64_t)g * 64 + lane;
+          x[u].w[g] = (live && w < Q.nwords) ? __builtin_nontemporal_load(p + w) : 0;
+        }
+      }
+      add_block_l<2, 4, kSmallGroups>(P, x);
+    }
+    r = epilogue<4, kSmallGroups>(P, Q.epi, Q.n, nullptr);
+  }
+#pragma unroll
+  for (int g = 0; g < kSmallGroups; ++g) store_word<4>(Q, base + (uint64_t)g * 64 + lane, r.w[g]);
+}
+
+__global__ __launch_bounds__(64) void batch_kernel(char* buf, uint32_t* qdone, uint32_t* qstarted,
+                                                  BatchRecord* rec) {
+  BatchHeader* hdr = reinterpret_cast<BatchHeader*>(buf);
+  const BatchQuery* qs = reinterpret_cast<const BatchQuery*>(buf + hdr->off_queries);
+  const uint32_t* item_begin = reinterpret_cast<const uint32_t*>(buf + hdr->off_item_begin);
+  const uint32_t nq = hdr->nq, total = hdr->total_items;
+  const int lane = threadIdx.x & 63;
+  uint32_t q = 0;
+  for (;;) {
+    uint32_t item = 0;
+    if (lane == 0) item = atomicAdd(&hdr->next, 1u);
+    item = __builtin_amdgcn_readfirstlane(__shfl(item, 0));
+    if (item >= total) break;
+    // items come in increasing order: move the cursor forward (binary search)
+    if (q + 1 < nq && item_begin[q + 1] <= item) {
+      uint32_t lo = q + 1, hi = nq - 1;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) / 2;
+        if (item_begin[mid] <= item) lo = mid; else hi = mid - 1;
+      }
+      q = lo;
+    }
+    const BatchQuery& Q = qs[q];
+    if (lane == 0 && atomicCAS(&qstarted[q], 0u, 1u) == 0u) rec[q].t_start = wall_clock64();
+    const uint64_t local = item - Q.item_begin;
+    const uint64_t* const* ptrs = reinterpret_cast<const uint64_t* const*>(Q.ptrs);
+    const uint32_t step = Q.K == 4 ? kSmallGroups : 1;
+    for (uint32_t g = 0; g < Q.groups; g += step) {
+      const uint64_t base = (local * Q.groups + g) * 64;
+      if (base >= Q.nwords) break;
+      switch (Q.K) {
+        case 4: run_small(Q, ptrs, base); break;
+        case 5: run_group<5>(Q, ptrs, base); break;
+        case 6: run_group<6>(Q, ptrs, base); break;
+        case 7: run_group<7>(Q, ptrs, base); break;
+        case 8: run_group<8>(Q, ptrs, base); break;
+        case 9: run_group<9>(Q, ptrs, base); break;
+        case 10: run_group<10>(Q, ptrs, base); break;
+        case 11: run_group<11>(Q, ptrs, base); break;
+        case 12: run_group<12>(Q, ptrs, base); break;
+        case 13: run_group<13>(Q, ptrs, base); break;
+        default: run_group<16>(Q, ptrs, base); break;
+      }
+    }
+    __threadfence();
+    if (lane == 0) {
+      const uint32_t prev = atomicAdd(&qdone[q], 1u);
+      if (prev + 1 == Q.items) {
+        rec[q].t_end = wall_clock64();
+        rec[q].status = 0;
+        __threadfence_system();
+        __hip_atomic_store(&rec[q].done, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+      }
+    }
+  }
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace
+
+struct BatchSlot {
+  bool in_use = false;
+  char* d_buf = nullptr;       // packed batch (device)
+  char* h_buf = nullptr;       // packed batch (pinned staging)
+  size_t cap_bytes = 0;
+  uint32_t* d_qdone = nullptr;
+  uint32_t* d_qstarted = nullptr;
+  BatchRecord* h_rec = nullptr;  // pinned, coherent, written by the GPU
+  BatchRecord* d_rec = nullptr;  // device view of h_rec
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipGraphNode_t copy_node = nullptr;
+  hipEvent_t done_ev = nullptr;
+};
+
+struct BatchState {
+  BatchSlot slots[kSlots];
+  int grid = 0;
+  double tick_ns = 10.0;
+};
+
+}  // namespace tq
+
+struct tq_batch {
+  tq_ctx* ctx;
+  int slot;
+  uint32_t nq;
+  std::vector<uint64_t> tags;
+};
+
+namespace tq {
+namespace {
+
+BatchState* batch_state(tq_ctx* ctx) {
+  if (!ctx->batch) {
+    BatchState* b = new (std::nothrow) BatchState();
+    if (!b) return nullptr;
+    b->grid = ctx->num_cus * kBatchWavesPerCU;
+    int rate_khz = 0;
+    if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, ctx->device) == hipSuccess && rate_khz > 0)
+      b->tick_ns = 1e6 / (double)rate_khz;
+    ctx->batch = b;
+  }
+  return static_cast<BatchState*>(ctx->batch);
+}
+
+tq_status slot_init(tq_ctx* ctx, BatchState* bs, BatchSlot& s) {
+  if (s.d_buf) return TQ_OK;
+  const size_t bytes = sizeof(BatchHeader) + kSlotQueries * (sizeof(BatchQuery) + 4) + kSlotPtrs * 8 + 4096;
+  hipError_t e;
+  if ((e = hipMalloc((void**)&s.d_buf, bytes)) != hipSuccess) return record_hip(ctx, e);
+  if ((e = hipHostMalloc((void**)&s.h_buf, bytes, hipHostMallocDefault)) != hipSuccess) return record_hip(ctx, e);
+  s.cap_bytes = bytes;
+  if ((e = hipMalloc((void**)&s.d_qdone, kSlotQueries * 8)) != hipSuccess) return record_hip(ctx, e);
+  s.d_qstarted = s.d_qdone + kSlotQueries;
+  if ((e = hipHostMalloc((void**)&s.h_rec, kSlotQueries * sizeof(BatchRecord),
+                         hipHostMallocMapped | hipHostMallocCoherent)) != hipSuccess)
+    return record_hip(ctx, e);
+  if ((e = hipHostGetDevicePointer((void**)&s.d_rec, s.h_rec, 0)) != hipSuccess) return record_hip(ctx, e);
+  if ((e = hipEventCreateWithFlags(&s.done_ev, hipEventDisableTiming)) != hipSuccess) return record_hip(ctx, e);
+  // graph: copy the packed buffer, reset the counters, run the persistent kernel
+  if ((e = hipGraphCreate(&s.graph, 0)) != hipSuccess) return record_hip(ctx, e);
+  if ((e = hipGraphAddMemcpyNode1D(&s.copy_node, s.graph, nullptr, 0, s.d_buf, s.h_buf, sizeof(BatchHeader),
+                                   hipMemcpyHostToDevice)) != hipSuccess)
+    return record_hip(ctx, e);
+  // kernel parameter values are copied when the node is created
+  BatchHeader* hdr_arg = reinterpret_cast<BatchHeader*>(s.d_buf);
+  uint32_t* qd = s.d_qdone;
+  uint32_t* qs = s.d_qstarted;
+  char* buf = s.d_buf;
+  BatchRecord* rec = s.d_rec;
+  void* rargs[3] = {&hdr_arg, &qd, &qs};
+  hipKernelNodeParams rp{};
+  rp.func = reinterpret_cast<void*>(batch_reset_kernel);
+  rp.gridDim = dim3(32);
+  rp.blockDim = dim3(256);
+  rp.sharedMemBytes = 0;
+  rp.kernelParams = rargs;
+  rp.extra = nullptr;
+  hipGraphNode_t reset_node, kernel_node;
+  if ((e = hipGraphAddKernelNode(&reset_node, s.graph, &s.copy_node, 1, &rp)) != hipSuccess) return record_hip(ctx, e);
+  void* kargs[4] = {&buf, &qd, &qs, &rec};
+  hipKernelNodeParams kp{};
+  kp.func = reinterpret_cast<void*>(batch_kernel);
+  kp.gridDim = dim3(bs->grid);
+  kp.blockDim = dim3(64);
+  kp.sharedMemBytes = 0;
+  kp.kernelParams = kargs;
+  kp.extra = nullptr;
+  if ((e = hipGraphAddKernelNode(&kernel_node, s.graph, &reset_node, 1, &kp)) != hipSuccess) return record_hip(ctx, e);
+  if ((e = hipGraphInstantiate(&s.exec, s.graph, nullptr, nullptr, 0)) != hipSuccess) return record_hip(ctx, e);
+  return TQ_OK;
+}
+
+}  // namespace
+
+void batch_destroy(tq_ctx* ctx) {
+  BatchState* bs = static_cast<BatchState*>(ctx->batch);
+  if (!bs) return;
+  for (auto& s : bs->slots) {
+    if (s.done_ev) hipEventSynchronize(s.done_ev);
+    if (s.exec) hipGraphExecDestroy(s.exec);
+    if (s.graph) hipGraphDestroy(s.graph);
+    if (s.done_ev) hipEventDestroy(s.done_ev);
+    if (s.d_buf) hipFree(s.d_buf);
+    if (s.h_buf) hipHostFree(s.h_buf);
+    if (s.d_qdone) hipFree(s.d_qdone);
+    if (s.h_rec) hipHostFree(s.h_rec);
+  }
+  delete bs;
+  ctx->batch = nullptr;
+}
+
+}  // namespace tq
+
+using namespace tq;
+
+extern "C" {
+
+tq_status tq_batch_submit(tq_ctx* ctx, const tq_query* queries, uint32_t count, uint32_t flags,
+                          hipStream_t stream, tq_batch** out) {
+  if (!ctx || !out || (count && !queries)) return TQ_EINVAL;
+  *out = nullptr;
+  if (count == 0 || count > kSlotQueries) return TQ_EINVAL;
+  BatchState* bs = batch_state(ctx);
+  if (!bs) return TQ_ENOMEM;
+  // validate and size
+  uint64_t nptrs = 0;
+  for (uint32_t i = 0; i < count; ++i) {
+    const tq_query& q = queries[i];
+    if (q.kind != TQ_QUERY_THRESHOLD && q.kind != TQ_QUERY_SYMMETRIC) return TQ_EINVAL;
+    if (q.n == 0 || q.n > TQ_MAX_INPUTS || !q.ptrs || !q.d_out || ((uintptr_t)q.d_out & 7)) return TQ_EINVAL;
+    if (q.kind == TQ_QUERY_SYMMETRIC && !q.h_truth) return TQ_EINVAL;
+    const uint64_t nw = words_for_bits(q.r_bits);
+    if (nw >= (1ull << 31)) return TQ_EINVAL;
+    for (uint32_t j = 0; j < q.n; ++j) {
+      const uintptr_t p = (uintptr_t)q.ptrs[j];
+      if (!p || (p & 7)) return TQ_EINVAL;
+      if (p < (uintptr_t)(q.d_out + nw) && (uintptr_t)q.d_out < p + nw * 8) return TQ_EINVAL;
+    }
+    nptrs += q.n;
+  }
+  if (nptrs > kSlotPtrs) return TQ_EINVAL;
+  int si = -1;
+  for (int k = 0; k < kSlots; ++k)
+    if (!bs->slots[k].in_use) { si = k; break; }
+  if (si < 0) return TQ_EBUSY;
+  BatchSlot& s = bs->slots[si];
+  tq_status st = slot_init(ctx, bs, s);
+  if (st != TQ_OK) return st;
+
+  // pack: header | queries | item_begin | pointer arrays
+  const size_t off_q = align_up(sizeof(BatchHeader), 256);
+  const size_t off_ib = align_up(off_q + (size_t)count * sizeof(BatchQuery), 256);
+  const size_t off_p = align_up(off_ib + (size_t)count * 4, 256);
+  const size_t used = off_p + nptrs * 8;
+  if (used > s.cap_bytes) return TQ_EINVAL;
+  BatchHeader* h = reinterpret_cast<BatchHeader*>(s.h_buf);
+  BatchQuery* qd = reinterpret_cast<BatchQuery*>(s.h_buf + off_q);
+  uint32_t* ib = reinterpret_cast<uint32_t*>(s.h_buf + off_ib);
+  uint64_t* pa = reinterpret_cast<uint64_t*>(s.h_buf + off_p);
+  uint64_t pcur = 0;
+  uint64_t items = 0;
+  tq_batch* b = new (std::nothrow) tq_batch();
+  if (!b) return TQ_ENOMEM;
+  b->ctx = ctx;
+  b->slot = si;
+  b->nq = count;
+  b->tags.resize(count);
+  for (uint32_t i = 0; i < count; ++i) {
+    const tq_query& q = queries[i];
+    const uint64_t nw = words_for_bits(q.r_bits);
+    SymPlan plan = q.kind == TQ_QUERY_THRESHOLD ? plan_threshold(q.n, q.theta) : plan_symmetric(q.n, q.h_truth);
+    if (!plan.constant && plan.epi.kind == EPI_TABLE) {
+      delete b;
+      return TQ_ENOTSUP;
+    }
+    BatchQuery& d = qd[i];
+    memset(&d, 0, sizeof(d));
+    d.ptrs = (uint64_t)(uintptr_t)(reinterpret_cast<uint64_t*>(s.d_buf + off_p) + pcur);
+    d.out = (uint64_t)(uintptr_t)q.d_out;
+    d.nwords = nw;
+    d.tail_mask = tail_mask_for(q.r_bits);
+    d.n = q.n;
+    d.K = (uint32_t)dense_planes_for(q.n);
+    // every item streams roughly the same number of bytes: ~4096 input words per lane
+    uint32_t groups = (4096 + q.n - 1) / q.n;
+    groups = std::max<uint32_t>(1, std::min<uint32_t>(64, groups));
+    if (dense_planes_for(q.n) == 4) groups = (groups + kSmallGroups - 1) / kSmallGroups * kSmallGroups;
+    const uint64_t ngroups = (nw + 63) / 64;
+    d.groups = groups;
+    d.items = (uint32_t)std::max<uint64_t>(1, (ngroups + groups - 1) / groups);
+    d.item_begin = (uint32_t)items;
+    d.constant = plan.constant ? (plan.const_word ? 1u : 2u) : 0u;
+    d.epi = plan.epi;
+    ib[i] = (uint32_t)items;
+    items += d.items;
+    memcpy(pa + pcur, q.ptrs, (size_t)q.n * 8);
+    pcur += q.n;
+    b->tags[i] = q.user_tag;
+    s.h_rec[i].t_start = 0;
+    s.h_rec[i].t_end = 0;
+    s.h_rec[i].status = 0;
+    s.h_rec[i].done = 0;
+  }
+  if (items >= 0xFFFFFFFFull) {
+    delete b;
+    return TQ_EINVAL;
+  }
+  memset(h, 0, sizeof(*h));
+  h->nq = count;
+  h->total_items = (uint32_t)items;
+  h->off_queries = off_q;
+  h->off_item_begin = off_ib;
+  h->off_ptrs = off_p;
+  hipError_t e;
+  if (flags & TQ_BATCH_NO_GRAPH) {
+    BatchHeader* dh = reinterpret_cast<BatchHeader*>(s.d_buf);
+    if ((e = hipMemcpyAsync(s.d_buf, s.h_buf, used, hipMemcpyHostToDevice, stream)) == hipSuccess) {
+      hipLaunchKernelGGL(batch_reset_kernel, dim3(32), dim3(256), 0, stream, dh, s.d_qdone, s.d_qstarted);
+      hipLaunchKernelGGL(batch_kernel, dim3(bs->grid), dim3(64), 0, stream, s.d_buf, s.d_qdone, s.d_qstarted,
+                         s.d_rec);
+      e = hipGetLastError();
+    }
+  } else {
+    e = hipGraphExecMemcpyNodeSetParams1D(s.exec, s.copy_node, s.d_buf, s.h_buf, used, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipGraphLaunch(s.exec, stream);
+  }
+  if (e == hipSuccess) e = hipEventRecord(s.done_ev, stream);
+  if (e != hipSuccess) {
+    delete b;
+    return record_hip(ctx, e);
+  }
+  s.in_use = true;
+  *out = b;
+  return TQ_OK;
+}
+
+tq_status tq_batch_poll(tq_batch* b, uint32_t* ndone) {
+  if (!b || !ndone) return TQ_EINVAL;
+  BatchState* bs = static_cast<BatchState*>(b->ctx->batch);
+  const BatchRecord* rec = bs->slots[b->slot].h_rec;
+  uint32_t d = 0;
+  for (uint32_t i = 0; i < b->nq; ++i)
+    d += __atomic_load_n(&rec[i].done, __ATOMIC_ACQUIRE) ? 1 : 0;
+  *ndone = d;
+  return TQ_OK;
+}
+
+tq_status tq_batch_wait(tq_batch* b) {
+  if (!b) return TQ_EINVAL;
+  BatchState* bs = static_cast<BatchState*>(b->ctx->batch);
+  return record_hip(b->ctx, hipEventSynchronize(bs->slots[b->slot].done_ev));
+}
+
+tq_status tq_batch_records(tq_batch* b, tq_query_record* out) {
+  if (!b || !out) return TQ_EINVAL;
+  BatchState* bs = static_cast<BatchState*>(b->ctx->batch);
+  const BatchRecord* rec = bs->slots[b->slot].h_rec;
+  for (uint32_t i = 0; i < b->nq; ++i) {
+    const uint32_t done = __atomic_load_n(&rec[i].done, __ATOMIC_ACQUIRE);
+    out[i].user_tag = b->tags[i];
+    out[i].done = done;
+    out[i].status = done ? rec[i].status : 0;
+    out[i].t_start_ns = (uint64_t)((double)rec[i].t_start * bs->tick_ns);
+    out[i].t_end_ns = done ? (uint64_t)((double)rec[i].t_end * bs->tick_ns) : 0;
+  }
+  return TQ_OK;
+}
+
+tq_status tq_batch_release(tq_batch* b) {
+  if (!b) return TQ_OK;
+  BatchState* bs = static_cast<BatchState*>(b->ctx->batch);
+  BatchSlot& s = bs->slots[b->slot];
+  hipError_t e = hipEventSynchronize(s.done_ev);
+  s.in_use = false;
+  tq_ctx* ctx = b->ctx;
+  delete b;
+  return record_hip(ctx, e);
+}
+
+}  // extern "C"

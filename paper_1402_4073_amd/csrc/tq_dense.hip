@@ -21,194 +21,12 @@
 // are the same for the whole grid, so the walk over them compiles to scalar
 // branches.  Symmetric functions use that comparator on interval ends, the
 // low plane for parity, or a per-bit table lookup for arbitrary truth tables.
-#include "tq_internal.h"
+#include "tq_csa.hpp"
 
 namespace tq {
 namespace {
 
-template <int WPL>
-struct Vec {
-  uint64_t w[WPL];
-};
-
-typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
-
-__device__ __forceinline__ uint32_t lo32(uint64_t x) { return (uint32_t)x; }
-__device__ __forceinline__ uint32_t hi32(uint64_t x) { return (uint32_t)(x >> 32); }
-__device__ __forceinline__ uint64_t join(uint32_t lo, uint32_t hi) {
-  return (uint64_t)lo | ((uint64_t)hi << 32);
-}
-
-// three-input XOR and majority, one v_bitop3_b32 per 32-bit half
-__device__ __forceinline__ uint64_t xor3(uint64_t a, uint64_t b, uint64_t c) {
-  return join(__builtin_amdgcn_bitop3_b32(lo32(a), lo32(b), lo32(c), 0x96),
-              __builtin_amdgcn_bitop3_b32(hi32(a), hi32(b), hi32(c), 0x96));
-}
-__device__ __forceinline__ uint64_t maj3(uint64_t a, uint64_t b, uint64_t c) {
-  return join(__builtin_amdgcn_bitop3_b32(lo32(a), lo32(b), lo32(c), 0xE8),
-              __builtin_amdgcn_bitop3_b32(hi32(a), hi32(b), hi32(c), 0xE8));
-}
-
-// full adder: h <- h ^ a ^ b, c <- majority(h, a, b)
-template <int WPL>
-__device__ __forceinline__ void csa(Vec<WPL>& h, const Vec<WPL>& a, const Vec<WPL>& b, Vec<WPL>& c) {
-#pragma unroll
-  for (int i = 0; i < WPL; ++i) {
-    const uint64_t hh = h.w[i];
-    c.w[i] = maj3(hh, a.w[i], b.w[i]);
-    h.w[i] = xor3(hh, a.w[i], b.w[i]);
-  }
-}
-
-// Fold 2^L inputs of weight 1 into planes 0..L-1; return the carry of weight 2^L.
-template <int L, int K, int WPL>
-__device__ __forceinline__ Vec<WPL> fold(Vec<WPL> (&P)[K], const Vec<WPL>* x) {
-  Vec<WPL> c;
-  if constexpr (L == 1) {
-    csa<WPL>(P[0], x[0], x[1], c);
-  } else {
-    const Vec<WPL> a = fold<L - 1, K, WPL>(P, x);
-    const Vec<WPL> b = fold<L - 1, K, WPL>(P, x + (1 << (L - 1)));
-    csa<WPL>(P[L - 1], a, b, c);
-  }
-  return c;
-}
-
-constexpr int kBlockLog = 4;
-constexpr int kBlock = 1 << kBlockLog;  // inputs folded per step
-
-// add 16 input vectors to the counter
-template <int K, int WPL>
-__device__ __forceinline__ void add_block(Vec<WPL> (&P)[K], const Vec<WPL>* x) {
-  Vec<WPL> c = fold<kBlockLog, K, WPL>(P, x);
-#pragma unroll
-  for (int k = kBlockLog; k < K; ++k) {
-#pragma unroll
-    for (int i = 0; i < WPL; ++i) {
-      const uint64_t t = P[k].w[i] & c.w[i];
-      P[k].w[i] ^= c.w[i];
-      c.w[i] = t;
-    }
-  }
-}
-
-template <int WPL, bool Guard>
-__device__ __forceinline__ Vec<WPL> load_cols(const uint64_t* __restrict__ p, uint64_t w,
-                                             uint64_t nwords) {
-  Vec<WPL> v;
-  if constexpr (!Guard) {
-    if constexpr (WPL == 2) {
-      const u64x2 t = __builtin_nontemporal_load(reinterpret_cast<const u64x2*>(p + w));
-      v.w[0] = t[0];
-      v.w[1] = t[1];
-    } else {
-      v.w[0] = __builtin_nontemporal_load(p + w);
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < WPL; ++i) v.w[i] = (w + i < nwords) ? p[w + i] : 0;
-  }
-  return v;
-}
-
-// stream inputs [i0, i1) into the counter
-template <int K, int WPL, bool Guard>
-__device__ __forceinline__ void accumulate(Vec<WPL> (&P)[K], const uint64_t* const* __restrict__ ptrs,
-                                           uint32_t i0, uint32_t i1, uint64_t w, uint64_t nwords) {
-  uint32_t i = i0;
-  for (; i + kBlock <= i1; i += kBlock) {
-    Vec<WPL> x[kBlock];
-#pragma unroll
-    for (int u = 0; u < kBlock; ++u) x[u] = load_cols<WPL, Guard>(ptrs[i + u], w, nwords);
-    add_block<K, WPL>(P, x);
-  }
-  if (i < i1) {
-    Vec<WPL> x[kBlock];
-#pragma unroll
-    for (int u = 0; u < kBlock; ++u) {
-      if (i + u < i1) {
-        x[u] = load_cols<WPL, Guard>(ptrs[i + u], w, nwords);
-      } else {
-#pragma unroll
-        for (int q = 0; q < WPL; ++q) x[u].w[q] = 0;
-      }
-    }
-    add_block<K, WPL>(P, x);
-  }
-}
-
-// count > a, for a < 2^K (a is grid-uniform)
-template <int K, int WPL>
-__device__ __forceinline__ Vec<WPL> greater_than(const Vec<WPL> (&P)[K], uint32_t a) {
-  Vec<WPL> pm, r;
-#pragma unroll
-  for (int i = 0; i < WPL; ++i) { pm.w[i] = ~(uint64_t)0; r.w[i] = 0; }
-#pragma unroll
-  for (int j = K - 1; j >= 0; --j) {
-    if ((a >> j) & 1u) {
-#pragma unroll
-      for (int i = 0; i < WPL; ++i) pm.w[i] &= P[j].w[i];
-    } else {
-#pragma unroll
-      for (int i = 0; i < WPL; ++i) r.w[i] |= pm.w[i] & P[j].w[i];
-    }
-  }
-  return r;
-}
-
-// count >= x for any x (x == 0: everything; x > n: nothing)
-template <int K, int WPL>
-__device__ __forceinline__ Vec<WPL> at_least(const Vec<WPL> (&P)[K], uint32_t x, uint32_t n) {
-  Vec<WPL> r;
-  if (x == 0) {
-#pragma unroll
-    for (int i = 0; i < WPL; ++i) r.w[i] = ~(uint64_t)0;
-  } else if (x > n) {
-#pragma unroll
-    for (int i = 0; i < WPL; ++i) r.w[i] = 0;
-  } else {
-    r = greater_than<K, WPL>(P, x - 1);
-  }
-  return r;
-}
-
-template <int K, int WPL>
-__device__ __forceinline__ Vec<WPL> epilogue(const Vec<WPL> (&P)[K], const EpiParams& e, uint32_t n,
-                                            const uint32_t* lds_table) {
-  Vec<WPL> r;
-  if (e.kind == EPI_THRESH) {
-    r = at_least<K, WPL>(P, e.theta, n);
-  } else if (e.kind == EPI_PARITY) {
-    r = P[0];
-  } else if (e.kind == EPI_INTERVALS) {
-#pragma unroll
-    for (int i = 0; i < WPL; ++i) r.w[i] = 0;
-    for (int t = 0; t < e.nint; ++t) {
-      const Vec<WPL> a = at_least<K, WPL>(P, e.lo[t], n);
-      const Vec<WPL> b = at_least<K, WPL>(P, e.hi1[t], n);
-#pragma unroll
-      for (int i = 0; i < WPL; ++i) r.w[i] |= a.w[i] & ~b.w[i];
-    }
-  } else {
-    // generic truth table: rebuild each position's count from the planes
-#pragma unroll
-    for (int i = 0; i < WPL; ++i) {
-      uint64_t o = 0;
-      for (int b = 0; b < 64; ++b) {
-        uint32_t c = 0;
-#pragma unroll
-        for (int k = 0; k < K; ++k) c |= (uint32_t)((P[k].w[i] >> b) & 1) << k;
-        o |= (uint64_t)((lds_table[c >> 5] >> (c & 31)) & 1u) << b;
-      }
-      r.w[i] = o;
-    }
-  }
-  if (e.invert) {
-#pragma unroll
-    for (int i = 0; i < WPL; ++i) r.w[i] = ~r.w[i];
-  }
-  return r;
-}
+using namespace csa;
 
 // K: counter planes, WPL: words per lane, S: waves that split the inputs of
 // one column group, G: column groups per workgroup.  Small workgroups (one

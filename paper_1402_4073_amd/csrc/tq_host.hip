@@ -265,6 +265,7 @@ tq_status tq_destroy(tq_ctx* ctx) {
   if (!ctx) return TQ_OK;
   hipSetDevice(ctx->device);
   hipDeviceSynchronize();
+  batch_destroy(ctx);
   for (auto& b : ctx->blobs) blob_release(b);
   if (ctx->ws) hipFree(ctx->ws);
   if (ctx->d_status) hipFree(ctx->d_status);

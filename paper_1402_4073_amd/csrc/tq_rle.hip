@@ -169,15 +169,24 @@ __global__ __launch_bounds__(kTileThreads) void rle_tile_kernel(
   __syncthreads();
 
   // 2. prefix sum: kd[c] = k + 65536 * d for column c
+  int undecided = 0;
   {
     const int32_t v = tid < kTile ? kd[tid] : 0;
     const int32_t ex = block_exclusive_scan<int32_t, kTileThreads / 64>(v, wave_tot, &total);
     if (tid < kTile) kd[tid] = ex + v;
+    if (tid < (int)(t1 - t0)) {
+      int k, d;
+      unpack_kd(ex + v, k, d);
+      const int tp = (int)theta - k;
+      // literal words matter where the column is undecided and has some
+      undecided = (tp >= 1 && tp <= d + (int)n_dense && d > 0) ? 1 : 0;
+    }
   }
-  __syncthreads();
+  // a tile whose columns the fills alone decide needs no literal word
+  undecided = __syncthreads_or(undecided);
 
   // 3. literal words of undecided columns into the per-column LDS counters
-  for (uint32_t j = tid; j < n_rle; j += kTileThreads) {
+  for (uint32_t j = tid; undecided && j < n_rle; j += kTileThreads) {
     const RleDesc dsc = descs[j];
     Walk wk;
     if (!seek(dsc, tile, t0, wk)) continue;
