@@ -292,9 +292,49 @@ class TqQueryRecord(ctypes.Structure):
                 ("t_start_ns", _U64), ("t_end_ns", _U64)]
 
 
+class PreparedQuery:
+    """A query with its host pointer array already built (marshalled once,
+    reusable across submissions)."""
+    __slots__ = ("ptrs", "n", "r_bits", "theta", "out", "tag", "truth")
+
+    def __init__(self, inputs, r_bits, out, theta=None, truth=None, tag=0):
+        self.ptrs = ptr_array(inputs)
+        self.n = len(inputs)
+        self.r_bits = int(r_bits)
+        self.out = _ptr(out)
+        self.theta = theta
+        self.truth = _u64_host(truth_words(truth)) if truth is not None else None
+        self.tag = int(tag)
+
+
+def tq_threshold_prepared(ctx: int, pq: "PreparedQuery", stream=None) -> None:
+    _check(_lib.tq_threshold(ctx, pq.ptrs, pq.n, pq.r_bits, pq.theta, pq.out, _stream(stream)), "tq_threshold")
+
+
 class BatchQueries:
     """Host-side tq_query array plus the pointer arrays and truth tables it
     points to (kept alive until submission has copied them)."""
+
+    @classmethod
+    def from_prepared(cls, prepared):
+        self = cls.__new__(cls)
+        self.keep = list(prepared)
+        self.arr = (TqQuery * max(1, len(prepared)))()
+        for i, pq in enumerate(prepared):
+            q = self.arr[i]
+            q.n = pq.n
+            q.ptrs = ctypes.addressof(pq.ptrs)
+            q.r_bits = pq.r_bits
+            q.d_out = pq.out
+            q.user_tag = pq.tag
+            if pq.truth is not None:
+                q.kind = TQ_QUERY_SYMMETRIC
+                q.h_truth = ctypes.addressof(pq.truth)
+            else:
+                q.kind = TQ_QUERY_THRESHOLD
+                q.theta = pq.theta
+        self.count = len(prepared)
+        return self
 
     def __init__(self, specs):
         """specs: list of dicts with keys inputs, r_bits, out, and theta or truth, optional tag."""
@@ -345,10 +385,16 @@ def tq_batch_wait(batch: int) -> None:
     _check(_lib.tq_batch_wait(batch), "tq_batch_wait")
 
 
+RECORD_DTYPE = [("user_tag", "<u8"), ("status", "<i4"), ("done", "<u4"), ("t_start_ns", "<u8"),
+                ("t_end_ns", "<u8")]
+
+
 def tq_batch_records(batch: int, count: int):
+    """Per-query records as a numpy structured array (fields of tq_query_record)."""
+    import numpy as np
     arr = (TqQueryRecord * max(1, count))()
     _check(_lib.tq_batch_records(batch, arr), "tq_batch_records")
-    return [(r.user_tag, r.status, r.done, r.t_start_ns, r.t_end_ns) for r in arr[:count]]
+    return np.frombuffer(arr, dtype=np.dtype(RECORD_DTYPE), count=count).copy()
 
 
 def tq_batch_release(batch: int) -> None:

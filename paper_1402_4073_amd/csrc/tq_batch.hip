@@ -67,26 +67,47 @@ struct BatchRecord {    // in pinned host memory, one per query
 constexpr uint32_t kSlotQueries = 8192;
 constexpr uint64_t kSlotPtrs = 1u << 21;
 constexpr int kSlots = 4;
-constexpr int kBatchWavesPerCU = 24;
+constexpr int kBatchWavesPerCU = 16;
+constexpr uint64_t kMinItemWork = 16;
 
-__global__ void batch_reset_kernel(BatchHeader* hdr, uint32_t* qdone, uint32_t* qstarted) {
+// Completion of a query is counted on kShards sub-counters (item i of the
+// query counts on shard i mod kShards) so that the items of one query, which
+// tend to finish together, do not all hit one address; the item that fills a
+// shard bumps the query's top counter, and the item that fills the last shard
+// completes the query.
+constexpr uint32_t kShards = 64;
+
+__global__ void batch_reset_kernel(BatchHeader* hdr, uint32_t* qshard, uint32_t* qtop) {
   const uint32_t nq = hdr->nq;
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nq; i += gridDim.x * blockDim.x) {
-    qdone[i] = 0;
-    qstarted[i] = 0;
-  }
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nq * kShards; i += gridDim.x * blockDim.x)
+    qshard[i] = 0;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nq; i += gridDim.x * blockDim.x) qtop[i] = 0;
   if (blockIdx.x == 0 && threadIdx.x == 0) hdr->next = 0;
 }
 
+// The packed batch is not written while the kernel runs (only the work
+// counter in its header is), so descriptors, item starts and pointer arrays
+// are read through the constant address space: uniform reads become scalar
+// loads instead of vector loads of one address.
+#define TQ_CONST __attribute__((address_space(4)))
+typedef const uint64_t* const TQ_CONST* CPtrArr;   // constant array of input pointers
+
+template <typename T>
+__device__ __forceinline__ const T TQ_CONST* as_const(const void* p) {
+  return (const T TQ_CONST*)(p);
+}
+
+typedef const BatchQuery TQ_CONST CBatchQuery;
+
 template <int K>
-__device__ __forceinline__ void store_word(const BatchQuery& Q, uint64_t w, uint64_t v) {
+__device__ __forceinline__ void store_word(CBatchQuery& Q, uint64_t w, uint64_t v) {
   uint64_t* out = reinterpret_cast<uint64_t*>(Q.out);
   if (w < Q.nwords) out[w] = (w == Q.nwords - 1) ? (v & Q.tail_mask) : v;
 }
 
 // N >= 16: one column group (64 words) per wave, 16 inputs folded per step
 template <int K>
-__device__ __forceinline__ void run_group(const BatchQuery& Q, const uint64_t* const* ptrs, uint64_t base) {
+__device__ __forceinline__ void run_group(CBatchQuery& Q, CPtrArr ptrs, uint64_t base) {
   const int lane = threadIdx.x & 63;
   const uint64_t w = base + lane;
   Vec<1> r;
@@ -110,7 +131,7 @@ __device__ __forceinline__ void run_group(const BatchQuery& Q, const uint64_t* c
 // loads in flight as with larger N
 constexpr int kSmallGroups = 4;
 
-__device__ __forceinline__ void run_small(const BatchQuery& Q, const uint64_t* const* ptrs, uint64_t base) {
+__device__ __forceinline__ void run_small(CBatchQuery& Q, CPtrArr ptrs, uint64_t base) {
   const int lane = threadIdx.x & 63;
   Vec<kSmallGroups> r;
   if (Q.constant) {
@@ -142,60 +163,97 @@ __device__ __forceinline__ void run_small(const BatchQuery& Q, const uint64_t* c
   for (int g = 0; g < kSmallGroups; ++g) store_word<4>(Q, base + (uint64_t)g * 64 + lane, r.w[g]);
 }
 
-__global__ __launch_bounds__(64) void batch_kernel(char* buf, uint32_t* qdone, uint32_t* qstarted,
-                                                  BatchRecord* rec) {
+// A workgroup of kItemWaves waves takes kItemWaves consecutive items per
+// round (one per wave).  Publishing a finished item needs a device-scope
+// release, which on this part writes back the XCD's L2; doing it once per
+// round for all the workgroup's items, from one instruction of wave 0, costs
+// one write-back instead of one per wave.  The barrier orders every wave's
+// output stores before that release.
+constexpr int kItemWaves = 8;
+
+__global__ __launch_bounds__(64 * kItemWaves) void batch_kernel(char* buf, uint32_t* qshard, uint32_t* qtop,
+                                                               BatchRecord* rec) {
+  __shared__ uint32_t s_q[kItemWaves];
+  __shared__ uint32_t s_local[kItemWaves];
+  __shared__ uint32_t s_next;
   BatchHeader* hdr = reinterpret_cast<BatchHeader*>(buf);
-  const BatchQuery* qs = reinterpret_cast<const BatchQuery*>(buf + hdr->off_queries);
-  const uint32_t* item_begin = reinterpret_cast<const uint32_t*>(buf + hdr->off_item_begin);
-  const uint32_t nq = hdr->nq, total = hdr->total_items;
+  const BatchHeader TQ_CONST* chdr = as_const<BatchHeader>(buf);
+  const BatchQuery TQ_CONST* qs = as_const<BatchQuery>(buf + chdr->off_queries);
+  const uint32_t TQ_CONST* item_begin = as_const<uint32_t>(buf + chdr->off_item_begin);
+  const uint32_t nq = chdr->nq, total = chdr->total_items;
+  const uint32_t nrounds = (total + kItemWaves - 1) / kItemWaves;
   const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   uint32_t q = 0;
-  for (;;) {
-    uint32_t item = 0;
-    if (lane == 0) item = atomicAdd(&hdr->next, 1u);
-    item = __builtin_amdgcn_readfirstlane(__shfl(item, 0));
-    if (item >= total) break;
-    // items come in increasing order: move the cursor forward (binary search)
-    if (q + 1 < nq && item_begin[q + 1] <= item) {
-      uint32_t lo = q + 1, hi = nq - 1;
-      while (lo < hi) {
-        const uint32_t mid = (lo + hi + 1) / 2;
-        if (item_begin[mid] <= item) lo = mid; else hi = mid - 1;
+  // the first round of every workgroup is its own index; later ones come from the counter
+  uint32_t round = blockIdx.x;
+  while (round < nrounds) {
+    const uint32_t item = round * kItemWaves + wave;
+    uint32_t my_q = 0xFFFFFFFFu, my_local = 0;
+    if (item < total) {
+      // items of a wave come in increasing order: move the cursor forward
+      if (q + 1 < nq && item_begin[q + 1] <= item) {
+        uint32_t lo = q + 1, hi = nq - 1;
+        while (lo < hi) {
+          const uint32_t mid = (lo + hi + 1) / 2;
+          if (item_begin[mid] <= item) lo = mid; else hi = mid - 1;
+        }
+        q = lo;
       }
-      q = lo;
-    }
-    const BatchQuery& Q = qs[q];
-    if (lane == 0 && atomicCAS(&qstarted[q], 0u, 1u) == 0u) rec[q].t_start = wall_clock64();
-    const uint64_t local = item - Q.item_begin;
-    const uint64_t* const* ptrs = reinterpret_cast<const uint64_t* const*>(Q.ptrs);
-    const uint32_t step = Q.K == 4 ? kSmallGroups : 1;
-    for (uint32_t g = 0; g < Q.groups; g += step) {
-      const uint64_t base = (local * Q.groups + g) * 64;
-      if (base >= Q.nwords) break;
-      switch (Q.K) {
-        case 4: run_small(Q, ptrs, base); break;
-        case 5: run_group<5>(Q, ptrs, base); break;
-        case 6: run_group<6>(Q, ptrs, base); break;
-        case 7: run_group<7>(Q, ptrs, base); break;
-        case 8: run_group<8>(Q, ptrs, base); break;
-        case 9: run_group<9>(Q, ptrs, base); break;
-        case 10: run_group<10>(Q, ptrs, base); break;
-        case 11: run_group<11>(Q, ptrs, base); break;
-        case 12: run_group<12>(Q, ptrs, base); break;
-        case 13: run_group<13>(Q, ptrs, base); break;
-        default: run_group<16>(Q, ptrs, base); break;
+      CBatchQuery& Q = qs[q];
+      const uint64_t local = item - Q.item_begin;
+      if (lane == 0 && local == 0) rec[q].t_start = wall_clock64();
+      CPtrArr ptrs = as_const<const uint64_t*>(reinterpret_cast<const void*>(Q.ptrs));
+      const uint32_t step = Q.K == 4 ? kSmallGroups : 1;
+      for (uint32_t g = 0; g < Q.groups; g += step) {
+        const uint64_t base = (local * Q.groups + g) * 64;
+        if (base >= Q.nwords) break;
+        switch (Q.K) {
+          case 4: run_small(Q, ptrs, base); break;
+          case 5: run_group<5>(Q, ptrs, base); break;
+          case 6: run_group<6>(Q, ptrs, base); break;
+          case 7: run_group<7>(Q, ptrs, base); break;
+          case 8: run_group<8>(Q, ptrs, base); break;
+          case 9: run_group<9>(Q, ptrs, base); break;
+          case 10: run_group<10>(Q, ptrs, base); break;
+          case 11: run_group<11>(Q, ptrs, base); break;
+          case 12: run_group<12>(Q, ptrs, base); break;
+          case 13: run_group<13>(Q, ptrs, base); break;
+          default: run_group<16>(Q, ptrs, base); break;
+        }
       }
+      my_q = q;
+      my_local = (uint32_t)local;
     }
-    __threadfence();
     if (lane == 0) {
-      const uint32_t prev = atomicAdd(&qdone[q], 1u);
-      if (prev + 1 == Q.items) {
-        rec[q].t_end = wall_clock64();
-        rec[q].status = 0;
-        __threadfence_system();
-        __hip_atomic_store(&rec[q].done, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-      }
+      s_q[wave] = my_q;
+      s_local[wave] = my_local;
     }
+    __syncthreads();
+    if (wave == 0) {
+      if (lane < kItemWaves && s_q[lane] != 0xFFFFFFFFu) {
+        const uint32_t qq = s_q[lane];
+        const uint32_t items = qs[qq].items;
+        const uint32_t shard = s_local[lane] % kShards;
+        const uint32_t nshards = items < kShards ? items : kShards;
+        const uint32_t shard_items = (items - shard + kShards - 1) / kShards;
+        bool last = __hip_atomic_fetch_add(&qshard[(uint64_t)qq * kShards + shard], 1u, __ATOMIC_RELEASE,
+                                           __HIP_MEMORY_SCOPE_AGENT) + 1 == shard_items;
+        if (last) {
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          last = __hip_atomic_fetch_add(&qtop[qq], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) + 1 == nshards;
+        }
+        if (last) {
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          rec[qq].t_end = wall_clock64();
+          rec[qq].status = 0;
+          __hip_atomic_store(&rec[qq].done, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+      }
+      if (lane == 0) s_next = nrounds > gridDim.x ? gridDim.x + atomicAdd(&hdr->next, 1u) : nrounds;
+    }
+    __syncthreads();
+    round = s_next;
   }
 }
 
@@ -208,8 +266,8 @@ struct BatchSlot {
   char* d_buf = nullptr;       // packed batch (device)
   char* h_buf = nullptr;       // packed batch (pinned staging)
   size_t cap_bytes = 0;
-  uint32_t* d_qdone = nullptr;
-  uint32_t* d_qstarted = nullptr;
+  uint32_t* d_qdone = nullptr;     // per query: kShards completion sub-counters
+  uint32_t* d_qstarted = nullptr;  // per query: completed shards
   BatchRecord* h_rec = nullptr;  // pinned, coherent, written by the GPU
   BatchRecord* d_rec = nullptr;  // device view of h_rec
   hipGraph_t graph = nullptr;
@@ -240,7 +298,7 @@ BatchState* batch_state(tq_ctx* ctx) {
   if (!ctx->batch) {
     BatchState* b = new (std::nothrow) BatchState();
     if (!b) return nullptr;
-    b->grid = ctx->num_cus * kBatchWavesPerCU;
+    b->grid = ctx->num_cus * kBatchWavesPerCU / kItemWaves;   // workgroups of kItemWaves waves
     int rate_khz = 0;
     if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, ctx->device) == hipSuccess && rate_khz > 0)
       b->tick_ns = 1e6 / (double)rate_khz;
@@ -256,8 +314,9 @@ tq_status slot_init(tq_ctx* ctx, BatchState* bs, BatchSlot& s) {
   if ((e = hipMalloc((void**)&s.d_buf, bytes)) != hipSuccess) return record_hip(ctx, e);
   if ((e = hipHostMalloc((void**)&s.h_buf, bytes, hipHostMallocDefault)) != hipSuccess) return record_hip(ctx, e);
   s.cap_bytes = bytes;
-  if ((e = hipMalloc((void**)&s.d_qdone, kSlotQueries * 8)) != hipSuccess) return record_hip(ctx, e);
-  s.d_qstarted = s.d_qdone + kSlotQueries;
+  if ((e = hipMalloc((void**)&s.d_qdone, (size_t)kSlotQueries * (kShards + 1) * 4)) != hipSuccess)
+    return record_hip(ctx, e);
+  s.d_qstarted = s.d_qdone + (size_t)kSlotQueries * kShards;
   if ((e = hipHostMalloc((void**)&s.h_rec, kSlotQueries * sizeof(BatchRecord),
                          hipHostMallocMapped | hipHostMallocCoherent)) != hipSuccess)
     return record_hip(ctx, e);
@@ -288,7 +347,7 @@ tq_status slot_init(tq_ctx* ctx, BatchState* bs, BatchSlot& s) {
   hipKernelNodeParams kp{};
   kp.func = reinterpret_cast<void*>(batch_kernel);
   kp.gridDim = dim3(bs->grid);
-  kp.blockDim = dim3(64);
+  kp.blockDim = dim3(64 * kItemWaves);
   kp.sharedMemBytes = 0;
   kp.kernelParams = kargs;
   kp.extra = nullptr;
@@ -366,6 +425,15 @@ tq_status tq_batch_submit(tq_ctx* ctx, const tq_query* queries, uint32_t count, 
   uint64_t* pa = reinterpret_cast<uint64_t*>(s.h_buf + off_p);
   uint64_t pcur = 0;
   uint64_t items = 0;
+  // Item size: enough items to give every wave of the grid several, but no
+  // item smaller than kMinItemWork group-inputs (64 words x 1 input each).
+  // A lone query is spread over the whole chip; a large batch gets items of
+  // up to 64 column groups, which keeps the work counter cold.
+  uint64_t work = 0;
+  for (uint32_t i = 0; i < count; ++i)
+    work += ((words_for_bits(queries[i].r_bits) + 63) / 64) * (uint64_t)queries[i].n;
+  const uint64_t target_items = (uint64_t)bs->grid * kItemWaves * 4;
+  const uint64_t item_work = std::max<uint64_t>(kMinItemWork, (work + target_items - 1) / target_items);
   tq_batch* b = new (std::nothrow) tq_batch();
   if (!b) return TQ_ENOMEM;
   b->ctx = ctx;
@@ -388,9 +456,9 @@ tq_status tq_batch_submit(tq_ctx* ctx, const tq_query* queries, uint32_t count, 
     d.tail_mask = tail_mask_for(q.r_bits);
     d.n = q.n;
     d.K = (uint32_t)dense_planes_for(q.n);
-    // every item streams roughly the same number of bytes: ~4096 input words per lane
-    uint32_t groups = (4096 + q.n - 1) / q.n;
-    groups = std::max<uint32_t>(1, std::min<uint32_t>(64, groups));
+    // every item streams roughly the same number of bytes
+    uint64_t g64 = (item_work + q.n - 1) / q.n;
+    uint32_t groups = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(64, g64));
     if (dense_planes_for(q.n) == 4) groups = (groups + kSmallGroups - 1) / kSmallGroups * kSmallGroups;
     const uint64_t ngroups = (nw + 63) / 64;
     d.groups = groups;
@@ -423,8 +491,8 @@ tq_status tq_batch_submit(tq_ctx* ctx, const tq_query* queries, uint32_t count, 
     BatchHeader* dh = reinterpret_cast<BatchHeader*>(s.d_buf);
     if ((e = hipMemcpyAsync(s.d_buf, s.h_buf, used, hipMemcpyHostToDevice, stream)) == hipSuccess) {
       hipLaunchKernelGGL(batch_reset_kernel, dim3(32), dim3(256), 0, stream, dh, s.d_qdone, s.d_qstarted);
-      hipLaunchKernelGGL(batch_kernel, dim3(bs->grid), dim3(64), 0, stream, s.d_buf, s.d_qdone, s.d_qstarted,
-                         s.d_rec);
+      hipLaunchKernelGGL(batch_kernel, dim3(bs->grid), dim3(64 * kItemWaves), 0, stream, s.d_buf, s.d_qdone,
+                         s.d_qstarted, s.d_rec);
       e = hipGetLastError();
     }
   } else {

@@ -99,9 +99,10 @@ __device__ __forceinline__ Vec<WPL> load_cols(const uint64_t* __restrict__ p, ui
   return v;
 }
 
-// stream inputs [i0, i1) into the counter
-template <int K, int WPL, bool Guard>
-__device__ __forceinline__ void accumulate(Vec<WPL> (&P)[K], const uint64_t* const* __restrict__ ptrs,
+// stream inputs [i0, i1) into the counter; PtrArr is any indexable array of
+// input pointers (a generic pointer, or one in the constant address space)
+template <int K, int WPL, bool Guard, typename PtrArr>
+__device__ __forceinline__ void accumulate(Vec<WPL> (&P)[K], PtrArr ptrs,
                                            uint32_t i0, uint32_t i1, uint64_t w, uint64_t nwords) {
   uint32_t i = i0;
   for (; i + kBlock <= i1; i += kBlock) {
@@ -160,8 +161,10 @@ __device__ __forceinline__ Vec<WPL> at_least(const Vec<WPL> (&P)[K], uint32_t x,
   return r;
 }
 
-template <int K, int WPL>
-__device__ __forceinline__ Vec<WPL> epilogue(const Vec<WPL> (&P)[K], const EpiParams& e, uint32_t n,
+// EPT: EpiParams, possibly qualified with an address space (kernel argument
+// or constant memory)
+template <int K, int WPL, typename EPT>
+__device__ __forceinline__ Vec<WPL> epilogue(const Vec<WPL> (&P)[K], EPT& e, uint32_t n,
                                             const uint32_t* lds_table) {
   Vec<WPL> r;
   if (e.kind == EPI_THRESH) {
