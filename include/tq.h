@@ -260,6 +260,93 @@ tq_status tq_batch_records(tq_batch* batch, tq_query_record* out);
 /* Wait for the batch, free its slot and the handle. */
 tq_status tq_batch_release(tq_batch* batch);
 
+/* ------------------------------------------------------------------------
+ * Kernel variants and the learned selector.
+ *
+ * Which threshold algorithm is fastest depends on N, T, the density and the
+ * run structure of the inputs (sections 5.7-5.10 and 6).  Four GPU variants
+ * compute the same bits (sections 2.3, 4.1, 4.2, 4.4):
+ *   TQ_VARIANT_CSA      carry-save vertical counter over dense words
+ *   TQ_VARIANT_COUNTER  per-position counters over dense words (ScanCount)
+ *   TQ_VARIANT_RLE      run-length tile merge over compressed inputs (RBMrg cases)
+ *   TQ_VARIANT_HYBRID   each input read in its smaller form
+ * A registered bitmap carries either or both forms plus its cardinality and
+ * run count; a small network (8 -> 64 -> 64 -> 4, ReLU, fp32) maps eight
+ * features of that metadata to predicted log run times of the variants.
+ * ---------------------------------------------------------------------- */
+#define TQ_SEL_FEATURES 8
+#define TQ_SEL_HIDDEN 64
+#define TQ_SEL_VARIANTS 4
+/* W1[64][8] b1[64] W2[64][64] b2[64] W3[4][64] b3[4], row-major (out x in) */
+#define TQ_SEL_PARAMS 4996
+
+typedef enum tq_variant {
+  TQ_VARIANT_CSA = 0,
+  TQ_VARIANT_COUNTER = 1,
+  TQ_VARIANT_RLE = 2,
+  TQ_VARIANT_HYBRID = 3
+} tq_variant;
+
+typedef struct tq_bitmap {
+  const uint64_t* dense;  /* device words, or NULL when only the compressed form exists */
+  tq_rle rle;             /* compressed form; rle.words NULL when absent */
+  uint64_t ones;          /* registered cardinality (positions < r that are set) */
+  uint64_t runs;          /* registered number of runs of equal bits in [0, r) */
+} tq_bitmap;
+
+/* Flags of tq_threshold_auto and bits of its *chosen report. */
+#define TQ_AUTO_FALLBACK 1u            /* time every variant when the prediction is uncertain */
+#define TQ_AUTO_CHOSE_BY_TIMING 0x100u /* set in *chosen when the fallback decided */
+
+/* Cardinality and run count of a dense bitmap (metadata registered with it,
+ * section 2.1: RunCount).  Both results are device uint64. */
+tq_status tq_bitmap_stats(tq_ctx* ctx, const uint64_t* d_dense, uint64_t r_bits, uint64_t* d_ones,
+                          uint64_t* d_runs, hipStream_t stream);
+
+/* The eight selector features of a query, from metadata only (host):
+ * log2 N, theta/N, log10 mean density, log10 mean ones-run length, standard
+ * deviation of log10 density, log2 r, log2 compression ratio, and
+ * log2(theta / (1 + expected count)). */
+tq_status tq_query_features(const tq_bitmap* inputs, uint32_t n, uint64_t r_bits, uint32_t theta, float* out);
+
+/* Threshold query run by the given variant (dense output, semantics of
+ * tq_threshold).  TQ_EINVAL if an input lacks the form the variant reads. */
+tq_status tq_threshold_variant(tq_ctx* ctx, const tq_bitmap* inputs, uint32_t n, uint64_t r_bits,
+                               uint32_t theta, uint32_t variant, uint64_t* d_out, hipStream_t stream);
+
+uint64_t tq_selector_param_count(void);
+
+/* Install trained weights (TQ_SEL_PARAMS floats, host), the feature
+ * normalisation (mean, std) and the feature range seen in training (lo, hi),
+ * and the decision margin in predicted log time below which a prediction
+ * counts as uncertain. */
+tq_status tq_selector_set(tq_ctx* ctx, const float* params, const float* feat_mean, const float* feat_std,
+                          const float* feat_lo, const float* feat_hi, float margin);
+
+/* Host inference: predicted log run times of the four variants. */
+tq_status tq_selector_predict(tq_ctx* ctx, const float* features, float* predicted);
+
+/* Threshold query with the variant the selector predicts fastest among those
+ * the inputs allow.  With TQ_AUTO_FALLBACK, an uncertain prediction (top two
+ * within the margin, or features outside the training range) makes the call
+ * time every available variant once and keep the fastest; that path
+ * synchronises the stream.  *chosen (nullable) receives the variant. */
+tq_status tq_threshold_auto(tq_ctx* ctx, const tq_bitmap* inputs, uint32_t n, uint64_t r_bits, uint32_t theta,
+                            uint64_t* d_out, uint32_t flags, uint32_t* chosen, hipStream_t stream);
+
+/* Selector network kernels (device arrays, fp32).  x: batch x 8 features,
+ * y: batch x 4 outputs, t: targets, mask (nullable): 0/1 per target; the
+ * loss is sum(mask * (y - t)^2) / mask_count.  tq_mlp_grad writes the
+ * gradient of the loss w.r.t. the parameters (and the loss, and y if
+ * non-NULL); tq_mlp_adam applies one Adam step (step counts from 1). */
+tq_status tq_mlp_forward(tq_ctx* ctx, const float* d_params, const float* d_x, uint32_t batch, float* d_y,
+                         hipStream_t stream);
+tq_status tq_mlp_grad(tq_ctx* ctx, const float* d_params, const float* d_x, const float* d_t, const float* d_mask,
+                      uint32_t batch, float mask_count, float* d_y, float* d_grad, float* d_loss,
+                      hipStream_t stream);
+tq_status tq_mlp_adam(tq_ctx* ctx, float* d_params, const float* d_grad, float* d_m, float* d_v, uint32_t count,
+                      float lr, float beta1, float beta2, float eps, uint32_t step, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

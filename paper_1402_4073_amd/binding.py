@@ -68,6 +68,17 @@ def _load():
         "tq_batch_wait": (_INT, [_P]),
         "tq_batch_records": (_INT, [_P, _P]),
         "tq_batch_release": (_INT, [_P]),
+        "tq_bitmap_stats": (_INT, [_P, _P, _U64, _P, _P, _P]),
+        "tq_query_features": (_INT, [_P, _U32, _U64, _U32, _P]),
+        "tq_threshold_variant": (_INT, [_P, _P, _U32, _U64, _U32, _U32, _P, _P]),
+        "tq_selector_param_count": (_U64, []),
+        "tq_selector_set": (_INT, [_P, _P, _P, _P, _P, _P, ctypes.c_float]),
+        "tq_selector_predict": (_INT, [_P, _P, _P]),
+        "tq_threshold_auto": (_INT, [_P, _P, _U32, _U64, _U32, _P, _U32, ctypes.POINTER(_U32), _P]),
+        "tq_mlp_forward": (_INT, [_P, _P, _P, _U32, _P, _P]),
+        "tq_mlp_grad": (_INT, [_P, _P, _P, _P, _P, _U32, ctypes.c_float, _P, _P, _P, _P]),
+        "tq_mlp_adam": (_INT, [_P, _P, _P, _P, _P, _U32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                               ctypes.c_float, _U32, _P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -399,6 +410,104 @@ def tq_batch_records(batch: int, count: int):
 
 def tq_batch_release(batch: int) -> None:
     _check(_lib.tq_batch_release(batch), "tq_batch_release")
+
+
+# --------------------------------------------------------- variants, selector
+TQ_SEL_FEATURES = 8
+TQ_SEL_VARIANTS = 4
+TQ_SEL_PARAMS = 4996
+TQ_VARIANT_CSA, TQ_VARIANT_COUNTER, TQ_VARIANT_RLE, TQ_VARIANT_HYBRID = 0, 1, 2, 3
+VARIANT_NAMES = ("csa", "counter", "rle", "hybrid")
+TQ_AUTO_FALLBACK = 1
+TQ_AUTO_CHOSE_BY_TIMING = 0x100
+
+
+class TqBitmap(ctypes.Structure):
+    _fields_ = [("dense", _U64), ("rle", TqRle), ("ones", _U64), ("runs", _U64)]
+
+
+def bitmap_array(bitmaps):
+    """bitmaps: sequence of dicts with keys dense (tensor/addr or None),
+    rle ((words, n_words, index) or None), ones, runs."""
+    arr = (TqBitmap * max(1, len(bitmaps)))()
+    for i, b in enumerate(bitmaps):
+        arr[i].dense = 0 if b.get("dense") is None else _ptr(b["dense"])
+        if b.get("rle") is not None:
+            w, nw, idx = b["rle"]
+            arr[i].rle.words = _ptr(w)
+            arr[i].rle.n_words = int(nw)
+            arr[i].rle.index = 0 if idx is None else _ptr(idx)
+        arr[i].ones = int(b["ones"])
+        arr[i].runs = int(b["runs"])
+    return arr
+
+
+def tq_bitmap_stats(ctx: int, dense, r_bits: int, ones_out, runs_out, stream=None) -> None:
+    _check(_lib.tq_bitmap_stats(ctx, _ptr(dense), r_bits, _ptr(ones_out), _ptr(runs_out), _stream(stream)),
+           "tq_bitmap_stats")
+
+
+def tq_query_features(bitmaps, r_bits: int, theta: int):
+    """Host computation; bitmaps as for bitmap_array (or a prebuilt array with n)."""
+    import numpy as np
+    arr, n = (bitmaps if isinstance(bitmaps, tuple) else (bitmap_array(bitmaps), len(bitmaps)))
+    out = (ctypes.c_float * TQ_SEL_FEATURES)()
+    _check(_lib.tq_query_features(arr, n, r_bits, theta, out), "tq_query_features")
+    return np.array(out[:], dtype=np.float32)
+
+
+def tq_threshold_variant(ctx: int, bitmaps, r_bits: int, theta: int, variant: int, out, stream=None) -> None:
+    arr, n = (bitmaps if isinstance(bitmaps, tuple) else (bitmap_array(bitmaps), len(bitmaps)))
+    _check(_lib.tq_threshold_variant(ctx, arr, n, r_bits, theta, variant, _ptr(out), _stream(stream)),
+           "tq_threshold_variant")
+
+
+def _f32(a):
+    import numpy as np
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    return a, a.ctypes.data
+
+
+def tq_selector_param_count() -> int:
+    return int(_lib.tq_selector_param_count())
+
+
+def tq_selector_set(ctx: int, params, mean, std, lo, hi, margin: float) -> None:
+    keep = [_f32(a) for a in (params, mean, std, lo, hi)]
+    _check(_lib.tq_selector_set(ctx, *[k[1] for k in keep], float(margin)), "tq_selector_set")
+
+
+def tq_selector_predict(ctx: int, features):
+    import numpy as np
+    f, fp = _f32(features)
+    out = np.zeros(TQ_SEL_VARIANTS, dtype=np.float32)
+    _check(_lib.tq_selector_predict(ctx, fp, out.ctypes.data), "tq_selector_predict")
+    return out
+
+
+def tq_threshold_auto(ctx: int, bitmaps, r_bits: int, theta: int, out, flags: int = 0, stream=None) -> int:
+    """Returns the chosen variant (with TQ_AUTO_CHOSE_BY_TIMING set if timed)."""
+    arr, n = (bitmaps if isinstance(bitmaps, tuple) else (bitmap_array(bitmaps), len(bitmaps)))
+    chosen = _U32()
+    _check(_lib.tq_threshold_auto(ctx, arr, n, r_bits, theta, _ptr(out), flags, ctypes.byref(chosen),
+                                  _stream(stream)), "tq_threshold_auto")
+    return chosen.value
+
+
+def tq_mlp_forward(ctx: int, params, x, batch: int, y, stream=None) -> None:
+    _check(_lib.tq_mlp_forward(ctx, _ptr(params), _ptr(x), batch, _ptr(y), _stream(stream)), "tq_mlp_forward")
+
+
+def tq_mlp_grad(ctx: int, params, x, t, mask, batch: int, mask_count: float, y, grad, loss, stream=None) -> None:
+    _check(_lib.tq_mlp_grad(ctx, _ptr(params), _ptr(x), _ptr(t), 0 if mask is None else _ptr(mask), batch,
+                            float(mask_count), 0 if y is None else _ptr(y), _ptr(grad),
+                            0 if loss is None else _ptr(loss), _stream(stream)), "tq_mlp_grad")
+
+
+def tq_mlp_adam(ctx: int, params, grad, m, v, count: int, lr: float, beta1: float, beta2: float, eps: float,
+                step: int, stream=None) -> None:
+    _check(_lib.tq_mlp_adam(ctx, _ptr(params), _ptr(grad), _ptr(m), _ptr(v), count, lr, beta1, beta2, eps, step,
+                            _stream(stream)), "tq_mlp_adam")
 
 
 class Context:

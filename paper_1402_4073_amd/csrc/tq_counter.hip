@@ -1,0 +1,146 @@
+// Per-position counter variant (the GPU form of ScanCount, section 4.2) and
+// per-bitmap statistics used as selector metadata.
+//
+// Counter variant: one lane owns one 64-bit word column and keeps a counter
+// for each of its 64 positions, packed SIMD-within-a-register: with W-bit
+// counters, register k holds the counters of positions k, k + W, k + 2W, ...
+// (64/W of them), and adding an input word x is C[k] += (x >> k) & E for the
+// W registers, E having a 1 at the bottom of every W-bit field.  W = 8 serves
+// N <= 255 and W = 16 any N <= 65535, so a counter never overflows.  The
+// threshold (or any truth table) is then applied per position.  Compared with
+// the carry-save counter this spends W times more ALU work per input word,
+// which is the trade the selector weighs.
+#include "tq_internal.h"
+
+namespace tq {
+namespace {
+
+template <int W>
+struct Packed {
+  static constexpr uint64_t E = W == 8 ? 0x0101010101010101ull : 0x0001000100010001ull;
+  static constexpr int F = 64 / W;   // counters per register
+};
+
+template <int W, bool Guard>
+__device__ __forceinline__ void count_inputs(uint64_t (&C)[W], const uint64_t* const* __restrict__ ptrs,
+                                             uint32_t n, uint64_t w, uint64_t nwords) {
+  constexpr uint64_t E = Packed<W>::E;
+  uint32_t i = 0;
+  for (; i + 8 <= n; i += 8) {
+    uint64_t x[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const uint64_t* p = ptrs[i + u];
+      x[u] = (!Guard || w < nwords) ? __builtin_nontemporal_load(p + w) : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int k = 0; k < W; ++k) C[k] += (x[u] >> k) & E;
+  }
+  for (; i < n; ++i) {
+    const uint64_t x = (!Guard || w < nwords) ? ptrs[i][w] : 0;
+#pragma unroll
+    for (int k = 0; k < W; ++k) C[k] += (x >> k) & E;
+  }
+}
+
+// W-bit counters per lane; the epilogue compares each counter with theta or
+// looks f up in a table of n + 1 bits (one of the two is used).
+template <int W>
+__global__ __launch_bounds__(256) void counter_kernel(const uint64_t* const* __restrict__ ptrs, uint32_t n,
+                                                     uint64_t nwords, uint64_t tail_mask, uint32_t theta,
+                                                     const uint32_t* __restrict__ table, uint64_t* __restrict__ out) {
+  constexpr int F = Packed<W>::F;
+  constexpr uint64_t M = (W == 8) ? 0xFFull : 0xFFFFull;
+  const uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t wave_base = w & ~(uint64_t)63;
+  uint64_t C[W];
+#pragma unroll
+  for (int k = 0; k < W; ++k) C[k] = 0;
+  if (wave_base + 64 <= nwords)
+    count_inputs<W, false>(C, ptrs, n, w, nwords);
+  else
+    count_inputs<W, true>(C, ptrs, n, w, nwords);
+  if (w >= nwords) return;
+  uint64_t o = 0;
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      const uint32_t c = (uint32_t)((C[k] >> (W * f)) & M);
+      const uint32_t bit = table ? ((table[c >> 5] >> (c & 31)) & 1u) : (c >= theta ? 1u : 0u);
+      o |= (uint64_t)bit << (k + W * f);
+    }
+  }
+  out[w] = (w == nwords - 1) ? (o & tail_mask) : o;
+}
+
+// ones and runs of one bitmap: runs = 1 + number of positions p in [1, r)
+// where bit p differs from bit p-1
+__global__ void stats_kernel(const uint64_t* __restrict__ d, uint64_t nwords, uint64_t tail_mask,
+                             uint64_t r_bits, unsigned long long* __restrict__ ones,
+                             unsigned long long* __restrict__ changes) {
+  unsigned long long so = 0, sc = 0;
+  for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nwords;
+       w += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t m = (w == nwords - 1) ? tail_mask : ~(uint64_t)0;
+    const uint64_t x = d[w] & m;
+    so += __popcll(x);
+    // bit p vs bit p-1 inside the word, and the first bit vs the previous word's last
+    const uint64_t prev_last = w ? (d[w - 1] >> 63) : (x & 1);
+    const uint64_t shifted = (x << 1) | prev_last;
+    sc += __popcll((x ^ shifted) & m);
+  }
+  // wave reduction then one atomic per wave
+  for (int off = 32; off > 0; off >>= 1) {
+    so += __shfl_down(so, off, 64);
+    sc += __shfl_down(sc, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(ones, so);
+    atomicAdd(changes, sc);
+  }
+}
+
+__global__ void stats_finish_kernel(unsigned long long* changes, uint64_t r_bits) {
+  *changes = r_bits ? *changes + 1 : 0;   // runs = changes + 1
+}
+
+__global__ void zero2_kernel(unsigned long long* a, unsigned long long* b) {
+  *a = 0;
+  *b = 0;
+}
+
+}  // namespace
+
+hipError_t launch_counter(const uint64_t* const* d_ptrs, uint32_t n, uint64_t nwords, uint64_t tail_mask,
+                          uint32_t theta, const uint32_t* d_table, uint64_t* d_out, hipStream_t stream) {
+  const uint64_t blocks = (nwords + 255) / 256;
+  if (blocks == 0) return hipSuccess;
+  if (n <= 255)
+    hipLaunchKernelGGL(counter_kernel<8>, dim3((uint32_t)blocks), dim3(256), 0, stream, d_ptrs, n, nwords,
+                       tail_mask, theta, d_table, d_out);
+  else
+    hipLaunchKernelGGL(counter_kernel<16>, dim3((uint32_t)blocks), dim3(256), 0, stream, d_ptrs, n, nwords,
+                       tail_mask, theta, d_table, d_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_stats(const uint64_t* d_dense, uint64_t r_bits, uint64_t* d_ones, uint64_t* d_runs,
+                        hipStream_t stream) {
+  const uint64_t nw = words_for_bits(r_bits);
+  unsigned long long* o = reinterpret_cast<unsigned long long*>(d_ones);
+  unsigned long long* c = reinterpret_cast<unsigned long long*>(d_runs);
+  hipLaunchKernelGGL(zero2_kernel, dim3(1), dim3(1), 0, stream, o, c);
+  if (nw) {
+    uint64_t blocks = (nw + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(stats_kernel, dim3((uint32_t)blocks), dim3(256), 0, stream, d_dense, nw,
+                       tail_mask_for(r_bits), r_bits, o, c);
+  }
+  hipLaunchKernelGGL(stats_finish_kernel, dim3(1), dim3(1), 0, stream, c, r_bits);
+  return hipGetLastError();
+}
+
+}  // namespace tq

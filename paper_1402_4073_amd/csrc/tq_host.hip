@@ -266,6 +266,7 @@ tq_status tq_destroy(tq_ctx* ctx) {
   hipSetDevice(ctx->device);
   hipDeviceSynchronize();
   batch_destroy(ctx);
+  selector_destroy(ctx);
   for (auto& b : ctx->blobs) blob_release(b);
   if (ctx->ws) hipFree(ctx->ws);
   if (ctx->d_status) hipFree(ctx->d_status);

@@ -118,6 +118,7 @@ struct tq_ctx {
   void* ws = nullptr;          // grow-only device workspace (RLE paths)
   size_t ws_bytes = 0;
   void* batch = nullptr;       // batch slots (created on first submission)
+  void* selector = nullptr;    // selector network and feature ranges
 };
 
 namespace tq {
@@ -143,6 +144,7 @@ inline int bit_length(uint64_t x) {
 tq_status record_hip(tq_ctx* ctx, hipError_t e);
 
 void batch_destroy(tq_ctx* ctx);
+void selector_destroy(tq_ctx* ctx);
 
 // Device workspace of at least `bytes` (grown with a device synchronisation).
 void* workspace(tq_ctx* ctx, size_t bytes);
