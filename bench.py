@@ -31,7 +31,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="large", choices=["large", "small", "rle", "serving"])
+    ap.add_argument("--workload", default="large", choices=["large", "small", "rle", "serving", "selector"])
+    ap.add_argument("--selector-queries", type=int, default=2500)
+    ap.add_argument("--selector-train", type=int, default=2000)
+    ap.add_argument("--selector-out", default=os.path.join(ROOT, "gpurun_out", "selector"))
     ap.add_argument("--serving-queries", type=int, default=20000)
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline sample")
@@ -373,6 +376,129 @@ def bench_serving(args):
     return rec
 
 
+def bench_selector(args):
+    """Selector workload: queries with N log-uniform in [2, 4096], r = 2^22,
+    density log-uniform in [1e-5, 0.5], mean ones-run log-uniform in
+    [1, 4096], theta/N uniform in (0, 1].  Every query's bitmaps are
+    generated on the GPU and registered in both forms (dense words; canonical
+    stream with checkpoint index; cardinality and run count), the four
+    variants are timed (median of 5 after a warm-up), the network is trained
+    on the first queries' log times with the library's kernels and evaluated
+    on the rest: regret against the exhaustive best, with and without the
+    exhaustive-timing fallback, against always running the default variant."""
+    import numpy as np
+    import torch
+    import tqgen
+    from paper_1402_4073_amd import binding as tq
+    from paper_1402_4073_amd import selector as sel
+
+    os.makedirs(args.selector_out, exist_ok=True)
+    r = tqgen.SELECTOR["r_bits"]
+    nw = (r + 63) // 64
+    qs = tqgen.selector_queries(4, count=args.selector_queries)
+    ctx = tq.tq_create(0)
+    dev = torch.device("cuda:0")
+    nq = len(qs)
+    X = np.zeros((nq, 8), dtype=np.float32)
+    Tm = np.zeros((nq, 4), dtype=np.float64)      # median seconds per variant
+    meta = []
+    iw = tq.tq_rle_index_words(r)
+    t_start = time.perf_counter()
+    for qi, q in enumerate(qs):
+        ms = tqgen.markov_density_runlength(q.seed, q.n, r, q.density, q.mean_run)
+        dense = torch.empty((q.n, nw), dtype=torch.int64, device=dev)
+        tqgen.fill_gpu(ms, dense.view(-1))
+        slots = torch.empty((q.n, nw + 2), dtype=torch.int64, device=dev)
+        idx = torch.empty((q.n, iw), dtype=torch.int64, device=dev)
+        lens = torch.zeros(q.n, dtype=torch.int64, device=dev)
+        stats = torch.zeros((q.n, 2), dtype=torch.int64, device=dev)
+        for j in range(q.n):
+            tq.tq_bitmap_stats(ctx, dense[j], r, stats[j, 0:1], stats[j, 1:2])
+            tq.tq_rle_encode(ctx, dense[j], r, slots[j], nw + 2, lens[j:j + 1], idx[j])
+        if tq.tq_ctx_check(ctx) != 0:
+            raise RuntimeError("encode failed")
+        st = stats.cpu().numpy()
+        ln = lens.cpu().numpy()
+        bms = [dict(dense=dense[j], rle=(slots[j], int(ln[j]), idx[j]), ones=int(st[j, 0]), runs=int(st[j, 1]))
+               for j in range(q.n)]
+        arr = (tq.bitmap_array(bms), q.n)
+        X[qi] = tq.tq_query_features(arr, r, q.theta)
+        out = torch.empty(nw, dtype=torch.int64, device=dev)
+        for v in range(4):
+            tq.tq_threshold_variant(ctx, arr, r, q.theta, v, out)      # warm-up
+            evs = []
+            for _ in range(5):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                tq.tq_threshold_variant(ctx, arr, r, q.theta, v, out)
+                b.record()
+                evs.append((a, b))
+            torch.cuda.synchronize()
+            Tm[qi, v] = float(np.median([a.elapsed_time(b) for a, b in evs])) / 1e3
+        meta.append(dict(n=q.n, theta=q.theta, density=q.density, mean_run=q.mean_run,
+                         comp_words=int(ln.sum())))
+        del dense, slots, idx
+        if qi % 250 == 0:
+            print("selector data: %d/%d queries, %.0f s" % (qi, nq, time.perf_counter() - t_start),
+                  file=sys.stderr, flush=True)
+    torch.cuda.empty_cache()
+    ntr = min(args.selector_train, nq - 1)
+    logT = np.log(Tm)
+    mean, std = sel.normalisation(X[:ntr])
+    Xn = (X - mean) / std
+    t0 = time.perf_counter()
+    params, hist = sel.train(ctx, Xn[:ntr], logT[:ntr].astype(np.float32), epochs=4000, lr=2e-3)
+    train_s = time.perf_counter() - t0
+    pred = sel.predict(ctx, params, Xn)
+    te = slice(ntr, nq)
+    P, Ttest = pred[te], Tm[te]
+    chosen = P.argmin(axis=1)
+    best_t = Ttest.min(axis=1)
+    res = {"selector": sel.regret(Ttest, chosen)}
+    res["always_csa"] = sel.regret(Ttest, np.zeros(len(chosen), dtype=int))
+    fixed = int(np.argmin(Tm[:ntr].sum(axis=0)))
+    res["best_fixed_variant"] = dict(sel.regret(Ttest, np.full(len(chosen), fixed)), variant=tq.VARIANT_NAMES[fixed])
+    # fallback: when the top two predictions are within the margin or the
+    # features leave the training range, time all variants (their cost counts)
+    srt = np.sort(P, axis=1)
+    margin = 0.0
+    lo, hi = X[:ntr].min(axis=0), X[:ntr].max(axis=0)
+    out_of_range = ~np.all((X[te] >= lo) & (X[te] <= hi), axis=1)
+    unsure = ((srt[:, 1] - srt[:, 0]) < margin) | out_of_range
+    eff = np.where(unsure, Ttest.sum(axis=1), Ttest[np.arange(len(chosen)), chosen])
+    res["selector_with_fallback"] = {"workload": float(eff.sum() / best_t.sum() - 1.0),
+                                     "fallback_rate": float(unsure.mean()), "margin": margin}
+    wins = np.bincount(Ttest.argmin(axis=1), minlength=4)
+    picks = np.bincount(chosen, minlength=4)
+    res["best_variant_counts"] = {tq.VARIANT_NAMES[v]: int(wins[v]) for v in range(4)}
+    res["selector_pick_counts"] = {tq.VARIANT_NAMES[v]: int(picks[v]) for v in range(4)}
+    res["speedup_vs_always_csa"] = float(Ttest[:, 0].sum() / Ttest[np.arange(len(chosen)), chosen].sum())
+    res["train"] = {"queries": ntr, "epochs": 4000, "seconds": round(train_s, 2), "loss_first_last": [hist[0][1], hist[-1][1]]}
+    # held-out queries through the library's own dispatch (host inference)
+    tq.tq_selector_set(ctx, params, mean, std, lo, hi, margin)
+    agree = sum(int(np.argmin(tq.tq_selector_predict(ctx, X[i]))) == int(pred[i].argmin()) for i in range(ntr, nq))
+    res["host_gpu_inference_agreement"] = agree / (nq - ntr)
+    np.savez(os.path.join(args.selector_out, "dataset.npz"), X=X, T=Tm, params=params, mean=mean, std=std)
+    with open(os.path.join(args.selector_out, "weights.json"), "w") as fh:
+        json.dump({"params": params.tolist(), "mean": mean.tolist(), "std": std.tolist(), "lo": lo.tolist(),
+                   "hi": hi.tolist(), "margin": margin, "queries": nq, "train": ntr,
+                   "features": ["log2 N", "theta/N", "log10 density", "log10 ones-run", "std log10 density",
+                                "log2 r", "log2 compression", "log2 theta/(1+E count)"],
+                   "variants": list(tq.VARIANT_NAMES)}, fh)
+    tq.tq_destroy(ctx)
+    return {
+        "metric": "selector regret on held-out queries (sum t_selected / sum t_best - 1)",
+        "value": round(res["selector"]["workload"], 4), "unit": "fraction", "n_gpus": 1,
+        "steps": 1, "warmup": 1, "ms_per_step": round((time.perf_counter() - t_start) * 1e3, 1),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "fp32 (selection only)",
+        "data": "synthetic (seeded Markov bitmaps generated per query)",
+        "config": {"workload": "selector: %d queries (%d train / %d held out), r=2^22, N log-uniform [2,4096], "
+                               "density log-uniform [1e-5,0.5], mean ones-run log-uniform [1,4096]"
+                               % (nq, ntr, nq - ntr)},
+        "results": res,
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -389,6 +515,9 @@ def main():
         return
     if args.workload == "serving":
         print(json.dumps(bench_serving(args)), flush=True)
+        return
+    if args.workload == "selector":
+        print(json.dumps(bench_selector(args)), flush=True)
         return
 
     import numpy as np

@@ -66,6 +66,21 @@ def predict(ctx: int, params: np.ndarray, X: np.ndarray, device: str = "cuda:0")
     return y.cpu().numpy()
 
 
+DEFAULT_WEIGHTS = __import__("os").path.join(__import__("os").path.dirname(__file__), "data",
+                                             "selector_mi355x.json")
+
+
+def load_default(ctx: int, path: str = DEFAULT_WEIGHTS) -> dict:
+    """Install the weights trained on this GPU model (see data/) into a context."""
+    import json
+    with open(path) as fh:
+        w = json.load(fh)
+    tq.tq_selector_set(ctx, np.array(w["params"], dtype=np.float32), np.array(w["mean"], dtype=np.float32),
+                       np.array(w["std"], dtype=np.float32), np.array(w["lo"], dtype=np.float32),
+                       np.array(w["hi"], dtype=np.float32), float(w["margin"]))
+    return w
+
+
 def regret(times: np.ndarray, chosen: np.ndarray) -> dict:
     """Workload regret sum(t_chosen)/sum(t_best) - 1 and mean per-query
     (t - t_best)/t_best, times in seconds (B, 4) with inf for unavailable."""

@@ -149,3 +149,18 @@ def test_auto_dispatch(ctx):
     chosen = tq.tq_threshold_auto(ctx, arr, r, 3, out2, tq.TQ_AUTO_FALLBACK)
     assert chosen & tq.TQ_AUTO_CHOSE_BY_TIMING and (chosen & 0xFF) < 4
     assert np.array_equal(to_host(out2), oracle.threshold(dense, r, 3))
+
+
+def test_default_weights_dispatch(ctx):
+    """The shipped weights load and drive tq_threshold_auto to a correct result."""
+    w = selector.load_default(ctx)
+    assert len(w["params"]) == tq.TQ_SEL_PARAMS
+    r = 1 << 20
+    for n, d, m, theta in ((8, 0.2, 2.0, 3), (100, 1e-3, 500.0, 2)):
+        ms = tqgen.markov_density_runlength(n, n, r, d, m)
+        dense = [ms.words(j) for j in range(n)]
+        bms, keep = registered(ctx, dense, r)
+        out = empty_words(r // 64)
+        chosen = tq.tq_threshold_auto(ctx, bms, r, theta, out)
+        assert chosen < 4
+        assert np.array_equal(to_host(out), oracle.threshold(dense, r, theta))
