@@ -80,6 +80,16 @@ tq_status tq_destroy(tq_ctx* ctx);
 /* Static, human-readable name of a status code. */
 const char* tq_status_string(int status);
 
+/* Context options. */
+#define TQ_OPTION_PRUNE 1  /* value 1 (default): threshold queries stop reading inputs once every
+                              position of a 64-word column group is decided, i.e. its count already
+                              reaches theta or cannot reach it with the remaining inputs (the skipping
+                              argument of section 1, "Lower Bound").  Results are identical either
+                              way; 0 reads every input word. */
+
+/* Set a context option; TQ_EINVAL for an unknown option. */
+tq_status tq_set_option(tq_ctx* ctx, int option, int64_t value);
+
 /* Wait for `stream`, then return (and clear) the first device-detected error
  * recorded by calls on this context, or TQ_EDEVICE if a HIP call failed. */
 tq_status tq_ctx_check(tq_ctx* ctx, hipStream_t stream);

@@ -53,6 +53,7 @@ def _load():
         "tq_destroy": (_INT, [_P]),
         "tq_status_string": (ctypes.c_char_p, [_INT]),
         "tq_ctx_check": (_INT, [_P, _P]),
+        "tq_set_option": (_INT, [_P, _INT, ctypes.c_int64]),
         "tq_threshold": (_INT, [_P, _P, _U32, _U64, _U32, _P, _P]),
         "tq_symmetric": (_INT, [_P, _P, _U32, _U64, _P, _P, _P]),
         "tq_rle_max_words": (_U64, [_U64]),
@@ -161,6 +162,13 @@ def tq_create(device: int = 0) -> int:
 
 def tq_destroy(ctx: int) -> None:
     _check(_lib.tq_destroy(ctx), "tq_destroy")
+
+
+TQ_OPTION_PRUNE = 1
+
+
+def tq_set_option(ctx: int, option: int, value: int) -> None:
+    _check(_lib.tq_set_option(ctx, option, value), "tq_set_option")
 
 
 def tq_ctx_check(ctx: int, stream=None) -> int:

@@ -126,6 +126,60 @@ __device__ __forceinline__ void accumulate(Vec<WPL> (&P)[K], PtrArr ptrs,
   }
 }
 
+// Threshold pruning (the skipping argument of section 1, "Lower Bound"):
+// after i of the inputs, a position whose count already reaches theta, or
+// could not reach it with all remaining inputs, is decided.  Every kPruneEvery
+// inputs the wave checks whether all its positions are decided and stops
+// loading if so; the counter then still gives the right answer, because
+// count >= theta holds exactly at the positions that were going to pass.
+constexpr int kPruneEvery = 32;
+
+template <int K, int WPL>
+__device__ __forceinline__ Vec<WPL> greater_than(const Vec<WPL> (&P)[K], uint32_t a);
+
+template <int K, int WPL, bool Guard, typename PtrArr>
+__device__ __forceinline__ void accumulate_pruned(Vec<WPL> (&P)[K], PtrArr ptrs, uint32_t n, uint64_t w,
+                                                  uint64_t nwords, uint32_t theta) {
+  uint32_t i = 0;
+  while (i + kBlock <= n) {
+    Vec<WPL> x[kBlock];
+#pragma unroll
+    for (int u = 0; u < kBlock; ++u) x[u] = load_cols<WPL, Guard>(ptrs[i + u], w, nwords);
+    add_block<K, WPL>(P, x);
+    i += kBlock;
+    if ((i % kPruneEvery) == 0 && i < n) {
+      const uint32_t rem = n - i;
+      // undecided: count >= theta - rem (could still pass) and count < theta (has not passed)
+      uint64_t und = 0;
+      if (theta > rem) {
+        const Vec<WPL> lo = greater_than<K, WPL>(P, theta - rem - 1);
+        const Vec<WPL> hi = greater_than<K, WPL>(P, theta - 1);
+#pragma unroll
+        for (int q = 0; q < WPL; ++q) und |= lo.w[q] & ~hi.w[q];
+      } else {
+        const Vec<WPL> hi = greater_than<K, WPL>(P, theta - 1);
+#pragma unroll
+        for (int q = 0; q < WPL; ++q) und |= ~hi.w[q];
+      }
+      if (Guard && w >= nwords) und = 0;
+      if (!__any(und != 0)) return;
+    }
+  }
+  if (i < n) {
+    Vec<WPL> x[kBlock];
+#pragma unroll
+    for (int u = 0; u < kBlock; ++u) {
+      if (i + u < n) {
+        x[u] = load_cols<WPL, Guard>(ptrs[i + u], w, nwords);
+      } else {
+#pragma unroll
+        for (int q = 0; q < WPL; ++q) x[u].w[q] = 0;
+      }
+    }
+    add_block<K, WPL>(P, x);
+  }
+}
+
 // count > a, for a < 2^K (a is grid-uniform)
 template <int K, int WPL>
 __device__ __forceinline__ Vec<WPL> greater_than(const Vec<WPL> (&P)[K], uint32_t a) {

@@ -65,10 +65,19 @@ __global__ __launch_bounds__(64 * S * G) void dense_kernel(
     for (int i = 0; i < WPL; ++i) P[k].w[i] = 0;
 
   if (base < nwords) {
-    if (base + 64 * WPL <= nwords)
-      accumulate<K, WPL, false>(P, ptrs, i0, i1, w, nwords);
-    else
-      accumulate<K, WPL, true>(P, ptrs, i0, i1, w, nwords);
+    // a threshold query whose inputs all go through this wave can stop early
+    const bool prune = S == 1 && epi.kind == EPI_THRESH && epi.prune && epi.theta >= 1 && epi.theta <= n;
+    if (base + 64 * WPL <= nwords) {
+      if (prune)
+        accumulate_pruned<K, WPL, false>(P, ptrs, n, w, nwords, epi.theta);
+      else
+        accumulate<K, WPL, false>(P, ptrs, i0, i1, w, nwords);
+    } else {
+      if (prune)
+        accumulate_pruned<K, WPL, true>(P, ptrs, n, w, nwords, epi.theta);
+      else
+        accumulate<K, WPL, true>(P, ptrs, i0, i1, w, nwords);
+    }
   }
 
   if constexpr (S > 1) {

@@ -274,6 +274,16 @@ tq_status tq_destroy(tq_ctx* ctx) {
   return TQ_OK;
 }
 
+tq_status tq_set_option(tq_ctx* ctx, int option, int64_t value) {
+  if (!ctx) return TQ_EINVAL;
+  switch (option) {
+    case TQ_OPTION_PRUNE:
+      ctx->prune = value ? 1 : 0;
+      return TQ_OK;
+  }
+  return TQ_EINVAL;
+}
+
 tq_status tq_ctx_check(tq_ctx* ctx, hipStream_t stream) {
   if (!ctx) return TQ_EINVAL;
   hipError_t e = hipStreamSynchronize(stream);
@@ -327,6 +337,7 @@ tq_status run_dense(tq_ctx* ctx, const uint64_t* const* ptrs, uint32_t n, uint64
   const void* d_ptrs = blob_get(ctx, reinterpret_cast<const uint64_t*>(ptrs), n, stream, &pb);
   if (!d_ptrs) return TQ_EDEVICE;
   EpiParams epi = plan.epi;
+  epi.prune = ctx->prune ? 1u : 0u;
   Blob* tb = nullptr;
   if (epi.kind == EPI_TABLE) {
     std::vector<uint64_t> t64((plan.table.size() + 1) / 2, 0);

@@ -34,7 +34,7 @@ struct EpiParams {
   uint32_t hi1[kMaxIntervals];  // c <  hi1  (> n means no upper bound)
   const uint32_t* table;        // EPI_TABLE: bit c of the table is f(c)
   uint32_t table_words;
-  uint32_t pad_;
+  uint32_t prune;               // EPI_THRESH: stop loading once every position is decided
 };
 
 // Plan of a symmetric function: a constant, or an epilogue.
@@ -119,6 +119,7 @@ struct tq_ctx {
   size_t ws_bytes = 0;
   void* batch = nullptr;       // batch slots (created on first submission)
   void* selector = nullptr;    // selector network and feature ranges
+  int prune = 1;               // TQ_OPTION_PRUNE
 };
 
 namespace tq {

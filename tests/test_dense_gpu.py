@@ -242,3 +242,33 @@ def test_large_config_sampled(ctx, large):
             out11 = torch.empty(bs.nwords, dtype=torch.int64, device="cuda")
             tq.tq_threshold(ctx, rows, bs.r_bits, 11, out11)
             assert torch.equal(out, want & ~out11)
+
+
+# ----------------------------------------------------------------- pruning
+@pytest.mark.parametrize("n", [40, 200, 1000])
+def test_pruning_equivalence(ctx, n):
+    """Threshold queries stop reading inputs once every position of a column
+    group is decided; the result must not change (against the unpruned run
+    and the oracle).  Densities vary per column group so waves stop at
+    different inputs."""
+    rng = np.random.default_rng(300 + n)
+    r = 64 * 64 * 9 + 31
+    nw = (r + 63) // 64
+    base = []
+    for j in range(min(n, 250)):
+        col_dens = np.repeat(rng.uniform(0.0, 1.0, (nw + 63) // 64), 64)[:nw]
+        bits = rng.random((nw, 64)) < col_dens[:, None] * rng.uniform(0.2, 1.0)
+        base.append(np.packbits(bits.astype(np.uint8), axis=1, bitorder="little").view("<u8").reshape(-1).astype(np.uint64))
+    pool = dev_pool(base)
+    pick = rng.integers(0, len(base), n)
+    rows = [pool[int(i)] for i in pick]
+    host = [base[int(i)] for i in pick]
+    for theta in sorted({1, 3, n // 3, n // 2, (3 * n) // 4, n - 1, n}):
+        want = oracle.threshold(host, r, theta)
+        outs = []
+        for prune in (1, 0):
+            tq.tq_set_option(ctx, tq.TQ_OPTION_PRUNE, prune)
+            outs.append(run_threshold(ctx, rows, r, theta))
+        tq.tq_set_option(ctx, tq.TQ_OPTION_PRUNE, 1)
+        assert np.array_equal(outs[0], want), theta
+        assert np.array_equal(outs[1], want), theta
