@@ -293,3 +293,24 @@ def test_rle_config_full_size(ctx):
         tq.tq_threshold(ctx, rows, r, theta, ref)                # uncompressed path, same inputs
         assert tq.tq_ctx_check(ctx) == 0
         assert np.array_equal(got, to_host(ref)), theta
+
+
+@pytest.mark.parametrize("n", [70, 150])
+def test_threshold_rle_many_dirty_words(ctx, n):
+    """Inputs dirty almost everywhere: undecided columns have more dirty words
+    than the on-chip counters hold, so tiles keep their counters in memory."""
+    r = 64 * 1100 + 5
+    dense = markov_bitmaps(500 + n, n, r, 2.0, 2.0)
+    inputs, keep = rle_inputs(ctx, dense, r)
+    for theta in (1, n // 3, n // 2, n - 1, n):
+        out = empty_words((r + 63) // 64)
+        tq.tq_threshold_rle_dense(ctx, inputs, r, theta, out)
+        assert tq.tq_ctx_check(ctx) == 0
+        assert np.array_equal(to_host(out), oracle.threshold(dense, r, theta)), theta
+    # hybrid with the same inputs split between the two forms
+    half = n // 2
+    pool = dev_pool(dense[half:])
+    out = empty_words((r + 63) // 64)
+    tq.tq_threshold_hybrid(ctx, inputs[:half], [pool[j] for j in range(n - half)], r, n // 2, out)
+    assert tq.tq_ctx_check(ctx) == 0
+    assert np.array_equal(to_host(out), oracle.threshold(dense, r, n // 2))
