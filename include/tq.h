@@ -86,6 +86,10 @@ const char* tq_status_string(int status);
                               reaches theta or cannot reach it with the remaining inputs (the skipping
                               argument of section 1, "Lower Bound").  Results are identical either
                               way; 0 reads every input word. */
+#define TQ_OPTION_RLE_TILES 2  /* tiles of TQ_RLE_INDEX_STRIDE words that one workgroup of a query over
+                                  RLE inputs walks in a row, each input read front to back across
+                                  them; 0 (default) picks one range per resident workgroup.  Any value
+                                  gives the same results; values outside [0, 2^20] are TQ_EINVAL. */
 
 /* Set a context option; TQ_EINVAL for an unknown option. */
 tq_status tq_set_option(tq_ctx* ctx, int option, int64_t value);
@@ -144,6 +148,10 @@ tq_status tq_symmetric(tq_ctx* ctx, const uint64_t* const* ptrs, uint32_t n, uin
 #define TQ_RLE_INDEX_STRIDE 512
 /* Largest N accepted by the compressed-input calls. */
 #define TQ_RLE_MAX_INPUTS 8192u
+/* The threshold calls over compressed inputs (tq_threshold_rle,
+ * tq_threshold_rle_dense, tq_threshold_hybrid) accept bitmaps of fewer than
+ * 2^31 words (r_bits < 2^37) and streams of at most 2^32 - 1024 words;
+ * larger ones are TQ_EINVAL. */
 
 typedef struct tq_rle {
   const uint64_t* words; /* device stream */

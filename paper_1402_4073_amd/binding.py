@@ -165,10 +165,16 @@ def tq_destroy(ctx: int) -> None:
 
 
 TQ_OPTION_PRUNE = 1
+TQ_OPTION_RLE_TILES = 2
 
 
 def tq_set_option(ctx: int, option: int, value: int) -> None:
     _check(_lib.tq_set_option(ctx, option, value), "tq_set_option")
+
+
+def raw_set_option(ctx: int, option: int, value: int) -> int:
+    """tq_set_option returning the status instead of raising."""
+    return _lib.tq_set_option(ctx, option, value)
 
 
 def tq_ctx_check(ctx: int, stream=None) -> int:

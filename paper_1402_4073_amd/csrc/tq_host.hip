@@ -280,6 +280,10 @@ tq_status tq_set_option(tq_ctx* ctx, int option, int64_t value) {
     case TQ_OPTION_PRUNE:
       ctx->prune = value ? 1 : 0;
       return TQ_OK;
+    case TQ_OPTION_RLE_TILES:
+      if (value < 0 || value > (1 << 20)) return TQ_EINVAL;
+      ctx->rle_tiles = (uint32_t)value;
+      return TQ_OK;
   }
   return TQ_EINVAL;
 }

@@ -77,10 +77,15 @@ struct RleDesc {
   const uint64_t* index;
 };
 
+// Largest stream length accepted by the queries over RLE inputs (bitmaps
+// are limited to fewer than 2^31 words): the tile kernel keeps positions in
+// 32 bits.
+constexpr uint64_t kRleMaxWords = (1ull << 32) - 1024;
 size_t rle_tile_lds_bytes(int K);
 hipError_t launch_rle_tile(const RleDesc* d_descs, uint32_t n_rle, const uint64_t* const* d_dense,
                            uint32_t n_dense, uint64_t nwords, uint64_t tail_mask, uint32_t theta,
-                           uint64_t* d_out, int* d_status, hipStream_t stream);
+                           int num_cus, uint32_t tiles_per_group, uint64_t* d_out, int* d_status,
+                           hipStream_t stream);
 size_t rle_encode_workspace_bytes(uint64_t nwords);
 hipError_t launch_rle_encode(const uint64_t* d_dense, uint64_t nwords, uint64_t tail_mask, uint64_t* d_out,
                              uint64_t cap, uint64_t* d_out_len, uint64_t* d_index, void* workspace,
@@ -120,6 +125,7 @@ struct tq_ctx {
   void* batch = nullptr;       // batch slots (created on first submission)
   void* selector = nullptr;    // selector network and feature ranges
   int prune = 1;               // TQ_OPTION_PRUNE
+  uint32_t rle_tiles = 0;      // TQ_OPTION_RLE_TILES (0: automatic)
 };
 
 namespace tq {

@@ -35,6 +35,7 @@ namespace tq {
 namespace {
 
 constexpr int kTile = TQ_RLE_INDEX_STRIDE;  // words per tile == checkpoint stride
+constexpr uint32_t kXcds = 8;                // accelerator complex dies per device
 constexpr int kTileThreads = 512;
 constexpr int kEncBlock = 256;
 constexpr int kEncPerThread = 4;
@@ -78,15 +79,18 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T* wave_tot, T* total) {
 }
 
 // ------------------------------------------------------------ tile kernel
+// Positions inside the kernel are 32-bit: the host admits only bitmaps of
+// fewer than 2^32 - kTile words and streams of fewer than 2^32 words.
 struct Walk {
-  uint64_t pos, w;
+  uint32_t pos, w;   // stream offset of a marker, uncompressed word where its run starts
 };
 
-// Enter stream j at the checkpoint of tile `tile`; returns false on a bad entry.
-__device__ __forceinline__ bool seek(const RleDesc& d, uint64_t tile, uint64_t t0, Walk& wk) {
-  wk.pos = d.index[2 * tile];
-  wk.w = d.index[2 * tile + 1];
-  return wk.pos < d.len && wk.w <= t0;
+// Enter a stream at the checkpoint of `tile`; returns false on a bad entry.
+__device__ __forceinline__ bool seek(const RleDesc& d, uint32_t tile, uint32_t t0, Walk& wk) {
+  const uint64_t pos = d.index[2 * (uint64_t)tile], w = d.index[2 * (uint64_t)tile + 1];
+  wk.pos = (uint32_t)pos;
+  wk.w = (uint32_t)w;
+  return pos < d.len && w <= t0;
 }
 
 template <int K>
@@ -104,7 +108,7 @@ __device__ __forceinline__ void unpack_kd(int32_t v, int& k, int& d) {
   d = (v >> 16) & 0xFFFF;
 }
 
-// count > a per lane (a differs between lanes)
+// count > a per lane (a differs between lanes), counter in registers
 template <int K>
 __device__ __forceinline__ uint64_t greater_than_lane(const uint64_t (&P)[K], uint32_t a) {
   uint64_t pm = ~(uint64_t)0, r = 0;
@@ -117,130 +121,277 @@ __device__ __forceinline__ uint64_t greater_than_lane(const uint64_t (&P)[K], ui
   return r;
 }
 
+// the same comparison reading the counter planes of column c from LDS
 template <int K>
-__global__ __launch_bounds__(kTileThreads) void rle_tile_kernel(
+__device__ __forceinline__ uint64_t greater_than_lds(const uint64_t* planes, int c, uint32_t a) {
+  uint64_t pm = ~(uint64_t)0, r = 0;
+#pragma unroll
+  for (int j = K - 1; j >= 0; --j) {
+    const uint64_t p = planes[j * kTile + c];
+    const uint64_t m = 0 - (uint64_t)((a >> j) & 1u);
+    r |= pm & p & ~m;
+    pm &= p | ~m;
+  }
+  return r;
+}
+
+// Sequential reader of one stream.  A lane walking its stream one marker at a
+// time would keep a cache line of its own open for the whole walk; with every
+// lane of the device doing so, the lines no longer fit in L2 and are fetched
+// again and again.  The reader instead loads the whole 64-byte sector holding
+// the word it needs into registers and serves the following words from
+// there, so each sector is fetched once per walk.  A sector never crosses a
+// page boundary, so loading all of it is safe whenever one of its words
+// belongs to the stream; words outside the stream are never returned.
+struct SectorReader {
+  const uint64_t* base;   // 64-byte aligned, at or below the stream start
+  uint32_t off;           // words from base to the stream start (0..7)
+  uint32_t cur;           // sector held (counted from base); kNone if none
+  uint64_t b0, b1, b2, b3, b4, b5, b6, b7;
+  static constexpr uint32_t kNone = 0xFFFFFFFFu;
+
+  __device__ __forceinline__ void reset(const uint64_t* w, uint64_t) {
+    const uintptr_t a = reinterpret_cast<uintptr_t>(w);
+    base = reinterpret_cast<const uint64_t*>(a & ~(uintptr_t)63);
+    off = (uint32_t)(a >> 3) & 7u;
+    cur = kNone;
+  }
+  __device__ __forceinline__ uint64_t at(uint32_t p) {
+    const uint32_t g = off + p;
+    const uint32_t sec = g >> 3;
+    if (sec != cur) {
+      const uint4* q = reinterpret_cast<const uint4*>(base + (uint64_t)sec * 8);
+      const uint4 v0 = q[0], v1 = q[1], v2 = q[2], v3 = q[3];
+      b0 = v0.x | ((uint64_t)v0.y << 32);
+      b1 = v0.z | ((uint64_t)v0.w << 32);
+      b2 = v1.x | ((uint64_t)v1.y << 32);
+      b3 = v1.z | ((uint64_t)v1.w << 32);
+      b4 = v2.x | ((uint64_t)v2.y << 32);
+      b5 = v2.z | ((uint64_t)v2.w << 32);
+      b6 = v3.x | ((uint64_t)v3.y << 32);
+      b7 = v3.z | ((uint64_t)v3.w << 32);
+      cur = sec;
+    }
+    const unsigned i = g & 7u;
+    const uint64_t x01 = (i & 1) ? b1 : b0, x23 = (i & 1) ? b3 : b2;
+    const uint64_t x45 = (i & 1) ? b5 : b4, x67 = (i & 1) ? b7 : b6;
+    const uint64_t x03 = (i & 2) ? x23 : x01, x47 = (i & 2) ? x67 : x45;
+    return (i & 4) ? x47 : x03;
+  }
+};
+
+// Word-at-a-time reader for the inputs past the first kTileThreads (few
+// queries have them; a sector buffer for them would cost occupancy).
+struct DirectReader {
+  const uint64_t* words;
+  __device__ __forceinline__ void reset(const uint64_t* w, uint64_t) { words = w; }
+  __device__ __forceinline__ uint64_t at(uint32_t p) const { return words[p]; }
+};
+
+// Decode the marker at wk.pos and check it against the stream and the bitmap;
+// on success w1 / w2 are the ends of its fill and literal runs.
+template <typename Reader>
+__device__ __forceinline__ bool read_marker(const RleDesc& dsc, Reader& rd, const Walk& wk, uint32_t nwords,
+                                            uint64_t& m, uint32_t& w1, uint32_t& w2) {
+  if (wk.pos >= dsc.len) return false;
+  m = rd.at(wk.pos);
+  const uint64_t run = (m >> 1) & 0xFFFFFFFFull, lits = m >> 33;
+  const uint64_t e1 = (uint64_t)wk.w + run, e2 = e1 + lits;
+  if (e2 > nwords || lits > dsc.len - wk.pos - 1) return false;
+  w1 = (uint32_t)e1;
+  w2 = (uint32_t)e2;
+  return true;
+}
+
+// Marker walk of one input over [t0, t1): fills of ones and literal runs go
+// into the difference array.  On return `next` is the entry state of the
+// following tile (the marker covering t1).
+template <typename Reader>
+__device__ __forceinline__ void walk_markers(const RleDesc& dsc, Reader& rd, Walk wk, uint32_t t0, uint32_t t1,
+                                             uint32_t nwords, int32_t* kd, int* status, Walk& next) {
+  next = wk;
+  while (wk.w < t1) {
+    uint64_t m;
+    uint32_t w1, w2;
+    if (!read_marker(dsc, rd, wk, nwords, m, w1, w2)) { set_status(status, TQ_EFORMAT); break; }
+    if ((m & 1) && w1 > wk.w) {
+      const uint32_t a = wk.w > t0 ? wk.w : t0, b = w1 < t1 ? w1 : t1;
+      if (a < b) {
+        atomicAdd(&kd[a - t0], 1);
+        atomicAdd(&kd[b - t0], -1);
+      }
+    }
+    if (w2 > w1) {
+      const uint32_t a = w1 > t0 ? w1 : t0, b = w2 < t1 ? w2 : t1;
+      if (a < b) {
+        atomicAdd(&kd[a - t0], 65536);
+        atomicAdd(&kd[b - t0], -65536);
+      }
+    }
+    // a marker reaching past t1 is where the next tile enters this stream
+    if (w2 > t1) {
+      next = wk;
+      return;
+    }
+    wk.pos += 1 + (w2 - w1);
+    wk.w = w2;
+    next = wk;
+  }
+}
+
+// Literal words of the undecided columns of [t0, t1) into the LDS counters.
+template <int K, typename Reader>
+__device__ __forceinline__ void walk_literals(const RleDesc& dsc, Reader& rd, Walk wk, uint32_t t0, uint32_t t1,
+                                              uint32_t nwords, uint32_t theta, uint32_t n_dense, const int32_t* kd,
+                                              uint64_t* planes) {
+  while (wk.w < t1) {
+    uint64_t m;
+    uint32_t w1, w2;
+    if (!read_marker(dsc, rd, wk, nwords, m, w1, w2)) break;
+    const uint32_t a = w1 > t0 ? w1 : t0, b = w2 < t1 ? w2 : t1;
+    for (uint32_t col = a; col < b; ++col) {
+      const int c = (int)(col - t0);
+      int k, d;
+      unpack_kd(kd[c], k, d);
+      const int tp = (int)theta - k;
+      if (tp >= 1 && tp <= d + (int)n_dense) ripple_lds<K>(planes, c, rd.at(wk.pos + 1 + (col - w1)));
+    }
+    wk.pos += 1 + (w2 - w1);
+    wk.w = w2;
+  }
+}
+
+// One workgroup processes a contiguous range of tiles.  The lane that owns
+// input j < kTileThreads carries its stream position (and its reader) from
+// one tile to the next, so a range reads each of its streams once, front to
+// back, and enters through the checkpoint index only at the range start;
+// further inputs (more than one per lane) enter every tile through the index.
+template <int K>
+__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(6))) void rle_tile_kernel(
     const RleDesc* __restrict__ descs, uint32_t n_rle, const uint64_t* const* __restrict__ dense,
-    uint32_t n_dense, uint64_t nwords, uint64_t tail_mask, uint32_t theta, uint64_t* __restrict__ out,
-    int* __restrict__ status) {
+    uint32_t n_dense, uint32_t nwords, uint64_t tail_mask, uint32_t theta, uint32_t tiles_per_group,
+    uint64_t* __restrict__ out, int* __restrict__ status) {
   extern __shared__ uint64_t lds[];
   uint64_t* planes = lds;                                         // K x kTile
   int32_t* kd = reinterpret_cast<int32_t*>(lds + K * kTile);      // kTile + 1 packed (k | d << 16)
   __shared__ int32_t wave_tot[kTileThreads / 64];
   __shared__ int32_t total;
 
-  const uint64_t tile = blockIdx.x;
-  const uint64_t t0 = tile * kTile;
-  const uint64_t t1 = t0 + kTile < nwords ? t0 + kTile : nwords;
+  // Workgroups are dealt to the eight XCDs round robin; give each XCD a
+  // contiguous block of ranges so that the cache lines two neighbouring
+  // ranges share are fetched into one L2.
+  const uint32_t tiles = (nwords + kTile - 1) / kTile;
+  const uint32_t ranges = (tiles + tiles_per_group - 1) / tiles_per_group;
+  const uint32_t per_xcd = (ranges + kXcds - 1) / kXcds;
+  const uint32_t range = (blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
+  if (range >= ranges) return;
+  const uint32_t tile_begin = range * tiles_per_group;
+  const uint32_t tile_end = tiles - tile_begin > tiles_per_group ? tile_begin + tiles_per_group : tiles;
   const int tid = threadIdx.x;
-
-  for (int i = tid; i < K * kTile; i += kTileThreads) planes[i] = 0;
-  for (int i = tid; i <= kTile; i += kTileThreads) kd[i] = 0;
-  __syncthreads();
-
-  // 1. markers only: difference array of (ones fills) + 65536 * (dirty)
-  for (uint32_t j = tid; j < n_rle; j += kTileThreads) {
-    const RleDesc dsc = descs[j];
-    Walk wk;
-    if (!seek(dsc, tile, t0, wk)) { set_status(status, TQ_EFORMAT); continue; }
-    while (wk.w < t1) {
-      if (wk.pos >= dsc.len) { set_status(status, TQ_EFORMAT); break; }
-      const uint64_t m = dsc.words[wk.pos];
-      const uint64_t run = (m >> 1) & 0xFFFFFFFFull, lits = m >> 33;
-      const uint64_t w1 = wk.w + run, w2 = w1 + lits;
-      if (w2 > nwords || lits > dsc.len - wk.pos - 1) { set_status(status, TQ_EFORMAT); break; }
-      if ((m & 1) && run) {
-        const uint64_t a = wk.w > t0 ? wk.w : t0, b = w1 < t1 ? w1 : t1;
-        if (a < b) {
-          atomicAdd(&kd[a - t0], 1);
-          atomicAdd(&kd[b - t0], -1);
-        }
-      }
-      if (lits) {
-        const uint64_t a = w1 > t0 ? w1 : t0, b = w2 < t1 ? w2 : t1;
-        if (a < b) {
-          atomicAdd(&kd[a - t0], 65536);
-          atomicAdd(&kd[b - t0], -65536);
-        }
-      }
-      wk.pos += 1 + lits;
-      wk.w = w2;
-    }
+  const bool own = (uint32_t)tid < n_rle;   // this lane carries input tid
+  RleDesc mine = {};
+  Walk carry = {0, 0};
+  bool carry_ok = false;
+  SectorReader rd;
+  DirectReader rx;
+  rd.reset(nullptr, 0);
+  if (own) {
+    mine = descs[tid];
+    rd.reset(mine.words, mine.len);
   }
-  __syncthreads();
 
-  // 2. prefix sum: kd[c] = k + 65536 * d for column c
-  int undecided = 0;
-  {
-    const int32_t v = tid < kTile ? kd[tid] : 0;
-    const int32_t ex = block_exclusive_scan<int32_t, kTileThreads / 64>(v, wave_tot, &total);
-    if (tid < kTile) kd[tid] = ex + v;
-    if (tid < (int)(t1 - t0)) {
+  for (uint32_t tile = tile_begin; tile < tile_end; ++tile) {
+    const uint32_t t0 = tile * kTile;
+    const uint32_t t1 = nwords - t0 > (uint32_t)kTile ? t0 + kTile : nwords;
+    if (tile != tile_begin) __syncthreads();   // the previous tile's phase 4 is done with the LDS
+    for (int i = tid; i < K * kTile; i += kTileThreads) planes[i] = 0;
+    for (int i = tid; i <= kTile; i += kTileThreads) kd[i] = 0;
+    __syncthreads();
+
+    // 1. markers only: difference array of (ones fills) + 65536 * (dirty)
+    Walk entry = {0, 0};
+    bool entry_ok = false;
+    if (own) {
+      if (carry_ok) {
+        entry = carry;
+        entry_ok = true;
+      } else {
+        entry_ok = seek(mine, tile, t0, entry);
+        if (!entry_ok) set_status(status, TQ_EFORMAT);
+      }
+      if (entry_ok) walk_markers(mine, rd, entry, t0, t1, nwords, kd, status, carry);
+      carry_ok = entry_ok;
+    }
+    for (uint32_t j = tid + kTileThreads; j < n_rle; j += kTileThreads) {
+      const RleDesc dsc = descs[j];
+      Walk wk, unused;
+      if (!seek(dsc, tile, t0, wk)) { set_status(status, TQ_EFORMAT); continue; }
+      rx.reset(dsc.words, dsc.len);
+      walk_markers(dsc, rx, wk, t0, t1, nwords, kd, status, unused);
+    }
+    __syncthreads();
+
+    // 2. prefix sum: kd[c] = k + 65536 * d for column c
+    int undecided = 0;
+    {
+      const int32_t v = tid < kTile ? kd[tid] : 0;
+      const int32_t ex = block_exclusive_scan<int32_t, kTileThreads / 64>(v, wave_tot, &total);
+      if (tid < kTile) kd[tid] = ex + v;
+      if (tid < (int)(t1 - t0)) {
+        int k, d;
+        unpack_kd(ex + v, k, d);
+        const int tp = (int)theta - k;
+        // literal words matter where the column is undecided and has some
+        undecided = (tp >= 1 && tp <= d + (int)n_dense && d > 0) ? 1 : 0;
+      }
+    }
+    // a tile whose columns the fills alone decide needs no literal word
+    undecided = __syncthreads_or(undecided);
+
+    // 3. literal words of undecided columns into the per-column LDS counters
+    if (undecided) {
+      if (own && entry_ok) walk_literals<K>(mine, rd, entry, t0, t1, nwords, theta, n_dense, kd, planes);
+      for (uint32_t j = tid + kTileThreads; j < n_rle; j += kTileThreads) {
+        const RleDesc dsc = descs[j];
+        Walk wk;
+        if (!seek(dsc, tile, t0, wk)) continue;
+        rx.reset(dsc.words, dsc.len);
+        walk_literals<K>(dsc, rx, wk, t0, t1, nwords, theta, n_dense, kd, planes);
+      }
+    }
+    __syncthreads();
+
+    // 4. one column per thread: decide, or count and compare
+    const int c = tid;
+    if (c < (int)(t1 - t0)) {
       int k, d;
-      unpack_kd(ex + v, k, d);
+      unpack_kd(kd[c], k, d);
       const int tp = (int)theta - k;
-      // literal words matter where the column is undecided and has some
-      undecided = (tp >= 1 && tp <= d + (int)n_dense && d > 0) ? 1 : 0;
-    }
-  }
-  // a tile whose columns the fills alone decide needs no literal word
-  undecided = __syncthreads_or(undecided);
-
-  // 3. literal words of undecided columns into the per-column LDS counters
-  for (uint32_t j = tid; undecided && j < n_rle; j += kTileThreads) {
-    const RleDesc dsc = descs[j];
-    Walk wk;
-    if (!seek(dsc, tile, t0, wk)) continue;
-    while (wk.w < t1) {
-      if (wk.pos >= dsc.len) break;
-      const uint64_t m = dsc.words[wk.pos];
-      const uint64_t run = (m >> 1) & 0xFFFFFFFFull, lits = m >> 33;
-      const uint64_t w1 = wk.w + run, w2 = w1 + lits;
-      if (w2 > nwords || lits > dsc.len - wk.pos - 1) break;
-      if (lits) {
-        const uint64_t a = w1 > t0 ? w1 : t0, b = w2 < t1 ? w2 : t1;
-        for (uint64_t col = a; col < b; ++col) {
-          const int c = (int)(col - t0);
-          int k, d;
-          unpack_kd(kd[c], k, d);
-          const int tp = (int)theta - k;
-          if (tp >= 1 && tp <= d + (int)n_dense)
-            ripple_lds<K>(planes, c, dsc.words[wk.pos + 1 + (col - w1)]);
-        }
-      }
-      wk.pos += 1 + lits;
-      wk.w = w2;
-    }
-  }
-  __syncthreads();
-
-  // 4. one column per thread: decide, or count and compare
-  const int c = tid;
-  if (c < (int)(t1 - t0)) {
-    int k, d;
-    unpack_kd(kd[c], k, d);
-    const int tp = (int)theta - k;
-    uint64_t res;
-    if (tp <= 0) {
-      res = ~(uint64_t)0;
-    } else if (tp > d + (int)n_dense) {
-      res = 0;
-    } else {
-      uint64_t P[K];
+      uint64_t res;
+      if (tp <= 0) {
+        res = ~(uint64_t)0;
+      } else if (tp > d + (int)n_dense) {
+        res = 0;
+      } else if (n_dense == 0) {
+        res = greater_than_lds<K>(planes, c, (uint32_t)(tp - 1));
+      } else {
+        uint64_t P[K];
 #pragma unroll
-      for (int q = 0; q < K; ++q) P[q] = planes[q * kTile + c];
-      const uint64_t col = t0 + c;
-      for (uint32_t i = 0; i < n_dense; ++i) {
-        uint64_t x = dense[i][col];
+        for (int q = 0; q < K; ++q) P[q] = planes[q * kTile + c];
+        const uint64_t col = (uint64_t)t0 + c;
+        for (uint32_t i = 0; i < n_dense; ++i) {
+          uint64_t x = dense[i][col];
 #pragma unroll
-        for (int q = 0; q < K; ++q) {
-          const uint64_t t = P[q] & x;
-          P[q] ^= x;
-          x = t;
+          for (int q = 0; q < K; ++q) {
+            const uint64_t t = P[q] & x;
+            P[q] ^= x;
+            x = t;
+          }
         }
+        res = greater_than_lane<K>(P, (uint32_t)(tp - 1));
       }
-      res = greater_than_lane<K>(P, (uint32_t)(tp - 1));
+      out[(uint64_t)t0 + c] = res & valid_mask_dev((uint64_t)t0 + c, nwords, tail_mask);
     }
-    out[t0 + c] = res & valid_mask_dev(t0 + c, nwords, tail_mask);
   }
 }
 
@@ -437,8 +588,8 @@ uint32_t grid_cap(uint64_t want, uint32_t cap) {
   return want > cap ? cap : (uint32_t)want;
 }
 
-typedef void (*TileFn)(const RleDesc*, uint32_t, const uint64_t* const*, uint32_t, uint64_t, uint64_t,
-                       uint32_t, uint64_t*, int*);
+typedef void (*TileFn)(const RleDesc*, uint32_t, const uint64_t* const*, uint32_t, uint32_t, uint64_t,
+                       uint32_t, uint32_t, uint64_t*, int*);
 
 TileFn pick_tile(int K) {
   switch (K) {
@@ -463,7 +614,8 @@ size_t rle_tile_lds_bytes(int K) { return (size_t)K * kTile * 8 + (size_t)(kTile
 
 hipError_t launch_rle_tile(const RleDesc* d_descs, uint32_t n_rle, const uint64_t* const* d_dense,
                            uint32_t n_dense, uint64_t nwords, uint64_t tail_mask, uint32_t theta,
-                           uint64_t* d_out, int* d_status, hipStream_t stream) {
+                           int num_cus, uint32_t tiles_per_group, uint64_t* d_out, int* d_status,
+                           hipStream_t stream) {
   const int K = dense_planes_for(n_rle + n_dense);
   TileFn fn = pick_tile(K);
   if (!fn) return hipErrorInvalidValue;
@@ -471,13 +623,25 @@ hipError_t launch_rle_tile(const RleDesc* d_descs, uint32_t n_rle, const uint64_
   if (tiles == 0) return hipSuccess;
   const size_t lds = rle_tile_lds_bytes(K);
   static bool attr_set[17] = {false};
+  static int resident[17] = {0};
   if (!attr_set[K]) {
     hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)lds);
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(fn), kTileThreads,
+                                                     lds) != hipSuccess || per_cu < 1)
+      per_cu = 1;
+    resident[K] = per_cu;
     attr_set[K] = true;
   }
-  hipLaunchKernelGGL(fn, dim3((uint32_t)tiles), dim3(kTileThreads), lds, stream, d_descs, n_rle, d_dense,
-                     n_dense, nwords, tail_mask, theta, d_out, d_status);
+  // by default one range of consecutive tiles per resident workgroup
+  const uint64_t slots = (uint64_t)(num_cus > 0 ? num_cus : 1) * (uint64_t)resident[K];
+  uint64_t per_group = tiles_per_group ? tiles_per_group : (tiles + slots - 1) / slots;
+  if (per_group > tiles) per_group = tiles;
+  const uint64_t ranges = (tiles + per_group - 1) / per_group;
+  const uint64_t grid = (ranges + kXcds - 1) / kXcds * kXcds;
+  hipLaunchKernelGGL(fn, dim3((uint32_t)grid), dim3(kTileThreads), lds, stream, d_descs, n_rle, d_dense,
+                     n_dense, (uint32_t)nwords, tail_mask, theta, (uint32_t)per_group, d_out, d_status);
   return hipGetLastError();
 }
 

@@ -46,9 +46,12 @@ namespace {
 // Validate compressed inputs; counts those without an index.
 tq_status check_rle_inputs(const tq_rle* inputs, uint32_t n, uint64_t nwords, uint32_t* missing_index) {
   *missing_index = 0;
+  // the tile kernel keeps word positions in 32 bits
+  if (nwords >= (1ull << 31)) return TQ_EINVAL;
   for (uint32_t j = 0; j < n; ++j) {
     const tq_rle& x = inputs[j];
     if (nwords > 0 && (!x.words || x.n_words == 0)) return TQ_EINVAL;
+    if (x.n_words > kRleMaxWords) return TQ_EINVAL;
     if (((uintptr_t)x.words & 7) || ((uintptr_t)x.index & 7)) return TQ_EINVAL;
     if (!x.index) ++*missing_index;
   }
@@ -104,7 +107,8 @@ tq_status run_rle_tiles(tq_ctx* ctx, const tq_rle* inputs, uint32_t n_rle, const
   }
   st = record_hip(ctx, launch_rle_tile(reinterpret_cast<const RleDesc*>(d_desc), n_rle,
                                        reinterpret_cast<const uint64_t* const*>(d_dense), n_dense, nw, tmask,
-                                       theta, d_dense_out, ctx->d_status, stream));
+                                       theta, ctx->num_cus, ctx->rle_tiles, d_dense_out, ctx->d_status,
+                                       stream));
   blob_used(ctx, bd, stream);
   if (bp) blob_used(ctx, bp, stream);
   return st;

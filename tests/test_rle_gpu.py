@@ -238,6 +238,11 @@ def test_threshold_rle_capacity_and_format(ctx):
     # host-side argument errors
     assert tq.raw_threshold_rle(ctx, [], r, 1, out.data_ptr(), 10, ln.data_ptr()) == tq.TQ_EINVAL
     assert tq.raw_threshold_rle(ctx, inputs, r, 1, out.data_ptr(), 10, 0) == tq.TQ_EINVAL
+    # size limits: bitmaps of 2^31 words or more, streams longer than 2^32 - 1024 words
+    huge = [(inputs[0][0], inputs[0][1], None)]
+    assert tq.raw_threshold_rle(ctx, huge, 64 << 31, 1, out.data_ptr(), 10, ln.data_ptr()) == tq.TQ_EINVAL
+    long_stream = [(inputs[0][0], (1 << 32) - 1023, None)]
+    assert tq.raw_threshold_rle(ctx, long_stream, r, 1, out.data_ptr(), 10, ln.data_ptr()) == tq.TQ_EINVAL
 
 
 @pytest.mark.parametrize("n_rle,n_dense", [(3, 2), (0, 4), (20, 20), (1, 0)])
@@ -297,8 +302,8 @@ def test_rle_config_full_size(ctx):
 
 @pytest.mark.parametrize("n", [70, 150])
 def test_threshold_rle_many_dirty_words(ctx, n):
-    """Inputs dirty almost everywhere: undecided columns have more dirty words
-    than the on-chip counters hold, so tiles keep their counters in memory."""
+    """Inputs dirty almost everywhere: nearly every column is undecided after
+    the fills and its counter receives a literal word from most inputs."""
     r = 64 * 1100 + 5
     dense = markov_bitmaps(500 + n, n, r, 2.0, 2.0)
     inputs, keep = rle_inputs(ctx, dense, r)
@@ -314,3 +319,68 @@ def test_threshold_rle_many_dirty_words(ctx, n):
     tq.tq_threshold_hybrid(ctx, inputs[:half], [pool[j] for j in range(n - half)], r, n // 2, out)
     assert tq.tq_ctx_check(ctx) == 0
     assert np.array_equal(to_host(out), oracle.threshold(dense, r, n // 2))
+
+
+# ------------------------------------------------ tile ranges per workgroup
+@pytest.fixture
+def tiles_option(ctx):
+    yield lambda v: tq.raw_set_option(ctx, tq.TQ_OPTION_RLE_TILES, v)
+    tq.tq_set_option(ctx, tq.TQ_OPTION_RLE_TILES, 0)
+
+
+def test_tiles_option_range(ctx, tiles_option):
+    assert tiles_option(-1) == tq.TQ_EINVAL
+    assert tiles_option((1 << 20) + 1) == tq.TQ_EINVAL
+    assert tiles_option(1 << 20) == tq.TQ_OK
+    assert tiles_option(0) == tq.TQ_OK
+
+
+@pytest.mark.parametrize("tiles", [1, 2, 3, 7, 1 << 20, 0])
+def test_tile_ranges(ctx, tiles_option, tiles):
+    """A workgroup that walks several tiles in a row carries every stream's
+    position from one tile to the next; any range length, a ragged last
+    range and a ragged last tile give the oracle's result, with and without
+    checkpoint indexes, and for hybrid queries."""
+    r = 64 * STRIDE * 9 + 37                      # 10 tiles, the last one short
+    n = 24
+    dense = markov_bitmaps(700, n, r, 40.0, 900.0)
+    sp = special_bitmaps(r)
+    dense[0], dense[1], dense[2] = sp[2], sp[4], sp[3]
+    assert tiles_option(tiles) == tq.TQ_OK
+    for with_index in (True, False):
+        inputs, keep = rle_inputs(ctx, dense, r, with_index=with_index)
+        for theta in (1, 2, 8, n - 1, n):
+            want_dense = oracle.threshold(dense, r, theta)
+            dout = empty_words((r + 63) // 64)
+            tq.tq_threshold_rle_dense(ctx, inputs, r, theta, dout)
+            assert tq.tq_ctx_check(ctx) == 0
+            assert np.array_equal(to_host(dout), want_dense), (with_index, theta)
+            want = oracle.rle_encode(want_dense, r)
+            cap = tq.tq_rle_max_words(r)
+            out = empty_words(cap)
+            ln = torch.zeros(1, dtype=torch.int64, device="cuda")
+            tq.tq_threshold_rle(ctx, inputs, r, theta, out, cap, ln)
+            assert tq.tq_ctx_check(ctx) == 0
+            assert np.array_equal(to_host(out)[:int(ln.item())], want), (with_index, theta)
+    inputs, keep = rle_inputs(ctx, dense[:10], r)
+    pool = dev_pool(dense[10:])
+    out = empty_words((r + 63) // 64)
+    tq.tq_threshold_hybrid(ctx, inputs, [pool[j] for j in range(n - 10)], r, 9, out)
+    assert tq.tq_ctx_check(ctx) == 0
+    assert np.array_equal(to_host(out), oracle.threshold(dense, r, 9))
+
+
+@pytest.mark.parametrize("tiles", [3, 0])
+def test_more_inputs_than_lanes(ctx, tiles_option, tiles):
+    """600 RLE inputs: a workgroup has 512 lanes, so the inputs past the first
+    512 enter each tile through their checkpoint index."""
+    r = 64 * STRIDE * 5 + 3
+    n = 600
+    dense = markov_bitmaps(800, n, r, 50.0, 2000.0)
+    assert tiles_option(tiles) == tq.TQ_OK
+    inputs, keep = rle_inputs(ctx, dense, r)
+    for theta in (1, 2, 30, 300, n):
+        out = empty_words((r + 63) // 64)
+        tq.tq_threshold_rle_dense(ctx, inputs, r, theta, out)
+        assert tq.tq_ctx_check(ctx) == 0
+        assert np.array_equal(to_host(out), oracle.threshold(dense, r, theta)), theta
