@@ -55,6 +55,10 @@ def lib():
         L.oracle_rle_encode.restype = U64
         L.oracle_run_count.argtypes = [P, U64]
         L.oracle_run_count.restype = U64
+        L.oracle_count.argtypes = [P, U64]
+        L.oracle_count.restype = U64
+        L.oracle_weighted_threshold.argtypes = [P, U32, P, U64, U64, P]
+        L.oracle_weighted_threshold.restype = ctypes.c_int
         for f in ("oracle_threshold_cols", "oracle_symmetric_cols", "oracle_threshold",
                   "oracle_symmetric", "oracle_rle_decode"):
             getattr(L, f).restype = ctypes.c_int
@@ -100,6 +104,36 @@ def symmetric(bitmaps, r_bits: int, truth) -> np.ndarray:
     if rc:
         raise ValueError("oracle_symmetric: %d" % rc)
     return out
+
+
+def weighted_threshold(bitmaps, weights, r_bits: int, theta: int) -> np.ndarray:
+    """Output bitmap of sum of weights[j] * bit_j(p) >= theta."""
+    n = len(bitmaps)
+    wt = np.ascontiguousarray(np.asarray(weights, dtype=np.uint32))
+    assert wt.size == n
+    arrs, ptrs = _ptr_array(bitmaps)
+    out = np.zeros(nwords(r_bits), dtype=np.uint64)
+    rc = lib().oracle_weighted_threshold(ptrs, n, wt.ctypes.data, r_bits, theta, out.ctypes.data)
+    if rc:
+        raise ValueError("oracle_weighted_threshold: %d" % rc)
+    return out
+
+
+def count(words, r_bits: int) -> int:
+    """Number of set positions p < r_bits of a bitmap."""
+    w = _u64(words)
+    assert w.size >= nwords(r_bits)
+    return int(lib().oracle_count(w.ctypes.data, r_bits))
+
+
+def consume(result, r_bits: int, filt=None):
+    """Consumers of a result bitmap (abstract and introduction: the result
+    is again a bitmap, combined with other criteria by AND, or counted):
+    returns (result AND filt, number of set positions below r_bits)."""
+    out = _u64(result).copy()
+    if filt is not None:
+        out &= _u64(filt)[:out.size]
+    return out, count(out, r_bits)
 
 
 def threshold_cols(words: np.ndarray, col_index, r_bits: int, theta: int) -> np.ndarray:

@@ -148,6 +148,41 @@ int oracle_symmetric(const uint64_t* const* bitmaps, uint32_t n, uint64_t r_bits
   return ORACLE_OK;
 }
 
+/*
+ * Weighted threshold (section 2.3: inputs may carry positive integer
+ * weights): output bit p is 1 iff the sum of weights[j] over the inputs j
+ * that have bit p set is at least theta.
+ */
+int oracle_weighted_threshold(const uint64_t* const* bitmaps, uint32_t n, const uint32_t* weights,
+                              uint64_t r_bits, uint64_t theta, uint64_t* out) {
+  if (n == 0) return ORACLE_EINVAL;
+  uint64_t nw = words_for_bits(r_bits);
+#pragma omp parallel for schedule(static)
+  for (int64_t w = 0; w < (int64_t)nw; ++w) {
+    uint64_t sum[64];
+    uint64_t mask = valid_mask((uint64_t)w, r_bits);
+    for (int b = 0; b < 64; ++b) sum[b] = 0;
+    for (uint32_t j = 0; j < n; ++j) {
+      uint64_t x = bitmaps[j][w] & mask;
+      for (int b = 0; b < 64; ++b)
+        if ((x >> b) & 1) sum[b] += weights[j];
+    }
+    uint64_t o = 0;
+    for (int b = 0; b < 64; ++b)
+      if (sum[b] >= theta) o |= (uint64_t)1 << b;
+    out[w] = o & mask;
+  }
+  return ORACLE_OK;
+}
+
+/* Number of positions p < r whose bit is set (the cardinality of a result
+ * bitmap, counted one position at a time). */
+uint64_t oracle_count(const uint64_t* words, uint64_t r_bits) {
+  uint64_t c = 0;
+  for (uint64_t p = 0; p < r_bits; ++p) c += (words[p / 64] >> (p % 64)) & 1;
+  return c;
+}
+
 /* ------------------------------------------------------------------ RLE */
 
 static uint64_t marker_fill(uint64_t m) { return m & 1; }

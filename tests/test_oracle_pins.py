@@ -318,3 +318,80 @@ def test_run_count(orc):
     assert orc.run_count(np.zeros(2, dtype=np.uint64), 100) == 1
     alt = np.full(2, np.uint64(0xAAAAAAAAAAAAAAAA))
     assert orc.run_count(alt, 128) == 128
+
+
+# -------------------------------------------- consumers of a result bitmap
+@pytest.mark.parametrize("n", [1, 3, 6, 10])
+def test_count_closed_form(orc, n):
+    """On the exhaustive fixture every combination of the N inputs appears
+    once, so |T_theta| = sum_{c >= theta} C(N, c), and ANDed with input 0 (a
+    filter) sum_{c >= theta} C(N-1, c-1); a symmetric f counts
+    sum_c f(c) C(N, c)."""
+    from math import comb
+    r = 1 << n
+    bm = [tqgen.exhaustive_words(j, n) for j in range(n)]
+    for theta in range(0, n + 2):
+        res = orc.threshold(bm, r, theta)
+        _, cnt = orc.consume(res, r)
+        assert cnt == sum(comb(n, c) for c in range(theta, n + 1)), theta
+        _, cnt_f = orc.consume(res, r, bm[0])
+        assert cnt_f == sum(comb(n - 1, c - 1) for c in range(max(theta, 1), n + 1)), theta
+    rng = np.random.default_rng(n)
+    f = rng.integers(0, 2, n + 1).astype(np.uint8)
+    _, cnt = orc.consume(orc.symmetric(bm, r, f), r)
+    assert cnt == sum(int(f[c]) * comb(n, c) for c in range(n + 1))
+
+
+def test_count_against_numpy(orc):
+    """Positions below r only, against numpy's bit unpacking; the filter
+    against numpy's AND."""
+    rng = np.random.default_rng(33)
+    for r in (1, 63, 64, 65, 1000, 64 * 77 + 5):
+        a, f = rand_bitmaps(rng, 2, r, p=0.4)
+        got, cnt = orc.consume(a, r, f)
+        assert np.array_equal(got, a & f)
+        assert cnt == int(unpack(a & f, r).sum()), r
+        assert orc.count(a, r) == int(unpack(a, r).sum())
+    assert orc.count(np.zeros(1, dtype=np.uint64), 0) == 0
+
+
+# -------------------------------------------------------- weighted inputs
+def subset_weight_counts(weights):
+    """Number of subsets of the inputs with each total weight (a DP over the
+    weights, independent of any bitmap)."""
+    tot = sum(weights)
+    ways = [0] * (tot + 1)
+    ways[0] = 1
+    for w in weights:
+        for s in range(tot, w - 1, -1):
+            ways[s] += ways[s - w]
+    return ways
+
+
+@pytest.mark.parametrize("weights", [[1], [3, 1, 2], [5, 5, 1, 7, 2, 2], [1, 2, 4, 8, 16, 32, 64, 100]])
+def test_weighted_exhaustive(orc, weights):
+    """Weighted threshold on the exhaustive fixture: the number of positions
+    with weight sum >= theta equals the number of input subsets of weight >=
+    theta; each position's bit equals the weight sum of its bits."""
+    n = len(weights)
+    r = 1 << n
+    bm = [tqgen.exhaustive_words(j, n) for j in range(n)]
+    ways = subset_weight_counts(weights)
+    wsum_at = np.array([sum(w for j, w in enumerate(weights) if (p >> j) & 1) for p in range(r)])
+    for theta in sorted({0, 1, 2, max(weights), sum(weights) // 2, sum(weights), sum(weights) + 1}):
+        res = orc.weighted_threshold(bm, weights, r, theta)
+        assert orc.count(res, r) == sum(ways[theta:]), theta
+        assert np.array_equal(unpack(res, r), (wsum_at >= theta).astype(np.uint8)), theta
+
+
+def test_weighted_equals_replication(orc):
+    """Section 2.3: a positive integer weight w is the same as w copies of
+    the input (the unweighted oracle on replicated inputs); weight 0 drops
+    the input."""
+    rng = np.random.default_rng(18)
+    r = 64 * 40 + 9
+    bm = rand_bitmaps(rng, 6, r, p=0.35)
+    w = [4, 0, 1, 3, 2, 1]
+    rep = [b for b, k in zip(bm, w) for _ in range(k)]
+    for t in range(0, sum(w) + 2):
+        assert np.array_equal(orc.weighted_threshold(bm, w, r, t), orc.threshold(rep, r, t)), t
