@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-consumers", action="store_true",
+                    help="skip the fused-consumer timings (profiling runs of the roofline kernel)")
     ap.add_argument("--prune", type=int, default=1,
                     help="threshold pruning in the timed pass (the roofline pass never prunes)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -501,6 +503,37 @@ def bench_selector(args):
     }
 
 
+def time_consumers(tq, ctx, rows, r, nw, stream, steps):
+    """Fused consumers of a result (threshold 16): the plain query, the query
+    with an AND filter and a count in the same pass, and the count alone."""
+    import torch
+    theta = 16
+    out = torch.empty(nw, dtype=torch.int64, device=rows[0].device)
+    cnt = torch.zeros(1, dtype=torch.int64, device=rows[0].device)
+    filt = rows[1]
+    runs = {
+        "threshold_ms": lambda: tq.tq_threshold(ctx, rows, r, theta, out, stream),
+        "threshold_and_filter_and_count_ms": lambda: tq.tq_threshold_fused(ctx, rows, r, theta, filt, out, cnt,
+                                                                           stream),
+        "count_only_ms": lambda: tq.tq_threshold_fused(ctx, rows, r, theta, None, None, cnt, stream),
+    }
+    res = {"theta": theta}
+    with torch.cuda.stream(stream):
+        for name, fn in runs.items():
+            fn()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(steps):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            res[name] = round(e0.elapsed_time(e1) / steps, 4)
+    if tq.tq_ctx_check(ctx, stream) != 0:
+        raise RuntimeError("device error in the consumer timings")
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -589,6 +622,7 @@ def main():
     # the roofline: every input word read (no pruning), so algorithmic bytes are the bytes moved
     _, kernel_ms = timed_pass(0)
     tq.tq_set_option(ctx, tq.TQ_OPTION_PRUNE, 1)
+    consumers = None if args.no_consumers else time_consumers(tq, ctx, rows, r, nw, stream, args.steps)
     mean_kernel_s = sum(kernel_ms) / len(kernel_ms) / 1e3
     in_bytes_query = n * nw * 8
     out_bytes_query = nw * 8
@@ -622,6 +656,7 @@ def main():
         "per_query_ms_unpruned": [round(sum(kernel_ms[i::len(queries)]) / args.steps, 4)
                                   for i in range(len(queries))],
         "prune": bool(args.prune),
+        "consumers": consumers,
     }
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(rows, n, nw, r, queries, args.cpu_seconds)

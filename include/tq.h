@@ -124,6 +124,29 @@ tq_status tq_threshold(tq_ctx* ctx, const uint64_t* const* ptrs, uint32_t n, uin
 tq_status tq_symmetric(tq_ctx* ctx, const uint64_t* const* ptrs, uint32_t n, uint64_t r_bits,
                        const uint64_t* h_truth, uint64_t* d_out, hipStream_t stream);
 
+/*
+ * Fused consumers of the result (the result of a threshold or symmetric
+ * query is again a bitmap, to be combined with other criteria by AND and
+ * friends or counted: abstract and introduction).  In the same pass:
+ *   R = T_theta(inputs)  (or f(count) for the symmetric form)  AND  filter,
+ *   d_out    = R                               (nullable: R is not stored),
+ *   *d_count = number of positions p < r_bits with bit p of R set
+ *                                              (nullable; one device uint64).
+ * d_filter: ceil(r_bits/64) device words, or NULL for no filter; it may be
+ * d_out itself (in place) but must not overlap it otherwise; it may alias
+ * the inputs.  At least one of d_out and d_count is given; d_count must not
+ * lie inside d_out.  The count uses the context's workspace (one uint32 per
+ * 64 output words): calls on one context that use workspace must be ordered.
+ * Other arguments, special cases and errors as for tq_threshold / tq_symmetric;
+ * r_bits == 0 sets *d_count = 0.
+ */
+tq_status tq_threshold_fused(tq_ctx* ctx, const uint64_t* const* ptrs, uint32_t n, uint64_t r_bits,
+                             uint32_t theta, const uint64_t* d_filter, uint64_t* d_out, uint64_t* d_count,
+                             hipStream_t stream);
+tq_status tq_symmetric_fused(tq_ctx* ctx, const uint64_t* const* ptrs, uint32_t n, uint64_t r_bits,
+                             const uint64_t* h_truth, const uint64_t* d_filter, uint64_t* d_out,
+                             uint64_t* d_count, hipStream_t stream);
+
 /* ------------------------------------------------------------------------
  * Run-length-encoded bitmaps (section 2.1, word-aligned RLE with markers that
  * carry both a fill-run length and a dirty-word count, as in EWAH).

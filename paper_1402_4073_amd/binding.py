@@ -56,6 +56,8 @@ def _load():
         "tq_set_option": (_INT, [_P, _INT, ctypes.c_int64]),
         "tq_threshold": (_INT, [_P, _P, _U32, _U64, _U32, _P, _P]),
         "tq_symmetric": (_INT, [_P, _P, _U32, _U64, _P, _P, _P]),
+        "tq_threshold_fused": (_INT, [_P, _P, _U32, _U64, _U32, _P, _P, _P, _P]),
+        "tq_symmetric_fused": (_INT, [_P, _P, _U32, _U64, _P, _P, _P, _P, _P]),
         "tq_rle_max_words": (_U64, [_U64]),
         "tq_rle_index_words": (_U64, [_U64]),
         "tq_rle_encode": (_INT, [_P, _P, _U64, _P, _U64, _P, _P, _P]),
@@ -195,6 +197,32 @@ def tq_symmetric(ctx: int, inputs, r_bits: int, truth, out, stream=None) -> None
     tw = _u64_host(truth_words(truth))
     _check(_lib.tq_symmetric(ctx, ptrs, len(inputs), r_bits, tw, _ptr(out), _stream(stream)),
            "tq_symmetric")
+
+
+def _optr(t):
+    """Device pointer of an optional tensor (None -> NULL)."""
+    return None if t is None else _ptr(t)
+
+
+def tq_threshold_fused(ctx: int, inputs, r_bits: int, theta: int, filt=None, out=None, count=None,
+                       stream=None) -> None:
+    """out = T_theta(inputs) AND filt; count[0] = popcount(out) (each optional)."""
+    ptrs = ptr_array(inputs)
+    _check(_lib.tq_threshold_fused(ctx, ptrs, len(inputs), r_bits, theta, _optr(filt), _optr(out), _optr(count),
+                                   _stream(stream)), "tq_threshold_fused")
+
+
+def tq_symmetric_fused(ctx: int, inputs, r_bits: int, truth, filt=None, out=None, count=None,
+                       stream=None) -> None:
+    ptrs = ptr_array(inputs)
+    tw = _u64_host(truth_words(truth))
+    _check(_lib.tq_symmetric_fused(ctx, ptrs, len(inputs), r_bits, tw, _optr(filt), _optr(out), _optr(count),
+                                   _stream(stream)), "tq_symmetric_fused")
+
+
+def raw_threshold_fused(ctx: int, ptrs, n: int, r_bits: int, theta: int, filt_ptr, out_ptr, count_ptr,
+                        stream=None) -> int:
+    return _lib.tq_threshold_fused(ctx, ptrs, n, r_bits, theta, filt_ptr, out_ptr, count_ptr, _stream(stream))
 
 
 def raw_threshold(ctx: int, ptrs, n: int, r_bits: int, theta: int, out_ptr: int, stream=None) -> int:

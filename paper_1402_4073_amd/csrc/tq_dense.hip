@@ -35,7 +35,7 @@ using namespace csa;
 template <int K, int WPL, int S, int G>
 __global__ __launch_bounds__(64 * S * G) void dense_kernel(
     const uint64_t* const* __restrict__ ptrs, uint32_t n, uint64_t nwords, uint64_t tail_mask,
-    uint64_t* __restrict__ out, EpiParams epi) {
+    uint64_t* __restrict__ out, EpiParams epi, Sink sink) {
   extern __shared__ uint64_t lds[];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -114,25 +114,42 @@ __global__ __launch_bounds__(64 * S * G) void dense_kernel(
   }
 
   if (base >= nwords) return;
-  const Vec<WPL> r = epilogue<K, WPL>(P, epi, n, lds_table);
-  if (base + 64 * WPL <= nwords) {
-    Vec<WPL> v = r;
+  Vec<WPL> v = epilogue<K, WPL>(P, epi, n, lds_table);
+  const bool full = base + 64 * WPL <= nwords;
+#pragma unroll
+  for (int i = 0; i < WPL; ++i) {
+    if (w + i == nwords - 1) v.w[i] &= tail_mask;
+    if (!full && w + i >= nwords) v.w[i] = 0;
+  }
+  // fused consumers: AND with a filter bitmap, popcount of the result
+  if (sink.filter) {
 #pragma unroll
     for (int i = 0; i < WPL; ++i)
-      if (w + i == nwords - 1) v.w[i] &= tail_mask;
-    if constexpr (WPL == 2) {
-      u64x2 t;
-      t[0] = v.w[0];
-      t[1] = v.w[1];
-      __builtin_nontemporal_store(t, reinterpret_cast<u64x2*>(out + w));
+      if (full || w + i < nwords) v.w[i] &= __builtin_nontemporal_load(sink.filter + w + i);
+  }
+  if (out) {
+    if (full) {
+      if constexpr (WPL == 2) {
+        u64x2 t;
+        t[0] = v.w[0];
+        t[1] = v.w[1];
+        __builtin_nontemporal_store(t, reinterpret_cast<u64x2*>(out + w));
+      } else {
+        __builtin_nontemporal_store(v.w[0], out + w);
+      }
     } else {
-      __builtin_nontemporal_store(v.w[0], out + w);
-    }
-  } else {
 #pragma unroll
-    for (int i = 0; i < WPL; ++i) {
-      if (w + i < nwords) out[w + i] = (w + i == nwords - 1) ? (r.w[i] & tail_mask) : r.w[i];
+      for (int i = 0; i < WPL; ++i)
+        if (w + i < nwords) out[w + i] = v.w[i];
     }
+  }
+  if (sink.partial) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int i = 0; i < WPL; ++i) c += (uint32_t)__popcll(v.w[i]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+    if (lane == 0) sink.partial[(uint64_t)blockIdx.x * G + g] = c;
   }
 }
 
@@ -143,7 +160,54 @@ __global__ void fill_kernel(uint64_t* __restrict__ out, uint64_t nwords, uint64_
     out[w] = (w == nwords - 1) ? (value & tail_mask) : value;
 }
 
-typedef void (*DenseFn)(const uint64_t* const*, uint32_t, uint64_t, uint64_t, uint64_t*, EpiParams);
+constexpr int kFillBlock = 256;
+
+// one word per thread: out = value AND filter, popcount per block
+__global__ __launch_bounds__(kFillBlock) void fill_sink_kernel(uint64_t* __restrict__ out, uint64_t nwords,
+                                                               uint64_t value, uint64_t tail_mask, Sink sink) {
+  __shared__ uint32_t wave_sum[kFillBlock / 64];
+  const uint64_t w = (uint64_t)blockIdx.x * kFillBlock + threadIdx.x;
+  uint64_t v = 0;
+  if (w < nwords) {
+    v = (w == nwords - 1) ? (value & tail_mask) : value;
+    if (sink.filter) v &= sink.filter[w];
+    if (out) out[w] = v;
+  }
+  if (sink.partial) {
+    uint32_t c = (uint32_t)__popcll(v);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+    if ((threadIdx.x & 63) == 0) wave_sum[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t t = 0;
+#pragma unroll
+      for (int i = 0; i < kFillBlock / 64; ++i) t += wave_sum[i];
+      sink.partial[blockIdx.x] = t;
+    }
+  }
+}
+
+constexpr int kReduceBlock = 1024;
+
+__global__ __launch_bounds__(kReduceBlock) void count_reduce_kernel(const uint32_t* __restrict__ partial,
+                                                                    uint64_t m, uint64_t* __restrict__ count) {
+  __shared__ uint64_t wave_sum[kReduceBlock / 64];
+  uint64_t c = 0;
+  for (uint64_t i = threadIdx.x; i < m; i += kReduceBlock) c += partial[i];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+  if ((threadIdx.x & 63) == 0) wave_sum[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t t = 0;
+#pragma unroll
+    for (int i = 0; i < kReduceBlock / 64; ++i) t += wave_sum[i];
+    *count = t;
+  }
+}
+
+typedef void (*DenseFn)(const uint64_t* const*, uint32_t, uint64_t, uint64_t, uint64_t*, EpiParams, Sink);
 
 // Instantiated shapes: one word per lane with S in {1,2,4,8} and G = 1 (the
 // default family), plus two-word lanes and four-wave workgroups for the tuner.
@@ -214,9 +278,14 @@ DenseConfig choose_dense_config(uint32_t n, uint64_t nwords, bool aligned16, int
   return c;
 }
 
+uint64_t dense_groups(const DenseConfig& cfg, uint64_t nwords) {
+  const uint64_t cols = (uint64_t)64 * cfg.wpl;
+  return (nwords + cols - 1) / cols;
+}
+
 hipError_t launch_dense(const DenseConfig& cfg, const uint64_t* const* d_ptrs, uint32_t n,
                         uint64_t nwords, uint64_t tail_mask, uint64_t* d_out, const EpiParams& epi,
-                        hipStream_t stream) {
+                        hipStream_t stream, const Sink& sink) {
   DenseFn fn = pick(cfg.K, cfg.wpl, cfg.split, cfg.groups);
   if (!fn) return hipErrorInvalidValue;
   const int G = cfg.groups;
@@ -228,7 +297,7 @@ hipError_t launch_dense(const DenseConfig& cfg, const uint64_t* const* d_ptrs, u
   if (epi.kind == EPI_TABLE) lds += ((size_t)epi.table_words + 1) / 2 * 8;
   if (cfg.split > 1) lds += (size_t)G * (cfg.split / 2) * cfg.K * cfg.wpl * 64 * 8;
   hipLaunchKernelGGL(fn, dim3((uint32_t)blocks), dim3(64 * cfg.split * G), lds, stream, d_ptrs, n,
-                     nwords, tail_mask, d_out, epi);
+                     nwords, tail_mask, d_out, epi, sink);
   return hipGetLastError();
 }
 
@@ -239,6 +308,23 @@ hipError_t launch_fill(uint64_t* d_out, uint64_t nwords, uint64_t value, uint64_
   if (blocks > 16384) blocks = 16384;
   hipLaunchKernelGGL(fill_kernel, dim3((uint32_t)blocks), dim3(256), 0, stream, d_out, nwords, value,
                      tail_mask);
+  return hipGetLastError();
+}
+
+uint64_t fill_groups(uint64_t nwords) { return (nwords + kFillBlock - 1) / kFillBlock; }
+
+hipError_t launch_fill_sink(uint64_t* d_out, uint64_t nwords, uint64_t value, uint64_t tail_mask,
+                            const Sink& sink, hipStream_t stream) {
+  const uint64_t blocks = fill_groups(nwords);
+  if (blocks == 0) return hipSuccess;
+  if (blocks > 0x7FFFFFFFull) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(fill_sink_kernel, dim3((uint32_t)blocks), dim3(kFillBlock), 0, stream, d_out, nwords, value,
+                     tail_mask, sink);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_reduce(const uint32_t* d_partial, uint64_t m, uint64_t* d_count, hipStream_t stream) {
+  hipLaunchKernelGGL(count_reduce_kernel, dim3(1), dim3(kReduceBlock), 0, stream, d_partial, m, d_count);
   return hipGetLastError();
 }
 

@@ -314,29 +314,67 @@ namespace {
 
 // Validate the pointer array and the output; returns whether every buffer is 16-byte aligned.
 tq_status check_dense_args(const uint64_t* const* ptrs, uint32_t n, uint64_t r_bits, const uint64_t* d_out,
-                           bool* aligned16) {
+                           bool* aligned16, bool out_optional = false) {
   if (!ptrs || n == 0 || n > TQ_MAX_INPUTS) return TQ_EINVAL;
   const uint64_t nw = words_for_bits(r_bits);
-  if (r_bits > 0 && !d_out) return TQ_EINVAL;
+  if (r_bits > 0 && !d_out && !out_optional) return TQ_EINVAL;
   uintptr_t any = (uintptr_t)d_out;
   const uintptr_t o0 = (uintptr_t)d_out, o1 = o0 + nw * 8;
   for (uint32_t j = 0; j < n; ++j) {
     const uintptr_t p = (uintptr_t)ptrs[j];
     if (!p || (p & 7)) return TQ_EINVAL;
     any |= p;
-    if (r_bits > 0 && p < o1 && o0 < p + nw * 8) return TQ_EINVAL;  // output overlaps an input
+    if (d_out && r_bits > 0 && p < o1 && o0 < p + nw * 8) return TQ_EINVAL;  // output overlaps an input
   }
   if ((uintptr_t)d_out & 7) return TQ_EINVAL;
   *aligned16 = (any & 15) == 0;
   return TQ_OK;
 }
 
+// Arguments of the fused consumers: the filter is nullable and may be the
+// output itself but must not overlap it otherwise; the count is nullable;
+// at least one of output and count is given.
+tq_status check_sink_args(uint64_t r_bits, const uint64_t* d_filter, const uint64_t* d_out,
+                          const uint64_t* d_count) {
+  if (!d_out && !d_count) return TQ_EINVAL;
+  if (((uintptr_t)d_filter & 7) || ((uintptr_t)d_count & 7)) return TQ_EINVAL;
+  const uint64_t nw = words_for_bits(r_bits);
+  if (d_filter && d_out && d_filter != d_out) {
+    const uintptr_t f0 = (uintptr_t)d_filter, o0 = (uintptr_t)d_out;
+    if (f0 < o0 + nw * 8 && o0 < f0 + nw * 8) return TQ_EINVAL;
+  }
+  if (d_count && d_out) {
+    const uintptr_t c0 = (uintptr_t)d_count, o0 = (uintptr_t)d_out;
+    if (c0 < o0 + nw * 8 && o0 < c0 + 8) return TQ_EINVAL;
+  }
+  return TQ_OK;
+}
+
 tq_status run_dense(tq_ctx* ctx, const uint64_t* const* ptrs, uint32_t n, uint64_t r_bits,
-                    const SymPlan& plan, uint64_t* d_out, hipStream_t stream, bool aligned16) {
+                    const SymPlan& plan, uint64_t* d_out, hipStream_t stream, bool aligned16,
+                    const uint64_t* d_filter = nullptr, uint64_t* d_count = nullptr) {
   const uint64_t nw = words_for_bits(r_bits);
   const uint64_t tmask = tail_mask_for(r_bits);
-  if (nw == 0) return TQ_OK;
-  if (plan.constant) return record_hip(ctx, launch_fill(d_out, nw, plan.const_word, tmask, stream));
+  if (nw == 0) return d_count ? record_hip(ctx, launch_set_u64(d_count, 0, stream)) : TQ_OK;
+  const bool fused = d_filter || d_count;
+  Sink sink;
+  sink.filter = d_filter;
+  if (plan.constant) {
+    if (!fused) return record_hip(ctx, launch_fill(d_out, nw, plan.const_word, tmask, stream));
+    const uint64_t slots = fill_groups(nw);
+    if (d_count) {
+      sink.partial = static_cast<uint32_t*>(workspace(ctx, slots * sizeof(uint32_t)));
+      if (!sink.partial) return TQ_ENOMEM;
+    }
+    tq_status st = record_hip(ctx, launch_fill_sink(d_out, nw, plan.const_word, tmask, sink, stream));
+    if (st == TQ_OK && d_count) st = record_hip(ctx, launch_count_reduce(sink.partial, slots, d_count, stream));
+    return st;
+  }
+  const DenseConfig cfg = choose_dense_config(n, nw, aligned16, ctx->num_cus);
+  if (d_count) {
+    sink.partial = static_cast<uint32_t*>(workspace(ctx, dense_groups(cfg, nw) * sizeof(uint32_t)));
+    if (!sink.partial) return TQ_ENOMEM;
+  }
   Blob* pb = nullptr;
   const void* d_ptrs = blob_get(ctx, reinterpret_cast<const uint64_t*>(ptrs), n, stream, &pb);
   if (!d_ptrs) return TQ_EDEVICE;
@@ -350,9 +388,10 @@ tq_status run_dense(tq_ctx* ctx, const uint64_t* const* ptrs, uint32_t n, uint64
     if (!d_t) return TQ_EDEVICE;
     epi.table = reinterpret_cast<const uint32_t*>(d_t);
   }
-  const DenseConfig cfg = choose_dense_config(n, nw, aligned16, ctx->num_cus);
   tq_status st = record_hip(ctx, launch_dense(cfg, reinterpret_cast<const uint64_t* const*>(d_ptrs), n, nw,
-                                              tmask, d_out, epi, stream));
+                                              tmask, d_out, epi, stream, sink));
+  if (st == TQ_OK && d_count)
+    st = record_hip(ctx, launch_count_reduce(sink.partial, dense_groups(cfg, nw), d_count, stream));
   blob_used(ctx, pb, stream);
   if (tb) blob_used(ctx, tb, stream);
   return st;
@@ -378,6 +417,30 @@ tq_status tq_symmetric(tq_ctx* ctx, const uint64_t* const* ptrs, uint32_t n, uin
   tq_status st = check_dense_args(ptrs, n, r_bits, d_out, &a16);
   if (st != TQ_OK) return st;
   return run_dense(ctx, ptrs, n, r_bits, plan_symmetric(n, h_truth), d_out, stream, a16);
+}
+
+tq_status tq_threshold_fused(tq_ctx* ctx, const uint64_t* const* ptrs, uint32_t n, uint64_t r_bits,
+                             uint32_t theta, const uint64_t* d_filter, uint64_t* d_out, uint64_t* d_count,
+                             hipStream_t stream) {
+  if (!ctx) return TQ_EINVAL;
+  tq_status st = check_sink_args(r_bits, d_filter, d_out, d_count);
+  if (st != TQ_OK) return st;
+  bool a16 = false;
+  st = check_dense_args(ptrs, n, r_bits, d_out, &a16, true);
+  if (st != TQ_OK) return st;
+  return run_dense(ctx, ptrs, n, r_bits, plan_threshold(n, theta), d_out, stream, a16, d_filter, d_count);
+}
+
+tq_status tq_symmetric_fused(tq_ctx* ctx, const uint64_t* const* ptrs, uint32_t n, uint64_t r_bits,
+                             const uint64_t* h_truth, const uint64_t* d_filter, uint64_t* d_out,
+                             uint64_t* d_count, hipStream_t stream) {
+  if (!ctx || !h_truth) return TQ_EINVAL;
+  tq_status st = check_sink_args(r_bits, d_filter, d_out, d_count);
+  if (st != TQ_OK) return st;
+  bool a16 = false;
+  st = check_dense_args(ptrs, n, r_bits, d_out, &a16, true);
+  if (st != TQ_OK) return st;
+  return run_dense(ctx, ptrs, n, r_bits, plan_symmetric(n, h_truth), d_out, stream, a16, d_filter, d_count);
 }
 
 }  // extern "C"

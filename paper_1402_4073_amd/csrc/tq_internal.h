@@ -62,12 +62,32 @@ int dense_planes_for(uint32_t n);
 
 DenseConfig choose_dense_config(uint32_t n, uint64_t nwords, bool aligned16, int num_cus);
 
+// Consumers fused into the store of a result word: AND with a filter bitmap
+// (nullable) and per-column-group popcounts of the stored word (nullable;
+// one uint32 per column group, summed afterwards by launch_count_reduce).
+struct Sink {
+  const uint64_t* filter = nullptr;
+  uint32_t* partial = nullptr;
+};
+
+// Column groups (= partial slots) of a dense launch over nwords words.
+uint64_t dense_groups(const DenseConfig& cfg, uint64_t nwords);
+
 hipError_t launch_dense(const DenseConfig& cfg, const uint64_t* const* d_ptrs, uint32_t n,
                         uint64_t nwords, uint64_t tail_mask, uint64_t* d_out,
-                        const EpiParams& epi, hipStream_t stream);
+                        const EpiParams& epi, hipStream_t stream, const Sink& sink = Sink());
 
 hipError_t launch_fill(uint64_t* d_out, uint64_t nwords, uint64_t value, uint64_t tail_mask,
                        hipStream_t stream);
+
+// Constant result with consumers: out = value AND filter (tail cleared),
+// partial popcounts per 256-word block (fill_groups(nwords) slots).
+uint64_t fill_groups(uint64_t nwords);
+hipError_t launch_fill_sink(uint64_t* d_out, uint64_t nwords, uint64_t value, uint64_t tail_mask,
+                            const Sink& sink, hipStream_t stream);
+
+// *d_count = sum of partial[0..m)
+hipError_t launch_count_reduce(const uint32_t* d_partial, uint64_t m, uint64_t* d_count, hipStream_t stream);
 
 // -------------------------------------------------------------------- RLE
 // Device-side description of one compressed input (3 words, staged as a blob).
