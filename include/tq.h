@@ -238,6 +238,22 @@ tq_status tq_threshold_hybrid(tq_ctx* ctx, const tq_rle* rle_inputs, uint32_t n_
                               const uint64_t* const* dense_ptrs, uint32_t n_dense, uint64_t r_bits,
                               uint32_t theta, uint64_t* d_out, hipStream_t stream);
 
+/*
+ * Symmetric functions over compressed inputs (section 2.2 for the functions;
+ * the run cases of section 4.1 generalised: where k inputs are 1-fills and d
+ * are dirty, the count lies in [k, k+d], so f constant on that range decides
+ * the word from the markers alone, and otherwise f is evaluated on k plus the
+ * counted dirty bits).  h_truth as for tq_symmetric (n + 1 entries); other
+ * arguments, outputs and errors as for the threshold forms above.
+ */
+tq_status tq_symmetric_rle(tq_ctx* ctx, const tq_rle* inputs, uint32_t n, uint64_t r_bits, const uint64_t* h_truth,
+                           uint64_t* d_out, uint64_t out_cap_words, uint64_t* d_out_len, hipStream_t stream);
+tq_status tq_symmetric_rle_dense(tq_ctx* ctx, const tq_rle* inputs, uint32_t n, uint64_t r_bits,
+                                 const uint64_t* h_truth, uint64_t* d_out, hipStream_t stream);
+tq_status tq_symmetric_hybrid(tq_ctx* ctx, const tq_rle* rle_inputs, uint32_t n_rle,
+                              const uint64_t* const* dense_ptrs, uint32_t n_dense, uint64_t r_bits,
+                              const uint64_t* h_truth, uint64_t* d_out, hipStream_t stream);
+
 /* ------------------------------------------------------------------------
  * Batched queries: many threshold / symmetric queries of uneven N, r and
  * theta served by one persistent kernel launch, replayed from a graph.

@@ -66,6 +66,9 @@ def _load():
         "tq_threshold_rle": (_INT, [_P, _P, _U32, _U64, _U32, _P, _U64, _P, _P]),
         "tq_threshold_rle_dense": (_INT, [_P, _P, _U32, _U64, _U32, _P, _P]),
         "tq_threshold_hybrid": (_INT, [_P, _P, _U32, _P, _U32, _U64, _U32, _P, _P]),
+        "tq_symmetric_rle": (_INT, [_P, _P, _U32, _U64, _P, _P, _U64, _P, _P]),
+        "tq_symmetric_rle_dense": (_INT, [_P, _P, _U32, _U64, _P, _P, _P]),
+        "tq_symmetric_hybrid": (_INT, [_P, _P, _U32, _P, _U32, _U64, _P, _P, _P]),
         "tq_batch_submit": (_INT, [_P, _P, _U32, _U32, _P, ctypes.POINTER(_P)]),
         "tq_batch_poll": (_INT, [_P, ctypes.POINTER(_U32)]),
         "tq_batch_wait": (_INT, [_P]),
@@ -291,6 +294,29 @@ def tq_threshold_hybrid(ctx: int, rle_inputs, dense_inputs, r_bits: int, theta: 
     ptrs = ptr_array(dense_inputs)
     _check(_lib.tq_threshold_hybrid(ctx, arr, len(rle_inputs), ptrs, len(dense_inputs), r_bits, theta, _ptr(out),
                                     _stream(stream)), "tq_threshold_hybrid")
+
+
+def tq_symmetric_rle(ctx: int, inputs, r_bits: int, truth, out, out_cap: int, out_len, stream=None) -> None:
+    """truth: f(0..n) as 0/1 values."""
+    arr = rle_array(inputs)
+    tw = _u64_host(truth_words(truth))
+    _check(_lib.tq_symmetric_rle(ctx, arr, len(inputs), r_bits, tw, _ptr(out) if out is not None else 0,
+                                 out_cap, _ptr(out_len), _stream(stream)), "tq_symmetric_rle")
+
+
+def tq_symmetric_rle_dense(ctx: int, inputs, r_bits: int, truth, out, stream=None) -> None:
+    arr = rle_array(inputs)
+    tw = _u64_host(truth_words(truth))
+    _check(_lib.tq_symmetric_rle_dense(ctx, arr, len(inputs), r_bits, tw, _ptr(out), _stream(stream)),
+           "tq_symmetric_rle_dense")
+
+
+def tq_symmetric_hybrid(ctx: int, rle_inputs, dense_inputs, r_bits: int, truth, out, stream=None) -> None:
+    arr = rle_array(rle_inputs)
+    ptrs = ptr_array(dense_inputs)
+    tw = _u64_host(truth_words(truth))
+    _check(_lib.tq_symmetric_hybrid(ctx, arr, len(rle_inputs), ptrs, len(dense_inputs), r_bits, tw, _ptr(out),
+                                    _stream(stream)), "tq_symmetric_hybrid")
 
 
 def raw_threshold_rle(ctx: int, inputs, r_bits: int, theta: int, out_ptr: int, out_cap: int, out_len_ptr: int,

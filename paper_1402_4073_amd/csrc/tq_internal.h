@@ -101,11 +101,21 @@ struct RleDesc {
 // are limited to fewer than 2^31 words): the tile kernel keeps positions in
 // 32 bits.
 constexpr uint64_t kRleMaxWords = (1ull << 32) - 1024;
+// A symmetric function over compressed inputs.  A column with k ones fills
+// and d dirty inputs has a count in [k, k + d]; it is decided when f is
+// constant there, i.e. when k + d <= run_end[k].
+struct RleSym {
+  const uint32_t* run_end;  // per count c in [0, n]: last count of the run of equal f values from c
+  const uint64_t* f;        // f(c) is bit c of this array, c in [0, n]
+  EpiParams epi;            // f(count) on the planes of the full count
+};
+
 size_t rle_tile_lds_bytes(int K);
+// sym == nullptr: threshold theta; otherwise the symmetric function *sym.
 hipError_t launch_rle_tile(const RleDesc* d_descs, uint32_t n_rle, const uint64_t* const* d_dense,
                            uint32_t n_dense, uint64_t nwords, uint64_t tail_mask, uint32_t theta,
-                           int num_cus, uint32_t tiles_per_group, uint64_t* d_out, int* d_status,
-                           hipStream_t stream);
+                           const RleSym* sym, int num_cus, uint32_t tiles_per_group, uint64_t* d_out,
+                           int* d_status, hipStream_t stream);
 size_t rle_encode_workspace_bytes(uint64_t nwords);
 hipError_t launch_rle_encode(const uint64_t* d_dense, uint64_t nwords, uint64_t tail_mask, uint64_t* d_out,
                              uint64_t cap, uint64_t* d_out_len, uint64_t* d_index, void* workspace,

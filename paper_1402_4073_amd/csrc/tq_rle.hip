@@ -29,7 +29,7 @@
 // (zero fill, ones fill, dirty), a marker starts at word 0 and at each clean
 // word after a dirty word or a different fill, and one scan of the packed pair
 // (markers, dirty words) before each word gives every output position.
-#include "tq_internal.h"
+#include "tq_csa.hpp"
 
 namespace tq {
 namespace {
@@ -103,9 +103,25 @@ __device__ __forceinline__ void ripple_lds(uint64_t* planes, int col, uint64_t x
   }
 }
 
+// kd word of a column after the scan: bits 0..15 k (ones fills), bits 16..30
+// d (dirty inputs), bit 31 set when the column is undecided
 __device__ __forceinline__ void unpack_kd(int32_t v, int& k, int& d) {
   k = v & 0xFFFF;
-  d = (v >> 16) & 0xFFFF;
+  d = (v >> 16) & 0x7FFF;
+}
+
+// P += k for a per-lane constant k (bit-sliced ripple; the sum fits in K planes)
+template <int K>
+__device__ __forceinline__ void add_constant(uint64_t (&P)[K], uint32_t k) {
+  uint64_t carry = 0;
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    const uint64_t kb = 0 - (uint64_t)((k >> q) & 1u);
+    const uint64_t x = P[q] ^ kb;
+    const uint64_t c2 = (P[q] & kb) | (carry & x);
+    P[q] = x ^ carry;
+    carry = c2;
+  }
 }
 
 // count > a per lane (a differs between lanes), counter in registers
@@ -242,8 +258,7 @@ __device__ __forceinline__ void walk_markers(const RleDesc& dsc, Reader& rd, Wal
 // Literal words of the undecided columns of [t0, t1) into the LDS counters.
 template <int K, typename Reader>
 __device__ __forceinline__ void walk_literals(const RleDesc& dsc, Reader& rd, Walk wk, uint32_t t0, uint32_t t1,
-                                              uint32_t nwords, uint32_t theta, uint32_t n_dense, const int32_t* kd,
-                                              uint64_t* planes) {
+                                              uint32_t nwords, const int32_t* kd, uint64_t* planes) {
   while (wk.w < t1) {
     uint64_t m;
     uint32_t w1, w2;
@@ -251,10 +266,7 @@ __device__ __forceinline__ void walk_literals(const RleDesc& dsc, Reader& rd, Wa
     const uint32_t a = w1 > t0 ? w1 : t0, b = w2 < t1 ? w2 : t1;
     for (uint32_t col = a; col < b; ++col) {
       const int c = (int)(col - t0);
-      int k, d;
-      unpack_kd(kd[c], k, d);
-      const int tp = (int)theta - k;
-      if (tp >= 1 && tp <= d + (int)n_dense) ripple_lds<K>(planes, c, rd.at(wk.pos + 1 + (col - w1)));
+      if (kd[c] < 0) ripple_lds<K>(planes, c, rd.at(wk.pos + 1 + (col - w1)));
     }
     wk.pos += 1 + (w2 - w1);
     wk.w = w2;
@@ -266,10 +278,15 @@ __device__ __forceinline__ void walk_literals(const RleDesc& dsc, Reader& rd, Wa
 // one tile to the next, so a range reads each of its streams once, front to
 // back, and enters through the checkpoint index only at the range start;
 // further inputs (more than one per lane) enter every tile through the index.
-template <int K>
+//
+// Sym = false: threshold theta (the RBMrg run cases of section 4.1: with k
+// ones fills, theta - k <= 0 gives ones and theta - k > d zeros).  Sym = true:
+// any symmetric f, decided where f is constant on [k, k + d] and otherwise
+// evaluated on k plus the counted dirty bits.
+template <int K, bool Sym>
 __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(6))) void rle_tile_kernel(
     const RleDesc* __restrict__ descs, uint32_t n_rle, const uint64_t* const* __restrict__ dense,
-    uint32_t n_dense, uint32_t nwords, uint64_t tail_mask, uint32_t theta, uint32_t tiles_per_group,
+    uint32_t n_dense, uint32_t nwords, uint64_t tail_mask, uint32_t theta, RleSym sym, uint32_t tiles_per_group,
     uint64_t* __restrict__ out, int* __restrict__ status) {
   extern __shared__ uint64_t lds[];
   uint64_t* planes = lds;                                         // K x kTile
@@ -331,32 +348,38 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(6)
     }
     __syncthreads();
 
-    // 2. prefix sum: kd[c] = k + 65536 * d for column c
+    // 2. prefix sum: kd[c] = k + 65536 * d for column c, flagged if undecided
     int undecided = 0;
     {
       const int32_t v = tid < kTile ? kd[tid] : 0;
       const int32_t ex = block_exclusive_scan<int32_t, kTileThreads / 64>(v, wave_tot, &total);
-      if (tid < kTile) kd[tid] = ex + v;
+      bool und = false;
       if (tid < (int)(t1 - t0)) {
         int k, d;
         unpack_kd(ex + v, k, d);
-        const int tp = (int)theta - k;
+        if constexpr (Sym) {
+          und = (uint32_t)(k + d) + n_dense > sym.run_end[k];
+        } else {
+          const int tp = (int)theta - k;
+          und = tp >= 1 && tp <= d + (int)n_dense;
+        }
         // literal words matter where the column is undecided and has some
-        undecided = (tp >= 1 && tp <= d + (int)n_dense && d > 0) ? 1 : 0;
+        undecided = (und && d > 0) ? 1 : 0;
       }
+      if (tid < kTile) kd[tid] = (ex + v) | (und ? (int32_t)0x80000000 : 0);
     }
     // a tile whose columns the fills alone decide needs no literal word
     undecided = __syncthreads_or(undecided);
 
     // 3. literal words of undecided columns into the per-column LDS counters
     if (undecided) {
-      if (own && entry_ok) walk_literals<K>(mine, rd, entry, t0, t1, nwords, theta, n_dense, kd, planes);
+      if (own && entry_ok) walk_literals<K>(mine, rd, entry, t0, t1, nwords, kd, planes);
       for (uint32_t j = tid + kTileThreads; j < n_rle; j += kTileThreads) {
         const RleDesc dsc = descs[j];
         Walk wk;
         if (!seek(dsc, tile, t0, wk)) continue;
         rx.reset(dsc.words, dsc.len);
-        walk_literals<K>(dsc, rx, wk, t0, t1, nwords, theta, n_dense, kd, planes);
+        walk_literals<K>(dsc, rx, wk, t0, t1, nwords, kd, planes);
       }
     }
     __syncthreads();
@@ -364,16 +387,20 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(6)
     // 4. one column per thread: decide, or count and compare
     const int c = tid;
     if (c < (int)(t1 - t0)) {
+      const int32_t v = kd[c];
       int k, d;
-      unpack_kd(kd[c], k, d);
-      const int tp = (int)theta - k;
+      unpack_kd(v, k, d);
       uint64_t res;
-      if (tp <= 0) {
-        res = ~(uint64_t)0;
-      } else if (tp > d + (int)n_dense) {
-        res = 0;
-      } else if (n_dense == 0) {
-        res = greater_than_lds<K>(planes, c, (uint32_t)(tp - 1));
+      if (v >= 0) {
+        // decided by the fills: f(k), resp. k >= theta
+        bool one;
+        if constexpr (Sym)
+          one = (sym.f[k >> 6] >> (k & 63)) & 1;
+        else
+          one = k >= (int)theta;
+        res = one ? ~(uint64_t)0 : 0;
+      } else if (!Sym && n_dense == 0) {
+        res = greater_than_lds<K>(planes, c, theta - (uint32_t)k - 1);
       } else {
         uint64_t P[K];
 #pragma unroll
@@ -388,7 +415,16 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(6)
             x = t;
           }
         }
-        res = greater_than_lane<K>(P, (uint32_t)(tp - 1));
+        if constexpr (Sym) {
+          // the full count of the column: its ones fills plus the counted bits
+          add_constant<K>(P, (uint32_t)k);
+          csa::Vec<1> V[K];
+#pragma unroll
+          for (int q = 0; q < K; ++q) V[q].w[0] = P[q];
+          res = csa::epilogue<K, 1>(V, sym.epi, n_rle + n_dense, sym.epi.table).w[0];
+        } else {
+          res = greater_than_lane<K>(P, theta - (uint32_t)k - 1);
+        }
       }
       out[(uint64_t)t0 + c] = res & valid_mask_dev((uint64_t)t0 + c, nwords, tail_mask);
     }
@@ -589,21 +625,22 @@ uint32_t grid_cap(uint64_t want, uint32_t cap) {
 }
 
 typedef void (*TileFn)(const RleDesc*, uint32_t, const uint64_t* const*, uint32_t, uint32_t, uint64_t,
-                       uint32_t, uint32_t, uint64_t*, int*);
+                       uint32_t, RleSym, uint32_t, uint64_t*, int*);
 
-TileFn pick_tile(int K) {
+template <bool Sym>
+TileFn pick_tile_k(int K) {
   switch (K) {
-    case 4: return rle_tile_kernel<4>;
-    case 5: return rle_tile_kernel<5>;
-    case 6: return rle_tile_kernel<6>;
-    case 7: return rle_tile_kernel<7>;
-    case 8: return rle_tile_kernel<8>;
-    case 9: return rle_tile_kernel<9>;
-    case 10: return rle_tile_kernel<10>;
-    case 11: return rle_tile_kernel<11>;
-    case 12: return rle_tile_kernel<12>;
-    case 13: return rle_tile_kernel<13>;
-    case 16: return rle_tile_kernel<16>;
+    case 4: return rle_tile_kernel<4, Sym>;
+    case 5: return rle_tile_kernel<5, Sym>;
+    case 6: return rle_tile_kernel<6, Sym>;
+    case 7: return rle_tile_kernel<7, Sym>;
+    case 8: return rle_tile_kernel<8, Sym>;
+    case 9: return rle_tile_kernel<9, Sym>;
+    case 10: return rle_tile_kernel<10, Sym>;
+    case 11: return rle_tile_kernel<11, Sym>;
+    case 12: return rle_tile_kernel<12, Sym>;
+    case 13: return rle_tile_kernel<13, Sym>;
+    case 16: return rle_tile_kernel<16, Sym>;
   }
   return nullptr;
 }
@@ -614,34 +651,36 @@ size_t rle_tile_lds_bytes(int K) { return (size_t)K * kTile * 8 + (size_t)(kTile
 
 hipError_t launch_rle_tile(const RleDesc* d_descs, uint32_t n_rle, const uint64_t* const* d_dense,
                            uint32_t n_dense, uint64_t nwords, uint64_t tail_mask, uint32_t theta,
-                           int num_cus, uint32_t tiles_per_group, uint64_t* d_out, int* d_status,
-                           hipStream_t stream) {
+                           const RleSym* sym, int num_cus, uint32_t tiles_per_group, uint64_t* d_out,
+                           int* d_status, hipStream_t stream) {
   const int K = dense_planes_for(n_rle + n_dense);
-  TileFn fn = pick_tile(K);
+  TileFn fn = sym ? pick_tile_k<true>(K) : pick_tile_k<false>(K);
   if (!fn) return hipErrorInvalidValue;
+  const int slot = K + (sym ? 17 : 0);
   const uint64_t tiles = (nwords + kTile - 1) / kTile;
   if (tiles == 0) return hipSuccess;
   const size_t lds = rle_tile_lds_bytes(K);
-  static bool attr_set[17] = {false};
-  static int resident[17] = {0};
-  if (!attr_set[K]) {
+  static bool attr_set[34] = {false};
+  static int resident[34] = {0};
+  if (!attr_set[slot]) {
     hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)lds);
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(fn), kTileThreads,
                                                      lds) != hipSuccess || per_cu < 1)
       per_cu = 1;
-    resident[K] = per_cu;
-    attr_set[K] = true;
+    resident[slot] = per_cu;
+    attr_set[slot] = true;
   }
   // by default one range of consecutive tiles per resident workgroup
-  const uint64_t slots = (uint64_t)(num_cus > 0 ? num_cus : 1) * (uint64_t)resident[K];
+  const uint64_t slots = (uint64_t)(num_cus > 0 ? num_cus : 1) * (uint64_t)resident[slot];
   uint64_t per_group = tiles_per_group ? tiles_per_group : (tiles + slots - 1) / slots;
   if (per_group > tiles) per_group = tiles;
   const uint64_t ranges = (tiles + per_group - 1) / per_group;
   const uint64_t grid = (ranges + kXcds - 1) / kXcds * kXcds;
   hipLaunchKernelGGL(fn, dim3((uint32_t)grid), dim3(kTileThreads), lds, stream, d_descs, n_rle, d_dense,
-                     n_dense, (uint32_t)nwords, tail_mask, theta, (uint32_t)per_group, d_out, d_status);
+                     n_dense, (uint32_t)nwords, tail_mask, theta, sym ? *sym : RleSym{}, (uint32_t)per_group,
+                     d_out, d_status);
   return hipGetLastError();
 }
 

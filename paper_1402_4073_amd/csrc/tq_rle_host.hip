@@ -28,7 +28,7 @@ void* workspace(tq_ctx* ctx, size_t bytes) {
   // the old buffer may still be read by queued work
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) { record_hip(ctx, e); return nullptr; }
-  if (ctx->ws) hipFree(ctx->ws);
+  if (ctx->ws) (void)hipFree(ctx->ws);
   ctx->ws = nullptr;
   ctx->ws_bytes = 0;
   size_t want = align256(bytes + bytes / 4);
@@ -66,18 +66,66 @@ tq_status missing_index_bytes(const tq_rle* inputs, uint32_t n_rle, uint64_t nw,
   return st;
 }
 
+// The function of a query over compressed inputs: a threshold, or (truth
+// non-null) the symmetric function whose truth table is truth[0..n].
+struct RleFn {
+  uint32_t theta;
+  const uint64_t* truth;
+};
+
+// Device tables of a symmetric function for the tile kernel (cached blobs).
+struct SymTables {
+  RleSym sym{};
+  Blob* blobs[3] = {nullptr, nullptr, nullptr};
+};
+
+tq_status sym_tables(tq_ctx* ctx, uint32_t n, const uint64_t* truth, const SymPlan& plan, hipStream_t stream,
+                     SymTables* t) {
+  const uint32_t fw = n / 64 + 1;
+  std::vector<uint64_t> f(truth, truth + fw);
+  if ((n + 1) % 64) f[fw - 1] &= ((uint64_t)1 << ((n + 1) % 64)) - 1;
+  // run_end[c]: last count of the run of equal f values that starts at c
+  std::vector<uint32_t> run_end(n + 2, 0);
+  run_end[n] = n;
+  for (uint32_t c = n; c-- > 0;) {
+    const bool fc = (f[c / 64] >> (c % 64)) & 1, fn = (f[(c + 1) / 64] >> ((c + 1) % 64)) & 1;
+    run_end[c] = fc == fn ? run_end[c + 1] : c;
+  }
+  std::vector<uint64_t> re64((n + 2) / 2, 0);
+  memcpy(re64.data(), run_end.data(), (size_t)(n + 1) * 4);
+  const void* d_f = blob_get(ctx, f.data(), f.size(), stream, &t->blobs[0]);
+  const void* d_re = blob_get(ctx, re64.data(), re64.size(), stream, &t->blobs[1]);
+  if (!d_f || !d_re) return TQ_EDEVICE;
+  t->sym.f = static_cast<const uint64_t*>(d_f);
+  t->sym.run_end = static_cast<const uint32_t*>(d_re);
+  t->sym.epi = plan.epi;
+  if (plan.epi.kind == EPI_TABLE) {
+    std::vector<uint64_t> t64((plan.table.size() + 1) / 2, 0);
+    memcpy(t64.data(), plan.table.data(), plan.table.size() * 4);
+    const void* d_t = blob_get(ctx, t64.data(), t64.size(), stream, &t->blobs[2]);
+    if (!d_t) return TQ_EDEVICE;
+    t->sym.epi.table = static_cast<const uint32_t*>(d_t);
+  }
+  return TQ_OK;
+}
+
 // Common part of the compressed-input queries: tile kernel into d_dense_out.
 // idx_area: workspace for the indexes the caller did not supply (sized with
 // missing_index_bytes), allocated by the caller before any pointer into the
 // workspace is taken.
 tq_status run_rle_tiles(tq_ctx* ctx, const tq_rle* inputs, uint32_t n_rle, const uint64_t* const* dense_ptrs,
-                        uint32_t n_dense, uint64_t r_bits, uint32_t theta, uint64_t* d_dense_out,
+                        uint32_t n_dense, uint64_t r_bits, const RleFn& qf, uint64_t* d_dense_out,
                         uint64_t* idx_area, hipStream_t stream) {
   const uint64_t nw = words_for_bits(r_bits);
   const uint64_t tmask = tail_mask_for(r_bits);
   const uint32_t n = n_rle + n_dense;
-  if (theta == 0 || theta > n)
-    return record_hip(ctx, launch_fill(d_dense_out, nw, theta == 0 ? ~(uint64_t)0 : 0, tmask, stream));
+  SymPlan plan = qf.truth ? plan_symmetric(n, qf.truth) : plan_threshold(n, qf.theta);
+  if (plan.constant) return record_hip(ctx, launch_fill(d_dense_out, nw, plan.const_word, tmask, stream));
+  SymTables tabs;
+  if (qf.truth) {
+    tq_status st = sym_tables(ctx, n, qf.truth, plan, stream, &tabs);
+    if (st != TQ_OK) return st;
+  }
   std::vector<uint64_t> desc(3 * (size_t)(n_rle ? n_rle : 1), 0);
   const uint64_t nchk = index_entries(nw);
   uint32_t built = 0;
@@ -107,16 +155,18 @@ tq_status run_rle_tiles(tq_ctx* ctx, const tq_rle* inputs, uint32_t n_rle, const
   }
   st = record_hip(ctx, launch_rle_tile(reinterpret_cast<const RleDesc*>(d_desc), n_rle,
                                        reinterpret_cast<const uint64_t* const*>(d_dense), n_dense, nw, tmask,
-                                       theta, ctx->num_cus, ctx->rle_tiles, d_dense_out, ctx->d_status,
-                                       stream));
+                                       qf.theta, qf.truth ? &tabs.sym : nullptr, ctx->num_cus, ctx->rle_tiles,
+                                       d_dense_out, ctx->d_status, stream));
   blob_used(ctx, bd, stream);
   if (bp) blob_used(ctx, bp, stream);
+  for (Blob* b : tabs.blobs)
+    if (b) blob_used(ctx, b, stream);
   return st;
 }
 
 // Query with a dense result written to d_out; workspace holds only built indexes.
 tq_status rle_query_dense(tq_ctx* ctx, const tq_rle* inputs, uint32_t n_rle, const uint64_t* const* dense_ptrs,
-                          uint32_t n_dense, uint64_t r_bits, uint32_t theta, uint64_t* d_out, hipStream_t stream) {
+                          uint32_t n_dense, uint64_t r_bits, const RleFn& qf, uint64_t* d_out, hipStream_t stream) {
   const uint64_t nw = words_for_bits(r_bits);
   size_t idx_bytes = 0;
   tq_status st = missing_index_bytes(inputs, n_rle, nw, &idx_bytes);
@@ -126,7 +176,60 @@ tq_status rle_query_dense(tq_ctx* ctx, const tq_rle* inputs, uint32_t n_rle, con
     idx_area = static_cast<uint64_t*>(workspace(ctx, idx_bytes));
     if (!idx_area) return TQ_ENOMEM;
   }
-  return run_rle_tiles(ctx, inputs, n_rle, dense_ptrs, n_dense, r_bits, theta, d_out, idx_area, stream);
+  return run_rle_tiles(ctx, inputs, n_rle, dense_ptrs, n_dense, r_bits, qf, d_out, idx_area, stream);
+}
+
+// Dense-output query over compressed inputs (argument checks included).
+tq_status rle_dense_entry(tq_ctx* ctx, const tq_rle* inputs, uint32_t n, uint64_t r_bits, const RleFn& qf,
+                          uint64_t* d_out, hipStream_t stream) {
+  if (!ctx || !inputs || n == 0 || n > TQ_RLE_MAX_INPUTS) return TQ_EINVAL;
+  const uint64_t nw = words_for_bits(r_bits);
+  if (nw >= (1ull << 31)) return TQ_EINVAL;
+  if (nw == 0) return TQ_OK;
+  if (!d_out || ((uintptr_t)d_out & 7)) return TQ_EINVAL;
+  return rle_query_dense(ctx, inputs, n, nullptr, 0, r_bits, qf, d_out, stream);
+}
+
+tq_status hybrid_entry(tq_ctx* ctx, const tq_rle* rle_inputs, uint32_t n_rle, const uint64_t* const* dense_ptrs,
+                       uint32_t n_dense, uint64_t r_bits, const RleFn& qf, uint64_t* d_out, hipStream_t stream) {
+  if (!ctx || (n_rle && !rle_inputs) || (n_dense && !dense_ptrs)) return TQ_EINVAL;
+  const uint64_t n = (uint64_t)n_rle + n_dense;
+  if (n == 0 || n > TQ_RLE_MAX_INPUTS) return TQ_EINVAL;
+  const uint64_t nw = words_for_bits(r_bits);
+  if (nw >= (1ull << 31)) return TQ_EINVAL;
+  if (nw == 0) return TQ_OK;
+  if (!d_out || ((uintptr_t)d_out & 7)) return TQ_EINVAL;
+  for (uint32_t j = 0; j < n_dense; ++j) {
+    const uintptr_t p = (uintptr_t)dense_ptrs[j];
+    if (!p || (p & 7)) return TQ_EINVAL;
+    if (p < (uintptr_t)(d_out + nw) && (uintptr_t)d_out < p + nw * 8) return TQ_EINVAL;
+  }
+  return rle_query_dense(ctx, rle_inputs, n_rle, dense_ptrs, n_dense, r_bits, qf, d_out, stream);
+}
+
+// Query with a canonical RLE result.
+tq_status rle_rle_entry(tq_ctx* ctx, const tq_rle* inputs, uint32_t n, uint64_t r_bits, const RleFn& qf,
+                        uint64_t* d_out, uint64_t out_cap_words, uint64_t* d_out_len, hipStream_t stream) {
+  if (!ctx || !inputs || n == 0 || n > TQ_RLE_MAX_INPUTS || !d_out_len) return TQ_EINVAL;
+  const uint64_t nw = words_for_bits(r_bits);
+  if (nw >= (1ull << 31)) return TQ_EINVAL;
+  if (nw == 0) return record_hip(ctx, launch_set_u64(d_out_len, 0, stream));
+  if ((!d_out && out_cap_words) || ((uintptr_t)d_out & 7)) return TQ_EINVAL;
+  // workspace: [dense result | encoder scratch | built indexes], sized once
+  // before any pointer into it is taken
+  const size_t dense_bytes = align256(nw * 8);
+  const size_t enc_bytes = align256(rle_encode_workspace_bytes(nw));
+  size_t idx_bytes = 0;
+  tq_status st = missing_index_bytes(inputs, n, nw, &idx_bytes);
+  if (st != TQ_OK) return st;
+  char* ws = static_cast<char*>(workspace(ctx, dense_bytes + enc_bytes + idx_bytes));
+  if (!ws) return TQ_ENOMEM;
+  uint64_t* dense = reinterpret_cast<uint64_t*>(ws);
+  uint64_t* idx_area = idx_bytes ? reinterpret_cast<uint64_t*>(ws + dense_bytes + enc_bytes) : nullptr;
+  st = run_rle_tiles(ctx, inputs, n, nullptr, 0, r_bits, qf, dense, idx_area, stream);
+  if (st != TQ_OK) return st;
+  return record_hip(ctx, launch_rle_encode(dense, nw, tail_mask_for(r_bits), d_out, out_cap_words, d_out_len,
+                                           nullptr, ws + dense_bytes, ctx->d_status, stream));
 }
 
 }  // namespace
@@ -171,58 +274,41 @@ tq_status tq_rle_decode(tq_ctx* ctx, const tq_rle* input, uint64_t r_bits, uint6
   if (nw == 0) return TQ_OK;
   if ((uintptr_t)d_dense & 7) return TQ_EINVAL;
   // the 1-threshold of a single input is the input itself
-  return rle_query_dense(ctx, input, 1, nullptr, 0, r_bits, 1, d_dense, stream);
+  return rle_query_dense(ctx, input, 1, nullptr, 0, r_bits, RleFn{1, nullptr}, d_dense, stream);
 }
 
 tq_status tq_threshold_rle_dense(tq_ctx* ctx, const tq_rle* inputs, uint32_t n, uint64_t r_bits, uint32_t theta,
                                  uint64_t* d_out, hipStream_t stream) {
-  if (!ctx || !inputs || n == 0 || n > TQ_RLE_MAX_INPUTS) return TQ_EINVAL;
-  const uint64_t nw = words_for_bits(r_bits);
-  if (nw >= (1ull << 31)) return TQ_EINVAL;
-  if (nw == 0) return TQ_OK;
-  if (!d_out || ((uintptr_t)d_out & 7)) return TQ_EINVAL;
-  return rle_query_dense(ctx, inputs, n, nullptr, 0, r_bits, theta, d_out, stream);
+  return rle_dense_entry(ctx, inputs, n, r_bits, RleFn{theta, nullptr}, d_out, stream);
 }
 
 tq_status tq_threshold_hybrid(tq_ctx* ctx, const tq_rle* rle_inputs, uint32_t n_rle, const uint64_t* const* dense_ptrs,
                               uint32_t n_dense, uint64_t r_bits, uint32_t theta, uint64_t* d_out, hipStream_t stream) {
-  if (!ctx || (n_rle && !rle_inputs) || (n_dense && !dense_ptrs)) return TQ_EINVAL;
-  const uint64_t n = (uint64_t)n_rle + n_dense;
-  if (n == 0 || n > TQ_RLE_MAX_INPUTS) return TQ_EINVAL;
-  const uint64_t nw = words_for_bits(r_bits);
-  if (nw >= (1ull << 31)) return TQ_EINVAL;
-  if (nw == 0) return TQ_OK;
-  if (!d_out || ((uintptr_t)d_out & 7)) return TQ_EINVAL;
-  for (uint32_t j = 0; j < n_dense; ++j) {
-    const uintptr_t p = (uintptr_t)dense_ptrs[j];
-    if (!p || (p & 7)) return TQ_EINVAL;
-    if (p < (uintptr_t)(d_out + nw) && (uintptr_t)d_out < p + nw * 8) return TQ_EINVAL;
-  }
-  return rle_query_dense(ctx, rle_inputs, n_rle, dense_ptrs, n_dense, r_bits, theta, d_out, stream);
+  return hybrid_entry(ctx, rle_inputs, n_rle, dense_ptrs, n_dense, r_bits, RleFn{theta, nullptr}, d_out, stream);
 }
 
 tq_status tq_threshold_rle(tq_ctx* ctx, const tq_rle* inputs, uint32_t n, uint64_t r_bits, uint32_t theta,
                            uint64_t* d_out, uint64_t out_cap_words, uint64_t* d_out_len, hipStream_t stream) {
-  if (!ctx || !inputs || n == 0 || n > TQ_RLE_MAX_INPUTS || !d_out_len) return TQ_EINVAL;
-  const uint64_t nw = words_for_bits(r_bits);
-  if (nw >= (1ull << 31)) return TQ_EINVAL;
-  if (nw == 0) return record_hip(ctx, launch_set_u64(d_out_len, 0, stream));
-  if ((!d_out && out_cap_words) || ((uintptr_t)d_out & 7)) return TQ_EINVAL;
-  // workspace: [dense result | encoder scratch | built indexes], sized once
-  // before any pointer into it is taken
-  const size_t dense_bytes = align256(nw * 8);
-  const size_t enc_bytes = align256(rle_encode_workspace_bytes(nw));
-  size_t idx_bytes = 0;
-  tq_status st = missing_index_bytes(inputs, n, nw, &idx_bytes);
-  if (st != TQ_OK) return st;
-  char* ws = static_cast<char*>(workspace(ctx, dense_bytes + enc_bytes + idx_bytes));
-  if (!ws) return TQ_ENOMEM;
-  uint64_t* dense = reinterpret_cast<uint64_t*>(ws);
-  uint64_t* idx_area = idx_bytes ? reinterpret_cast<uint64_t*>(ws + dense_bytes + enc_bytes) : nullptr;
-  st = run_rle_tiles(ctx, inputs, n, nullptr, 0, r_bits, theta, dense, idx_area, stream);
-  if (st != TQ_OK) return st;
-  return record_hip(ctx, launch_rle_encode(dense, nw, tail_mask_for(r_bits), d_out, out_cap_words, d_out_len,
-                                           nullptr, ws + dense_bytes, ctx->d_status, stream));
+  return rle_rle_entry(ctx, inputs, n, r_bits, RleFn{theta, nullptr}, d_out, out_cap_words, d_out_len, stream);
+}
+
+tq_status tq_symmetric_rle_dense(tq_ctx* ctx, const tq_rle* inputs, uint32_t n, uint64_t r_bits,
+                                 const uint64_t* h_truth, uint64_t* d_out, hipStream_t stream) {
+  if (!h_truth) return TQ_EINVAL;
+  return rle_dense_entry(ctx, inputs, n, r_bits, RleFn{0, h_truth}, d_out, stream);
+}
+
+tq_status tq_symmetric_hybrid(tq_ctx* ctx, const tq_rle* rle_inputs, uint32_t n_rle, const uint64_t* const* dense_ptrs,
+                              uint32_t n_dense, uint64_t r_bits, const uint64_t* h_truth, uint64_t* d_out,
+                              hipStream_t stream) {
+  if (!h_truth) return TQ_EINVAL;
+  return hybrid_entry(ctx, rle_inputs, n_rle, dense_ptrs, n_dense, r_bits, RleFn{0, h_truth}, d_out, stream);
+}
+
+tq_status tq_symmetric_rle(tq_ctx* ctx, const tq_rle* inputs, uint32_t n, uint64_t r_bits, const uint64_t* h_truth,
+                           uint64_t* d_out, uint64_t out_cap_words, uint64_t* d_out_len, hipStream_t stream) {
+  if (!h_truth) return TQ_EINVAL;
+  return rle_rle_entry(ctx, inputs, n, r_bits, RleFn{0, h_truth}, d_out, out_cap_words, d_out_len, stream);
 }
 
 }  // extern "C"

@@ -298,6 +298,17 @@ def test_rle_config_full_size(ctx):
         tq.tq_threshold(ctx, rows, r, theta, ref)                # uncompressed path, same inputs
         assert tq.tq_ctx_check(ctx) == 0
         assert np.array_equal(got, to_host(ref)), theta
+    # symmetric functions over the same compressed inputs: parity, 2 <= count <= 10
+    for t in (oracle.truth_parity(n), oracle.truth_interval(n, 2, 10)):
+        tq.tq_symmetric_rle(ctx, inputs, r, t, out, cap, ln)
+        assert tq.tq_ctx_check(ctx) == 0
+        stream = to_host(out)[:int(ln.item())]
+        got = oracle.rle_decode(stream, r)
+        assert np.array_equal(oracle.rle_encode(got, r), stream)
+        assert np.array_equal(got[cols], oracle.symmetric_cols(words, cols, r, t))
+        tq.tq_symmetric(ctx, rows, r, t, ref)
+        assert tq.tq_ctx_check(ctx) == 0
+        assert np.array_equal(got, to_host(ref))
 
 
 @pytest.mark.parametrize("n", [70, 150])
@@ -384,3 +395,87 @@ def test_more_inputs_than_lanes(ctx, tiles_option, tiles):
         tq.tq_threshold_rle_dense(ctx, inputs, r, theta, out)
         assert tq.tq_ctx_check(ctx) == 0
         assert np.array_equal(to_host(out), oracle.threshold(dense, r, theta)), theta
+
+
+# ------------------------------------------- symmetric functions over RLE
+def sym_tables(n, rng):
+    t = [oracle.truth_parity(n), oracle.truth_interval(n, 2, min(n, 10)),
+         oracle.truth_interval(n, min(n, 3), min(n, 3)),                     # delta: count == 3
+         1 - oracle.truth_threshold(n, max(1, n // 2)),                       # count < n/2
+         rng.integers(0, 2, n + 1).astype(np.uint8),
+         np.ones(n + 1, dtype=np.uint8), np.zeros(n + 1, dtype=np.uint8)]
+    return [np.asarray(x, dtype=np.uint8) for x in t]
+
+
+@pytest.mark.parametrize("n,r,tiles", [(1, 64 * 700, 0), (6, 64 * STRIDE * 3 + 17, 2), (33, 64 * 2100 + 5, 0),
+                                       (90, 64 * STRIDE * 4 + 64, 1)])
+def test_symmetric_rle_matches_oracle(ctx, tiles_option, n, r, tiles):
+    """Symmetric functions over compressed inputs: dense and canonical RLE
+    outputs equal the oracle's, with and without checkpoint indexes, over
+    several tile-range lengths; a threshold written as a truth table equals
+    the threshold call."""
+    rng = np.random.default_rng(40 + n)
+    dense = markov_bitmaps(900 + n, n, r, float(rng.integers(20, 300)), float(rng.integers(100, 3000)))
+    sp = special_bitmaps(r)
+    for j in range(min(n, 3)):
+        dense[j] = sp[(j + n) % 5]
+    assert tiles_option(tiles) == tq.TQ_OK
+    for with_index in (True, False):
+        inputs, keep = rle_inputs(ctx, dense, r, with_index=with_index)
+        for t in sym_tables(n, rng):
+            want_dense = oracle.symmetric(dense, r, t)
+            dout = empty_words((r + 63) // 64)
+            tq.tq_symmetric_rle_dense(ctx, inputs, r, t, dout)
+            assert tq.tq_ctx_check(ctx) == 0
+            assert np.array_equal(to_host(dout), want_dense), (with_index, list(t))
+            want = oracle.rle_encode(want_dense, r)
+            cap = tq.tq_rle_max_words(r)
+            out = empty_words(cap)
+            ln = torch.zeros(1, dtype=torch.int64, device="cuda")
+            tq.tq_symmetric_rle(ctx, inputs, r, t, out, cap, ln)
+            assert tq.tq_ctx_check(ctx) == 0
+            assert np.array_equal(to_host(out)[:int(ln.item())], want), (with_index, list(t))
+    theta = max(1, n // 3)
+    d1 = empty_words((r + 63) // 64)
+    d2 = empty_words((r + 63) // 64)
+    tq.tq_symmetric_rle_dense(ctx, inputs, r, oracle.truth_threshold(n, theta), d1)
+    tq.tq_threshold_rle_dense(ctx, inputs, r, theta, d2)
+    assert tq.tq_ctx_check(ctx) == 0
+    assert np.array_equal(to_host(d1), to_host(d2))
+
+
+@pytest.mark.parametrize("n_rle,n_dense", [(4, 3), (0, 5), (25, 25)])
+def test_symmetric_hybrid(ctx, n_rle, n_dense):
+    r = 64 * 1300 + 9
+    n = n_rle + n_dense
+    dense_all = markov_bitmaps(950 + n, n, r, 40.0, 300.0)
+    inputs, keep = rle_inputs(ctx, dense_all[:n_rle], r)
+    pool = dev_pool(dense_all[n_rle:])
+    drows = [pool[j] for j in range(n_dense)]
+    rng = np.random.default_rng(n)
+    for t in sym_tables(n, rng):
+        out = empty_words((r + 63) // 64)
+        tq.tq_symmetric_hybrid(ctx, inputs, drows, r, t, out)
+        assert tq.tq_ctx_check(ctx) == 0
+        assert np.array_equal(to_host(out), oracle.symmetric(dense_all, r, t)), list(t)
+
+
+def test_symmetric_rle_many_inputs(ctx):
+    """600 inputs (more than one per lane) and inputs dirty almost everywhere."""
+    r = 64 * STRIDE * 2 + 3
+    dense = markov_bitmaps(990, 600, r, 3.0, 40.0)
+    inputs, keep = rle_inputs(ctx, dense, r)
+    for t in (oracle.truth_parity(600), oracle.truth_interval(600, 20, 45), oracle.truth_interval(600, 0, 5)):
+        out = empty_words((r + 63) // 64)
+        tq.tq_symmetric_rle_dense(ctx, inputs, r, t, out)
+        assert tq.tq_ctx_check(ctx) == 0
+        assert np.array_equal(to_host(out), oracle.symmetric(dense, r, t))
+
+
+def test_symmetric_rle_errors(ctx):
+    r = 640
+    inputs, keep = rle_inputs(ctx, markov_bitmaps(1, 2, r, 5.0, 5.0), r)
+    out = empty_words(10)
+    arr = tq.rle_array(inputs)
+    assert tq._lib.tq_symmetric_rle_dense(ctx, arr, 2, r, None, out.data_ptr(), None) == tq.TQ_EINVAL
+    assert tq._lib.tq_symmetric_rle(ctx, arr, 2, r, None, out.data_ptr(), 10, out.data_ptr(), None) == tq.TQ_EINVAL
