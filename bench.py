@@ -40,7 +40,7 @@ def parse():
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-consumers", action="store_true",
-                    help="skip the fused-consumer timings (profiling runs of the roofline kernel)")
+                    help="skip the fused-consumer and weighted timings (profiling runs of the roofline kernel)")
     ap.add_argument("--prune", type=int, default=1,
                     help="threshold pruning in the timed pass (the roofline pass never prunes)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -167,6 +167,19 @@ def bench_rle(args):
                 b.record(stream)
                 ev_tile.append((a, b))
         torch.cuda.synchronize()
+    # symmetric functions over the same compressed inputs (canonical RLE output)
+    sym = {"parity": oracle.truth_parity(n), "2<=count<=10": oracle.truth_interval(n, 2, 10)}
+    sym_ms = {}
+    with torch.cuda.stream(stream):
+        for name, t in sym.items():
+            tq.tq_symmetric_rle(ctx, inputs, r, t, out, cap, ln, stream)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(args.steps):
+                tq.tq_symmetric_rle(ctx, inputs, r, t, out, cap, ln, stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+            sym_ms[name] = round(a.elapsed_time(b) / args.steps, 4)
     st = tq.tq_ctx_check(ctx, stream)
     if st != 0:
         raise RuntimeError("device error: %s" % tq.status_string(st))
@@ -191,6 +204,7 @@ def bench_rle(args):
         "compressed_input_GBps": round(q * comp_bytes * args.steps / elapsed / 1e9, 2),
         "per_query_ms": [round(sum(full_ms[i::q]) / args.steps, 4) for i in range(q)],
         "tile_kernel_ms": [round(sum(tile_ms[i::q]) / args.steps, 4) for i in range(q)],
+        "symmetric_query_ms": sym_ms,
         "roofline": {"bound": "hbm", "achieved": round(alg / tile_s / 1e9, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(alg / tile_s / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "rle_tile_kernel<K=10>", "mean_launch_us": round(tile_s * 1e6, 2),
@@ -534,6 +548,36 @@ def time_consumers(tq, ctx, rows, r, nw, stream, steps):
     return res
 
 
+def time_weighted(tq, ctx, rows, r, nw, stream, steps):
+    """Weighted threshold with weights 1..4 (cycling over the inputs), theta =
+    half the total: one read of each input, against the same query through
+    replication (input j listed w_j times, section 2.3)."""
+    import torch
+    weights = [1 + (j % 4) for j in range(len(rows))]
+    theta = sum(weights) // 2
+    rep = [rows[j] for j in range(len(rows)) for _ in range(weights[j])]
+    out = torch.empty(nw, dtype=torch.int64, device=rows[0].device)
+    runs = {
+        "weighted_ms": lambda: tq.tq_threshold_weighted(ctx, rows, weights, r, theta, out, stream),
+        "replicated_ms": lambda: tq.tq_threshold(ctx, rep, r, theta, out, stream),
+    }
+    res = {"weights": "1 + (j mod 4)", "theta": theta, "total_weight": sum(weights)}
+    with torch.cuda.stream(stream):
+        for name, fn in runs.items():
+            fn()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(steps):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            res[name] = round(e0.elapsed_time(e1) / steps, 4)
+    if tq.tq_ctx_check(ctx, stream) != 0:
+        raise RuntimeError("device error in the weighted timings")
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -623,6 +667,7 @@ def main():
     _, kernel_ms = timed_pass(0)
     tq.tq_set_option(ctx, tq.TQ_OPTION_PRUNE, 1)
     consumers = None if args.no_consumers else time_consumers(tq, ctx, rows, r, nw, stream, args.steps)
+    weighted = None if args.no_consumers else time_weighted(tq, ctx, rows, r, nw, stream, args.steps)
     mean_kernel_s = sum(kernel_ms) / len(kernel_ms) / 1e3
     in_bytes_query = n * nw * 8
     out_bytes_query = nw * 8
@@ -657,6 +702,7 @@ def main():
                                   for i in range(len(queries))],
         "prune": bool(args.prune),
         "consumers": consumers,
+        "weighted": weighted,
     }
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(rows, n, nw, r, queries, args.cpu_seconds)

@@ -125,6 +125,18 @@ tq_status tq_symmetric(tq_ctx* ctx, const uint64_t* const* ptrs, uint32_t n, uin
                        const uint64_t* h_truth, uint64_t* d_out, hipStream_t stream);
 
 /*
+ * Weighted threshold query (section 2.3: inputs may carry positive integer
+ * weights, there realised by replicating input j weights[j] times):
+ *   d_out bit p = [ sum_j weights[j] * bit p of ptrs[j] >= theta ]  for p < r_bits.
+ * Each input is read once whatever its weight.  h_weights: HOST array of n
+ * uint32 weights (0 allowed: the input is ignored); their sum must not exceed
+ * 2^32 - 1 (else TQ_EINVAL).  theta == 0 gives all ones on [0, r_bits), theta
+ * above the sum gives zeros.  Other arguments and errors as for tq_threshold.
+ */
+tq_status tq_threshold_weighted(tq_ctx* ctx, const uint64_t* const* ptrs, uint32_t n, const uint32_t* h_weights,
+                                uint64_t r_bits, uint64_t theta, uint64_t* d_out, hipStream_t stream);
+
+/*
  * Fused consumers of the result (the result of a threshold or symmetric
  * query is again a bitmap, to be combined with other criteria by AND and
  * friends or counted: abstract and introduction).  In the same pass:

@@ -57,6 +57,7 @@ def _load():
         "tq_threshold": (_INT, [_P, _P, _U32, _U64, _U32, _P, _P]),
         "tq_symmetric": (_INT, [_P, _P, _U32, _U64, _P, _P, _P]),
         "tq_threshold_fused": (_INT, [_P, _P, _U32, _U64, _U32, _P, _P, _P, _P]),
+        "tq_threshold_weighted": (_INT, [_P, _P, _U32, _P, _U64, _U64, _P, _P]),
         "tq_symmetric_fused": (_INT, [_P, _P, _U32, _U64, _P, _P, _P, _P, _P]),
         "tq_rle_max_words": (_U64, [_U64]),
         "tq_rle_index_words": (_U64, [_U64]),
@@ -200,6 +201,26 @@ def tq_symmetric(ctx: int, inputs, r_bits: int, truth, out, stream=None) -> None
     tw = _u64_host(truth_words(truth))
     _check(_lib.tq_symmetric(ctx, ptrs, len(inputs), r_bits, tw, _ptr(out), _stream(stream)),
            "tq_symmetric")
+
+
+def _u32_host(values):
+    arr = (ctypes.c_uint32 * max(1, len(values)))()
+    for i, v in enumerate(values):
+        arr[i] = int(v)
+    return arr
+
+
+def tq_threshold_weighted(ctx: int, inputs, weights, r_bits: int, theta: int, out, stream=None) -> None:
+    """out bit p = [sum_j weights[j] * bit_j(p) >= theta] (non-negative integer weights)."""
+    ptrs = ptr_array(inputs)
+    _check(_lib.tq_threshold_weighted(ctx, ptrs, len(inputs), _u32_host(weights), r_bits, theta, _ptr(out),
+                                      _stream(stream)), "tq_threshold_weighted")
+
+
+def raw_threshold_weighted(ctx: int, inputs, weights, r_bits: int, theta: int, out_ptr, stream=None) -> int:
+    ptrs = ptr_array(inputs)
+    w = _u32_host(weights) if weights is not None else None
+    return _lib.tq_threshold_weighted(ctx, ptrs, len(inputs), w, r_bits, theta, out_ptr, _stream(stream))
 
 
 def _optr(t):

@@ -419,6 +419,53 @@ tq_status tq_symmetric(tq_ctx* ctx, const uint64_t* const* ptrs, uint32_t n, uin
   return run_dense(ctx, ptrs, n, r_bits, plan_symmetric(n, h_truth), d_out, stream, a16);
 }
 
+tq_status tq_threshold_weighted(tq_ctx* ctx, const uint64_t* const* ptrs, uint32_t n, const uint32_t* h_weights,
+                                uint64_t r_bits, uint64_t theta, uint64_t* d_out, hipStream_t stream) {
+  if (!ctx || !h_weights) return TQ_EINVAL;
+  bool a16 = false;
+  tq_status st = check_dense_args(ptrs, n, r_bits, d_out, &a16);
+  if (st != TQ_OK) return st;
+  uint64_t total = 0;
+  for (uint32_t j = 0; j < n; ++j) total += h_weights[j];
+  if (total > 0xFFFFFFFFull) return TQ_EINVAL;
+  const uint64_t nw = words_for_bits(r_bits);
+  const uint64_t tmask = tail_mask_for(r_bits);
+  if (nw == 0) return TQ_OK;
+  if (theta == 0 || theta > total)
+    return record_hip(ctx, launch_fill(d_out, nw, theta == 0 ? ~(uint64_t)0 : 0, tmask, stream));
+  // group the inputs of equal weight (weight 0 contributes nothing)
+  std::vector<uint32_t> order;
+  order.reserve(n);
+  for (uint32_t j = 0; j < n; ++j)
+    if (h_weights[j]) order.push_back(j);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](uint32_t a, uint32_t b) { return h_weights[a] < h_weights[b]; });
+  std::vector<uint64_t> sorted(order.size());
+  std::vector<WeightClass> classes;
+  uint32_t max_class = 0;
+  for (size_t i = 0; i < order.size(); ++i) {
+    sorted[i] = (uint64_t)(uintptr_t)ptrs[order[i]];
+    const uint32_t wt = h_weights[order[i]];
+    if (classes.empty() || classes.back().weight != wt) classes.push_back(WeightClass{wt, (uint32_t)i, (uint32_t)i, 0});
+    classes.back().end = (uint32_t)i + 1;
+    const uint32_t size = classes.back().end - classes.back().begin;
+    if (size > max_class) max_class = size;
+  }
+  Blob* pb = nullptr;
+  Blob* cb = nullptr;
+  const void* d_ptrs = blob_get(ctx, sorted.data(), sorted.size(), stream, &pb);
+  if (!d_ptrs) return TQ_EDEVICE;
+  const void* d_cls = blob_get(ctx, reinterpret_cast<const uint64_t*>(classes.data()), classes.size() * 2, stream,
+                               &cb);
+  if (!d_cls) return TQ_EDEVICE;
+  st = record_hip(ctx, launch_weighted(reinterpret_cast<const uint64_t* const*>(d_ptrs),
+                                       reinterpret_cast<const WeightClass*>(d_cls), (uint32_t)classes.size(),
+                                       max_class, nw, tmask, (uint32_t)theta, (uint32_t)total, d_out, stream));
+  blob_used(ctx, pb, stream);
+  blob_used(ctx, cb, stream);
+  return st;
+}
+
 tq_status tq_threshold_fused(tq_ctx* ctx, const uint64_t* const* ptrs, uint32_t n, uint64_t r_bits,
                              uint32_t theta, const uint64_t* d_filter, uint64_t* d_out, uint64_t* d_count,
                              hipStream_t stream) {

@@ -80,6 +80,15 @@ hipError_t launch_dense(const DenseConfig& cfg, const uint64_t* const* d_ptrs, u
 hipError_t launch_fill(uint64_t* d_out, uint64_t nwords, uint64_t value, uint64_t tail_mask,
                        hipStream_t stream);
 
+// Weighted threshold: inputs [begin, end) of the (reordered) pointer array
+// all carry `weight`.
+struct WeightClass {
+  uint32_t weight, begin, end, pad;
+};
+hipError_t launch_weighted(const uint64_t* const* d_ptrs, const WeightClass* d_classes, uint32_t nclasses,
+                           uint32_t max_class, uint64_t nwords, uint64_t tail_mask, uint32_t theta,
+                           uint32_t total_weight, uint64_t* d_out, hipStream_t stream);
+
 // Constant result with consumers: out = value AND filter (tail cleared),
 // partial popcounts per 256-word block (fill_groups(nwords) slots).
 uint64_t fill_groups(uint64_t nwords);
