@@ -62,18 +62,21 @@ def copy_calibration():
 
 def load_traffic(kernel_key: str):
     """HBM bytes per launch measured by rocprofv3 counters (profiles/traffic.json),
-    or None if not measured for the current kernel build."""
+    or None if not measured for the current source of that kernel."""
+    import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as fh:
             rec = json.load(fh).get(kernel_key)
     except (OSError, ValueError):
         return None
-    if not rec:
+    if not rec or "source" not in rec:
         return None
-    src = os.path.join(ROOT, "paper_1402_4073_amd", "csrc", "tq_dense.hip")
-    import hashlib
-    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    try:
+        with open(os.path.join(ROOT, rec["source"]), "rb") as fh:
+            h = hashlib.sha256(fh.read()).hexdigest()[:16]
+    except OSError:
+        return None
     if rec.get("source_sha") != h:
         return None
     return rec.get("bytes_per_launch")
@@ -206,7 +209,8 @@ def bench_rle(args):
         "tile_kernel_ms": [round(sum(tile_ms[i::q]) / args.steps, 4) for i in range(q)],
         "symmetric_query_ms": sym_ms,
         "roofline": {"bound": "hbm", "achieved": round(alg / tile_s / 1e9, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(alg / tile_s / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(alg / tile_s / 1e9 / HBM_PEAK_GBS, 4),
+                     "traffic": load_traffic("rle_tile_kernel<K=10>/rle"),
                      "kernel": "rle_tile_kernel<K=10>", "mean_launch_us": round(tile_s * 1e6, 2),
                      "alg_bytes_per_launch": alg,
                      "alg_bytes_note": "all compressed input words + one index entry per tile per input + dense output"},
