@@ -37,6 +37,9 @@ namespace {
 constexpr int kTile = TQ_RLE_INDEX_STRIDE;  // words per tile == checkpoint stride
 constexpr uint32_t kXcds = 8;                // accelerator complex dies per device
 constexpr int kTileThreads = 512;
+// columns needing literal words in a tile from which on the next tile is done
+// in one pass
+constexpr int kOnePassColumns = kTile / 16;
 constexpr int kEncBlock = 256;
 constexpr int kEncPerThread = 4;
 constexpr int kEncWords = kEncBlock * kEncPerThread;
@@ -220,11 +223,13 @@ __device__ __forceinline__ bool read_marker(const RleDesc& dsc, Reader& rd, cons
 }
 
 // Marker walk of one input over [t0, t1): fills of ones and literal runs go
-// into the difference array.  On return `next` is the entry state of the
-// following tile (the marker covering t1).
-template <typename Reader>
+// into the difference array; with `lits` the literal words are also added to
+// the column counters right away (the one-pass form of a tile).  On return
+// `next` is the entry state of the following tile (the marker covering t1).
+template <int K, typename Reader>
 __device__ __forceinline__ void walk_markers(const RleDesc& dsc, Reader& rd, Walk wk, uint32_t t0, uint32_t t1,
-                                             uint32_t nwords, int32_t* kd, int* status, Walk& next) {
+                                             uint32_t nwords, int32_t* kd, int* status, bool lits,
+                                             uint64_t* planes, Walk& next) {
   next = wk;
   while (wk.w < t1) {
     uint64_t m;
@@ -242,6 +247,9 @@ __device__ __forceinline__ void walk_markers(const RleDesc& dsc, Reader& rd, Wal
       if (a < b) {
         atomicAdd(&kd[a - t0], 65536);
         atomicAdd(&kd[b - t0], -65536);
+        if (lits)
+          for (uint32_t col = a; col < b; ++col)
+            ripple_lds<K>(planes, (int)(col - t0), rd.at(wk.pos + 1 + (col - w1)));
       }
     }
     // a marker reaching past t1 is where the next tile enters this stream
@@ -316,6 +324,12 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(6)
     mine = descs[tid];
     rd.reset(mine.words, mine.len);
   }
+  // Tiles whose literal words are mostly needed are done in one pass (the
+  // marker walk adds every literal word to the counters), saving the second
+  // walk at the cost of counting literal words of decided columns too.  The
+  // choice follows the previous tile of the range: neighbouring tiles of a
+  // bitmap tend to look alike.
+  bool one_pass = false;
 
   for (uint32_t tile = tile_begin; tile < tile_end; ++tile) {
     const uint32_t t0 = tile * kTile;
@@ -336,7 +350,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(6)
         entry_ok = seek(mine, tile, t0, entry);
         if (!entry_ok) set_status(status, TQ_EFORMAT);
       }
-      if (entry_ok) walk_markers(mine, rd, entry, t0, t1, nwords, kd, status, carry);
+      if (entry_ok) walk_markers<K>(mine, rd, entry, t0, t1, nwords, kd, status, one_pass, planes, carry);
       carry_ok = entry_ok;
     }
     for (uint32_t j = tid + kTileThreads; j < n_rle; j += kTileThreads) {
@@ -344,7 +358,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(6)
       Walk wk, unused;
       if (!seek(dsc, tile, t0, wk)) { set_status(status, TQ_EFORMAT); continue; }
       rx.reset(dsc.words, dsc.len);
-      walk_markers(dsc, rx, wk, t0, t1, nwords, kd, status, unused);
+      walk_markers<K>(dsc, rx, wk, t0, t1, nwords, kd, status, one_pass, planes, unused);
     }
     __syncthreads();
 
@@ -369,10 +383,12 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(6)
       if (tid < kTile) kd[tid] = (ex + v) | (und ? (int32_t)0x80000000 : 0);
     }
     // a tile whose columns the fills alone decide needs no literal word
-    undecided = __syncthreads_or(undecided);
+    const int need = __syncthreads_count(undecided);
+    const bool walk_again = need > 0 && !one_pass;
+    one_pass = need >= kOnePassColumns;
 
     // 3. literal words of undecided columns into the per-column LDS counters
-    if (undecided) {
+    if (walk_again) {
       if (own && entry_ok) walk_literals<K>(mine, rd, entry, t0, t1, nwords, kd, planes);
       for (uint32_t j = tid + kTileThreads; j < n_rle; j += kTileThreads) {
         const RleDesc dsc = descs[j];

@@ -165,6 +165,12 @@ def test_decode_rejects_malformed(ctx):
 
 
 # ---------------------------------------------------------------- threshold
+@pytest.fixture
+def tiles_option(ctx):
+    yield lambda v: tq.raw_set_option(ctx, tq.TQ_OPTION_RLE_TILES, v)
+    tq.tq_set_option(ctx, tq.TQ_OPTION_RLE_TILES, 0)
+
+
 def rle_inputs(ctx, dense_list, r, with_index=True, use_oracle_encoding=False):
     keep, inputs = [], []
     for dense in dense_list:
@@ -311,11 +317,14 @@ def test_rle_config_full_size(ctx):
         assert np.array_equal(got, to_host(ref))
 
 
-@pytest.mark.parametrize("n", [70, 150])
-def test_threshold_rle_many_dirty_words(ctx, n):
+@pytest.mark.parametrize("n,tiles", [(70, 0), (150, 0), (70, 3), (150, 2)])
+def test_threshold_rle_many_dirty_words(ctx, tiles_option, n, tiles):
     """Inputs dirty almost everywhere: nearly every column is undecided after
-    the fills and its counter receives a literal word from most inputs."""
+    the fills and its counter receives a literal word from most inputs.  With
+    several tiles per workgroup the tiles after the first are done in one
+    pass."""
     r = 64 * 1100 + 5
+    assert tiles_option(tiles) == tq.TQ_OK
     dense = markov_bitmaps(500 + n, n, r, 2.0, 2.0)
     inputs, keep = rle_inputs(ctx, dense, r)
     for theta in (1, n // 3, n // 2, n - 1, n):
@@ -333,12 +342,6 @@ def test_threshold_rle_many_dirty_words(ctx, n):
 
 
 # ------------------------------------------------ tile ranges per workgroup
-@pytest.fixture
-def tiles_option(ctx):
-    yield lambda v: tq.raw_set_option(ctx, tq.TQ_OPTION_RLE_TILES, v)
-    tq.tq_set_option(ctx, tq.TQ_OPTION_RLE_TILES, 0)
-
-
 def test_tiles_option_range(ctx, tiles_option):
     assert tiles_option(-1) == tq.TQ_EINVAL
     assert tiles_option((1 << 20) + 1) == tq.TQ_EINVAL
@@ -460,8 +463,11 @@ def test_symmetric_hybrid(ctx, n_rle, n_dense):
         assert np.array_equal(to_host(out), oracle.symmetric(dense_all, r, t)), list(t)
 
 
-def test_symmetric_rle_many_inputs(ctx):
-    """600 inputs (more than one per lane) and inputs dirty almost everywhere."""
+@pytest.mark.parametrize("tiles", [0, 3])
+def test_symmetric_rle_many_inputs(ctx, tiles_option, tiles):
+    """600 inputs (more than one per lane) and inputs dirty almost everywhere,
+    one tile per workgroup and three (one-pass tiles)."""
+    assert tiles_option(tiles) == tq.TQ_OK
     r = 64 * STRIDE * 2 + 3
     dense = markov_bitmaps(990, 600, r, 3.0, 40.0)
     inputs, keep = rle_inputs(ctx, dense, r)
