@@ -272,3 +272,35 @@ def test_pruning_equivalence(ctx, n):
         tq.tq_set_option(ctx, tq.TQ_OPTION_PRUNE, 1)
         assert np.array_equal(outs[0], want), theta
         assert np.array_equal(outs[1], want), theta
+
+
+def test_complement_identity_gpu(ctx):
+    """Section 2.3, corrected: NOT T_theta(B) = T_{N-theta+1}(NOT B) on [0, r),
+    for the dense kernel and for compressed inputs (the complemented bitmaps
+    encoded by the library)."""
+    rng = np.random.default_rng(77)
+    n, r = 23, 64 * 1500 + 29
+    nw = (r + 63) // 64
+    host = rand_words(rng, n, nw, 0.2)
+    pool = dev_pool(host)
+    comp = torch.bitwise_not(pool)
+    rows = [pool[j] for j in range(n)]
+    crows = [comp[j] for j in range(n)]
+    mask = np.full(nw, np.uint64(0xFFFFFFFFFFFFFFFF))
+    mask[-1] = np.uint64(tail_mask(r))
+    cap = tq.tq_rle_max_words(r)
+    enc = []
+    for j in range(n):
+        s = torch.empty(cap, dtype=torch.int64, device="cuda")
+        ln = torch.zeros(1, dtype=torch.int64, device="cuda")
+        tq.tq_rle_encode(ctx, crows[j], r, s, cap, ln, None)
+        assert tq.tq_ctx_check(ctx) == 0
+        enc.append((s, int(ln.item()), None))
+    for theta in (1, 2, 7, n // 2, n - 1, n):
+        a = run_threshold(ctx, rows, r, theta)
+        b = run_threshold(ctx, crows, r, n - theta + 1)
+        assert np.array_equal(a, ~b & mask), theta
+        c = empty_words(nw)
+        tq.tq_threshold_rle_dense(ctx, enc, r, n - theta + 1, c)
+        assert tq.tq_ctx_check(ctx) == 0
+        assert np.array_equal(a, ~to_host(c)[:nw] & mask), theta
