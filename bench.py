@@ -34,7 +34,8 @@ def parse():
     ap.add_argument("--workload", default="large", choices=["large", "small", "rle", "serving", "selector"])
     ap.add_argument("--selector-queries", type=int, default=2500)
     ap.add_argument("--selector-train", type=int, default=2000)
-    ap.add_argument("--selector-out", default=os.path.join(ROOT, "gpurun_out", "selector"))
+    ap.add_argument("--selector-out", default=None,
+                    help="directory for the selector's timing dataset and trained weights (not written if unset)")
     ap.add_argument("--serving-queries", type=int, default=20000)
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline sample")
@@ -414,7 +415,8 @@ def bench_selector(args):
     from paper_1402_4073_amd import binding as tq
     from paper_1402_4073_amd import selector as sel
 
-    os.makedirs(args.selector_out, exist_ok=True)
+    if args.selector_out:
+        os.makedirs(args.selector_out, exist_ok=True)
     r = tqgen.SELECTOR["r_bits"]
     nw = (r + 63) // 64
     qs = tqgen.selector_queries(4, count=args.selector_queries)
@@ -500,13 +502,14 @@ def bench_selector(args):
     tq.tq_selector_set(ctx, params, mean, std, lo, hi, margin)
     agree = sum(int(np.argmin(tq.tq_selector_predict(ctx, X[i]))) == int(pred[i].argmin()) for i in range(ntr, nq))
     res["host_gpu_inference_agreement"] = agree / (nq - ntr)
-    np.savez(os.path.join(args.selector_out, "dataset.npz"), X=X, T=Tm, params=params, mean=mean, std=std)
-    with open(os.path.join(args.selector_out, "weights.json"), "w") as fh:
-        json.dump({"params": params.tolist(), "mean": mean.tolist(), "std": std.tolist(), "lo": lo.tolist(),
-                   "hi": hi.tolist(), "margin": margin, "queries": nq, "train": ntr,
-                   "features": ["log2 N", "theta/N", "log10 density", "log10 ones-run", "std log10 density",
-                                "log2 r", "log2 compression", "log2 theta/(1+E count)"],
-                   "variants": list(tq.VARIANT_NAMES)}, fh)
+    if args.selector_out:
+        np.savez(os.path.join(args.selector_out, "dataset.npz"), X=X, T=Tm, params=params, mean=mean, std=std)
+        with open(os.path.join(args.selector_out, "weights.json"), "w") as fh:
+            json.dump({"params": params.tolist(), "mean": mean.tolist(), "std": std.tolist(), "lo": lo.tolist(),
+                       "hi": hi.tolist(), "margin": margin, "queries": nq, "train": ntr,
+                       "features": ["log2 N", "theta/N", "log10 density", "log10 ones-run", "std log10 density",
+                                    "log2 r", "log2 compression", "log2 theta/(1+E count)"],
+                       "variants": list(tq.VARIANT_NAMES)}, fh)
     tq.tq_destroy(ctx)
     return {
         "metric": "selector regret on held-out queries (sum t_selected / sum t_best - 1)",
@@ -585,7 +588,7 @@ def time_weighted(tq, ctx, rows, r, nw, stream, steps):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: this library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 

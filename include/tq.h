@@ -64,7 +64,7 @@ typedef enum tq_status {
   TQ_ECAPACITY = -4,  /* output capacity too small; the required length is reported */
   TQ_EDEVICE = -5,    /* a HIP runtime call failed */
   TQ_EBUSY = -6,      /* admission refused: the batch ring or workspace is full, retry later */
-  TQ_ENOTSUP = -7     /* the request is valid but not supported by this build */
+  TQ_ENOTSUP = -7     /* the request is valid but not supported by this library */
 } tq_status;
 
 typedef struct tq_ctx tq_ctx;

@@ -307,7 +307,7 @@ def markov_density_runlength(seed: int, n: int, r_bits: int, density: float, mea
 
 
 # ------------------------------------------------------- the five workloads
-# Sizes of the paper-shaped synthetic workloads (see the design doc for the recipe).
+# Sizes of the paper-shaped synthetic workloads.
 SMALL = dict(n=16, r_bits=1 << 20, p=0.05, thetas=(1, 2, 8, 16))
 LARGE = dict(n=256, r_bits=1 << 26, dens=(1e-4, 0.5), thetas=(2, 16, 128, 255), interval=(2, 10))
 RLE = dict(n=512, r_bits=1 << 28, mean_ones=64.0, mean_zeros=4096.0, thetas=(2, 64, 256))
