@@ -91,8 +91,28 @@ const char* tq_status_string(int status);
                                   them; 0 (default) picks one range per resident workgroup.  Any value
                                   gives the same results; values outside [0, 2^20] are TQ_EINVAL. */
 
+#define TQ_OPTION_AUTOTUNE 3  /* value 1: the first dense or compressed-input query of each shape
+                                 class (counter width, log2 N, log2 words, epilogue, pruned theta's
+                                 eighth, alignment) times every launch shape of its kernel on the
+                                 caller's stream, synchronising it once, and caches the fastest in
+                                 the context for later queries of the class (skipped while the
+                                 stream is being captured into a graph).  0 (default): fixed
+                                 shape rules.  Results are identical either way. */
+
 /* Set a context option; TQ_EINVAL for an unknown option. */
 tq_status tq_set_option(tq_ctx* ctx, int option, int64_t value);
+
+/* The tuned launch shapes of a context as text, one shape class per line:
+ * "family K log2N log2words epilogue pruned theta8 aligned16 : p0 p1 p2 p3 : us".
+ * tq_tune_export writes the text and its terminating NUL into buf (cap
+ * bytes; cap == 0 only reports the length in *len, without the NUL;
+ * TQ_ECAPACITY if cap is too small).  tq_tune_import adds the lines of a
+ * NUL-terminated text to the context (TQ_EINVAL, and nothing added, if any
+ * line is malformed or names a shape that does not exist).  tq_tune_clear
+ * empties the cache. */
+tq_status tq_tune_export(tq_ctx* ctx, char* buf, size_t cap, size_t* len);
+tq_status tq_tune_import(tq_ctx* ctx, const char* text);
+tq_status tq_tune_clear(tq_ctx* ctx);
 
 /* Wait for `stream`, then return (and clear) the first device-detected error
  * recorded by calls on this context, or TQ_EDEVICE if a HIP call failed. */
@@ -328,6 +348,25 @@ tq_status tq_batch_records(tq_batch* batch, tq_query_record* out);
 
 /* Wait for the batch, free its slot and the handle. */
 tq_status tq_batch_release(tq_batch* batch);
+
+/*
+ * Word-column schedule of batches: the work of a batch (64-word column groups
+ * times inputs) is cut into items so that every wave of the persistent grid
+ * gets about `items_per_wave` of them, and no item is smaller than
+ * `min_item_work` group-inputs.  tq_batch_tune submits the given batch under
+ * each candidate schedule (items per wave 1, 2, 4, 8, 16 x smallest item 4,
+ * 16, 64; best of three submissions each, timed with HIP events on `stream`,
+ * which it synchronises), keeps the fastest for later submissions on this
+ * context and returns it (either out pointer may be NULL).  The queries'
+ * outputs are written as by tq_batch_submit.  It needs a free batch slot
+ * (TQ_EBUSY otherwise) and a stream that is not being captured (TQ_EINVAL).
+ * tq_batch_set_schedule sets a schedule directly (items_per_wave in [1, 64],
+ * min_item_work in [1, 4096]); the default is 4 and 16.  Results never
+ * depend on the schedule.
+ */
+tq_status tq_batch_tune(tq_ctx* ctx, const tq_query* queries, uint32_t count, hipStream_t stream,
+                        uint32_t* items_per_wave, uint32_t* min_item_work);
+tq_status tq_batch_set_schedule(tq_ctx* ctx, uint32_t items_per_wave, uint32_t min_item_work);
 
 /* ------------------------------------------------------------------------
  * Kernel variants and the learned selector.

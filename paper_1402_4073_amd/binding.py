@@ -75,6 +75,11 @@ def _load():
         "tq_batch_wait": (_INT, [_P]),
         "tq_batch_records": (_INT, [_P, _P]),
         "tq_batch_release": (_INT, [_P]),
+        "tq_batch_tune": (_INT, [_P, _P, _U32, _P, ctypes.POINTER(_U32), ctypes.POINTER(_U32)]),
+        "tq_batch_set_schedule": (_INT, [_P, _U32, _U32]),
+        "tq_tune_export": (_INT, [_P, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
+        "tq_tune_import": (_INT, [_P, ctypes.c_char_p]),
+        "tq_tune_clear": (_INT, [_P]),
         "tq_bitmap_stats": (_INT, [_P, _P, _U64, _P, _P, _P]),
         "tq_query_features": (_INT, [_P, _U32, _U64, _U32, _P]),
         "tq_threshold_variant": (_INT, [_P, _P, _U32, _U64, _U32, _U32, _P, _P]),
@@ -172,6 +177,7 @@ def tq_destroy(ctx: int) -> None:
 
 TQ_OPTION_PRUNE = 1
 TQ_OPTION_RLE_TILES = 2
+TQ_OPTION_AUTOTUNE = 3
 
 
 def tq_set_option(ctx: int, option: int, value: int) -> None:
@@ -473,6 +479,38 @@ def raw_batch_submit(ctx: int, queries: "BatchQueries", flags: int = 0, stream=N
     h = _P()
     st = _lib.tq_batch_submit(ctx, queries.arr, queries.count, flags, _stream(stream), ctypes.byref(h))
     return st, h.value
+
+
+def tq_batch_tune(ctx: int, queries: "BatchQueries", stream=None):
+    """Time the batch under each candidate schedule; returns (items_per_wave, min_item_work) kept."""
+    a, m = _U32(), _U32()
+    _check(_lib.tq_batch_tune(ctx, queries.arr, queries.count, _stream(stream), ctypes.byref(a), ctypes.byref(m)),
+           "tq_batch_tune")
+    return a.value, m.value
+
+
+def tq_batch_set_schedule(ctx: int, items_per_wave: int, min_item_work: int) -> int:
+    return _lib.tq_batch_set_schedule(ctx, items_per_wave, min_item_work)
+
+
+def tq_tune_export(ctx: int) -> str:
+    n = ctypes.c_size_t()
+    _check(_lib.tq_tune_export(ctx, None, 0, ctypes.byref(n)), "tq_tune_export")
+    buf = ctypes.create_string_buffer(n.value + 1)
+    _check(_lib.tq_tune_export(ctx, buf, n.value + 1, ctypes.byref(n)), "tq_tune_export")
+    return buf.value.decode()
+
+
+def tq_tune_import(ctx: int, text: str) -> None:
+    _check(_lib.tq_tune_import(ctx, text.encode()), "tq_tune_import")
+
+
+def raw_tune_import(ctx: int, text: str) -> int:
+    return _lib.tq_tune_import(ctx, text.encode())
+
+
+def tq_tune_clear(ctx: int) -> None:
+    _check(_lib.tq_tune_clear(ctx), "tq_tune_clear")
 
 
 def tq_batch_poll(batch: int) -> int:

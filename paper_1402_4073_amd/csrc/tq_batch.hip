@@ -280,6 +280,10 @@ struct BatchState {
   BatchSlot slots[kSlots];
   int grid = 0;
   double tick_ns = 10.0;
+  // word-column schedule: items per wave of the grid the work is cut into,
+  // and the smallest item (in 64-word group-inputs); set by tq_batch_tune
+  uint32_t items_per_wave = 4;
+  uint32_t min_item_work = (uint32_t)kMinItemWork;
 };
 
 }  // namespace tq
@@ -432,8 +436,8 @@ tq_status tq_batch_submit(tq_ctx* ctx, const tq_query* queries, uint32_t count, 
   uint64_t work = 0;
   for (uint32_t i = 0; i < count; ++i)
     work += ((words_for_bits(queries[i].r_bits) + 63) / 64) * (uint64_t)queries[i].n;
-  const uint64_t target_items = (uint64_t)bs->grid * kItemWaves * 4;
-  const uint64_t item_work = std::max<uint64_t>(kMinItemWork, (work + target_items - 1) / target_items);
+  const uint64_t target_items = (uint64_t)bs->grid * kItemWaves * bs->items_per_wave;
+  const uint64_t item_work = std::max<uint64_t>(bs->min_item_work, (work + target_items - 1) / target_items);
   tq_batch* b = new (std::nothrow) tq_batch();
   if (!b) return TQ_ENOMEM;
   b->ctx = ctx;
@@ -550,6 +554,70 @@ tq_status tq_batch_release(tq_batch* b) {
   tq_ctx* ctx = b->ctx;
   delete b;
   return record_hip(ctx, e);
+}
+
+tq_status tq_batch_tune(tq_ctx* ctx, const tq_query* queries, uint32_t count, hipStream_t stream,
+                        uint32_t* items_per_wave, uint32_t* min_item_work) {
+  if (!ctx) return TQ_EINVAL;
+  BatchState* bs = batch_state(ctx);
+  if (!bs) return TQ_ENOMEM;
+  if (stream_capturing(stream)) return TQ_EINVAL;
+  static const uint32_t ipw[] = {1, 2, 4, 8, 16};
+  static const uint32_t miw[] = {4, 16, 64};
+  const uint32_t keep_ipw = bs->items_per_wave, keep_miw = bs->min_item_work;
+  uint32_t best_ipw = keep_ipw, best_miw = keep_miw;
+  float best_us = -1.f;
+  tq_status st = TQ_OK;
+  for (uint32_t a : ipw) {
+    for (uint32_t m : miw) {
+      bs->items_per_wave = a;
+      bs->min_item_work = m;
+      float us = -1.f;
+      // best of three submissions (packing, upload and kernels, on the stream)
+      for (int rep = 0; rep < 3 && st == TQ_OK; ++rep) {
+        tq_batch* b = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+          if (e0) (void)hipEventDestroy(e0);
+          st = record_hip(ctx, hipErrorOutOfMemory);
+          break;
+        }
+        (void)hipEventRecord(e0, stream);
+        st = tq_batch_submit(ctx, queries, count, 0, stream, &b);
+        if (st == TQ_OK) {
+          (void)hipEventRecord(e1, stream);
+          float ms = 0.f;
+          if (hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
+            us = us < 0.f ? ms * 1000.f : std::min(us, ms * 1000.f);
+          st = tq_batch_release(b);
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+      }
+      if (st != TQ_OK) break;
+      if (us > 0.f && (best_us < 0.f || us < best_us)) {
+        best_us = us;
+        best_ipw = a;
+        best_miw = m;
+      }
+    }
+    if (st != TQ_OK) break;
+  }
+  bs->items_per_wave = st == TQ_OK ? best_ipw : keep_ipw;
+  bs->min_item_work = st == TQ_OK ? best_miw : keep_miw;
+  if (items_per_wave) *items_per_wave = bs->items_per_wave;
+  if (min_item_work) *min_item_work = bs->min_item_work;
+  return st;
+}
+
+tq_status tq_batch_set_schedule(tq_ctx* ctx, uint32_t items_per_wave, uint32_t min_item_work) {
+  if (!ctx || items_per_wave == 0 || items_per_wave > 64 || min_item_work == 0 || min_item_work > 4096)
+    return TQ_EINVAL;
+  BatchState* bs = batch_state(ctx);
+  if (!bs) return TQ_ENOMEM;
+  bs->items_per_wave = items_per_wave;
+  bs->min_item_work = min_item_work;
+  return TQ_OK;
 }
 
 }  // extern "C"

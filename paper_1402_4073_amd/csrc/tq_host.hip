@@ -2,6 +2,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <functional>
 #include <new>
 
 #include "tq_internal.h"
@@ -267,6 +268,7 @@ tq_status tq_destroy(tq_ctx* ctx) {
   hipDeviceSynchronize();
   batch_destroy(ctx);
   selector_destroy(ctx);
+  tuner_destroy(ctx);
   for (auto& b : ctx->blobs) blob_release(b);
   if (ctx->ws) hipFree(ctx->ws);
   if (ctx->d_status) hipFree(ctx->d_status);
@@ -283,6 +285,9 @@ tq_status tq_set_option(tq_ctx* ctx, int option, int64_t value) {
     case TQ_OPTION_RLE_TILES:
       if (value < 0 || value > (1 << 20)) return TQ_EINVAL;
       ctx->rle_tiles = (uint32_t)value;
+      return TQ_OK;
+    case TQ_OPTION_AUTOTUNE:
+      ctx->autotune = value ? 1 : 0;
       return TQ_OK;
   }
   return TQ_EINVAL;
@@ -350,6 +355,49 @@ tq_status check_sink_args(uint64_t r_bits, const uint64_t* d_filter, const uint6
   return TQ_OK;
 }
 
+// The launch shape of a dense query: the tuned shape of its class if the
+// autotuner is on (timing every candidate on the first query of the class),
+// else the default rule.
+DenseConfig dense_shape(tq_ctx* ctx, uint32_t n, uint64_t nw, const EpiParams& epi, bool aligned16,
+                        const std::function<hipError_t(const DenseConfig&)>& launch, hipStream_t stream) {
+  const DenseConfig dflt = choose_dense_config(n, nw, aligned16, ctx->num_cus);
+  if (!ctx->autotune) return dflt;
+  TuneClass c;
+  c.family = kTuneDense;
+  c.K = dflt.K;
+  c.log_n = bit_length(n) - 1;
+  c.log_words = bit_length(nw) - 1;
+  c.kind = epi.kind;
+  c.pruned = (epi.kind == EPI_THRESH && epi.prune) ? 1 : 0;
+  c.theta_class = c.pruned ? (int)((8ull * epi.theta) / ((uint64_t)n + 1)) : 0;
+  c.aligned16 = aligned16 ? 1 : 0;
+  TuneEntry e;
+  if (tune_lookup(ctx, c, &e)) return DenseConfig{dflt.K, e.p[0], e.p[1], e.p[2]};
+  if (stream_capturing(stream)) return dflt;
+  static const int cand[][3] = {{1, 1, 1}, {1, 2, 1}, {1, 4, 1}, {1, 8, 1}, {1, 1, 4}, {2, 1, 1}, {2, 1, 4}};
+  DenseConfig best = dflt;
+  float best_us = -1.f;
+  for (const auto& q : cand) {
+    const DenseConfig cfg{dflt.K, q[0], q[1], q[2]};
+    if (cfg.wpl == 2 && !aligned16) continue;
+    if (!dense_config_valid(cfg)) continue;
+    const float us = time_launches(stream, [&]() { return launch(cfg); }, 5);
+    if (us > 0.f && (best_us < 0.f || us < best_us)) {
+      best = cfg;
+      best_us = us;
+    }
+  }
+  if (best_us > 0.f) {
+    e.p[0] = best.wpl;
+    e.p[1] = best.split;
+    e.p[2] = best.groups;
+    e.p[3] = 0;
+    e.us = best_us;
+    tune_store(ctx, c, e);
+  }
+  return best;
+}
+
 tq_status run_dense(tq_ctx* ctx, const uint64_t* const* ptrs, uint32_t n, uint64_t r_bits,
                     const SymPlan& plan, uint64_t* d_out, hipStream_t stream, bool aligned16,
                     const uint64_t* d_filter = nullptr, uint64_t* d_count = nullptr) {
@@ -370,11 +418,6 @@ tq_status run_dense(tq_ctx* ctx, const uint64_t* const* ptrs, uint32_t n, uint64
     if (st == TQ_OK && d_count) st = record_hip(ctx, launch_count_reduce(sink.partial, slots, d_count, stream));
     return st;
   }
-  const DenseConfig cfg = choose_dense_config(n, nw, aligned16, ctx->num_cus);
-  if (d_count) {
-    sink.partial = static_cast<uint32_t*>(workspace(ctx, dense_groups(cfg, nw) * sizeof(uint32_t)));
-    if (!sink.partial) return TQ_ENOMEM;
-  }
   Blob* pb = nullptr;
   const void* d_ptrs = blob_get(ctx, reinterpret_cast<const uint64_t*>(ptrs), n, stream, &pb);
   if (!d_ptrs) return TQ_EDEVICE;
@@ -388,8 +431,15 @@ tq_status run_dense(tq_ctx* ctx, const uint64_t* const* ptrs, uint32_t n, uint64
     if (!d_t) return TQ_EDEVICE;
     epi.table = reinterpret_cast<const uint32_t*>(d_t);
   }
-  tq_status st = record_hip(ctx, launch_dense(cfg, reinterpret_cast<const uint64_t* const*>(d_ptrs), n, nw,
-                                              tmask, d_out, epi, stream, sink));
+  const uint64_t* const* dp = reinterpret_cast<const uint64_t* const*>(d_ptrs);
+  const DenseConfig cfg = dense_shape(
+      ctx, n, nw, epi, aligned16,
+      [&](const DenseConfig& c) { return launch_dense(c, dp, n, nw, tmask, d_out, epi, stream); }, stream);
+  if (d_count) {
+    sink.partial = static_cast<uint32_t*>(workspace(ctx, dense_groups(cfg, nw) * sizeof(uint32_t)));
+    if (!sink.partial) return TQ_ENOMEM;
+  }
+  tq_status st = record_hip(ctx, launch_dense(cfg, dp, n, nw, tmask, d_out, epi, stream, sink));
   if (st == TQ_OK && d_count)
     st = record_hip(ctx, launch_count_reduce(sink.partial, dense_groups(cfg, nw), d_count, stream));
   blob_used(ctx, pb, stream);
@@ -398,6 +448,18 @@ tq_status run_dense(tq_ctx* ctx, const uint64_t* const* ptrs, uint32_t n, uint64
 }
 
 }  // namespace
+
+// An imported tuning entry must name a shape that exists.
+bool tq::tune_entry_valid(const TuneClass& c, const TuneEntry& e) {
+  if (!(e.us >= 0.f)) return false;
+  if (c.family == kTuneDense) {
+    const DenseConfig cfg{c.K, e.p[0], e.p[1], e.p[2]};
+    if (e.p[0] == 2 && !c.aligned16) return false;
+    return dense_config_valid(cfg) && e.p[3] == 0;
+  }
+  if (c.family == kTuneRle) return e.p[0] >= 0 && e.p[0] <= (1 << 20) && e.p[1] == 0 && e.p[2] == 0 && e.p[3] == 0;
+  return false;
+}
 
 extern "C" {
 

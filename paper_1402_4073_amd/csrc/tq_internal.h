@@ -6,6 +6,7 @@
 
 #include <string>
 #include <unordered_map>
+#include <functional>
 #include <vector>
 
 #include "../../include/tq.h"
@@ -133,6 +134,28 @@ hipError_t launch_build_index(const uint64_t* d_words, uint64_t len, uint64_t nw
                               int* d_status, hipStream_t stream);
 hipError_t launch_set_u64(uint64_t* d_dst, uint64_t value, hipStream_t stream);
 
+// --------------------------------------------------------------- autotuner
+constexpr int kTuneDense = 1;   // dense_kernel: p = {wpl, split, groups}
+constexpr int kTuneRle = 2;     // rle_tile_kernel: p = {tiles per workgroup (0: one range per slot)}
+
+struct TuneClass {
+  int family = 0, K = 0, log_n = 0, log_words = 0, kind = 0, pruned = 0, theta_class = 0, aligned16 = 0;
+};
+struct TuneEntry {
+  int32_t p[4] = {0, 0, 0, 0};
+  float us = 0.f;   // measured time of the chosen shape
+};
+
+uint64_t tune_key(const TuneClass& c);
+bool tune_lookup(tq_ctx* ctx, const TuneClass& c, TuneEntry* e);
+void tune_store(tq_ctx* ctx, const TuneClass& c, const TuneEntry& e);
+bool tune_entry_valid(const TuneClass& c, const TuneEntry& e);
+void tuner_destroy(tq_ctx* ctx);
+// true while the stream records a graph (tuning is skipped then)
+bool stream_capturing(hipStream_t stream);
+// mean microseconds of `reps` launches after one warm-up, or < 0 on error
+float time_launches(hipStream_t stream, const std::function<hipError_t()>& launch, int reps);
+
 // -------------------------------------------------------------- blob cache
 // Small host arrays that kernels read (pointer arrays, truth tables) are
 // staged through pinned memory into device memory and cached by content, so
@@ -165,6 +188,8 @@ struct tq_ctx {
   void* selector = nullptr;    // selector network and feature ranges
   int prune = 1;               // TQ_OPTION_PRUNE
   uint32_t rle_tiles = 0;      // TQ_OPTION_RLE_TILES (0: automatic)
+  int autotune = 0;            // TQ_OPTION_AUTOTUNE
+  void* tuner = nullptr;       // tuned launch shapes by shape class
 };
 
 namespace tq {

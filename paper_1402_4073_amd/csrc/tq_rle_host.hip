@@ -109,6 +109,40 @@ tq_status sym_tables(tq_ctx* ctx, uint32_t n, const uint64_t* truth, const SymPl
   return TQ_OK;
 }
 
+// Tiles per workgroup of a query over compressed inputs: the tuned value of
+// its shape class if the autotuner is on, else 0 (one range per resident
+// workgroup).
+uint32_t rle_shape(tq_ctx* ctx, uint32_t n, uint64_t nw, const RleFn& qf, const SymPlan& plan,
+                   const std::function<hipError_t(uint32_t)>& launch, hipStream_t stream) {
+  if (!ctx->autotune) return 0;
+  TuneClass c;
+  c.family = kTuneRle;
+  c.K = dense_planes_for(n);
+  c.log_n = bit_length(n) - 1;
+  c.log_words = bit_length(nw) - 1;
+  c.kind = qf.truth ? 1 + plan.epi.kind : 0;
+  c.theta_class = qf.truth ? 0 : (int)((8ull * qf.theta) / ((uint64_t)n + 1));
+  TuneEntry e;
+  if (tune_lookup(ctx, c, &e)) return (uint32_t)e.p[0];
+  if (stream_capturing(stream)) return 0;
+  static const uint32_t cand[] = {0, 1, 2, 4, 16};
+  uint32_t best = 0;
+  float best_us = -1.f;
+  for (uint32_t t : cand) {
+    const float us = time_launches(stream, [&]() { return launch(t); }, 3);
+    if (us > 0.f && (best_us < 0.f || us < best_us)) {
+      best = t;
+      best_us = us;
+    }
+  }
+  if (best_us > 0.f) {
+    e.p[0] = (int32_t)best;
+    e.us = best_us;
+    tune_store(ctx, c, e);
+  }
+  return best;
+}
+
 // Common part of the compressed-input queries: tile kernel into d_dense_out.
 // idx_area: workspace for the indexes the caller did not supply (sized with
 // missing_index_bytes), allocated by the caller before any pointer into the
@@ -153,10 +187,14 @@ tq_status run_rle_tiles(tq_ctx* ctx, const tq_rle* inputs, uint32_t n_rle, const
     d_dense = blob_get(ctx, reinterpret_cast<const uint64_t*>(dense_ptrs), n_dense, stream, &bp);
     if (!d_dense) return TQ_EDEVICE;
   }
-  st = record_hip(ctx, launch_rle_tile(reinterpret_cast<const RleDesc*>(d_desc), n_rle,
-                                       reinterpret_cast<const uint64_t* const*>(d_dense), n_dense, nw, tmask,
-                                       qf.theta, qf.truth ? &tabs.sym : nullptr, ctx->num_cus, ctx->rle_tiles,
-                                       d_dense_out, ctx->d_status, stream));
+  auto launch = [&](uint32_t tiles_per_group) {
+    return launch_rle_tile(reinterpret_cast<const RleDesc*>(d_desc), n_rle,
+                           reinterpret_cast<const uint64_t* const*>(d_dense), n_dense, nw, tmask, qf.theta,
+                           qf.truth ? &tabs.sym : nullptr, ctx->num_cus, tiles_per_group, d_dense_out,
+                           ctx->d_status, stream);
+  };
+  const uint32_t tiles = ctx->rle_tiles ? ctx->rle_tiles : rle_shape(ctx, n, nw, qf, plan, launch, stream);
+  st = record_hip(ctx, launch(tiles));
   blob_used(ctx, bd, stream);
   if (bp) blob_used(ctx, bp, stream);
   for (Blob* b : tabs.blobs)
