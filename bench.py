@@ -360,10 +360,19 @@ def bench_serving(args):
     el_d, _ = run_batched(zero, tq.TQ_BATCH_NO_GRAPH)
     el_s, _ = run_single(zero)
     sat_qps = nq / el_g
+    # word-column schedule chosen by the autotuner on one full batch, then the
+    # saturation run again (the latency runs below keep the default schedule)
+    with torch.cuda.stream(stream):
+        tuned = tq.tq_batch_tune(ctx, tq.BatchQueries.from_prepared(specs[:max_batch]), stream)
+    el_t, _ = run_batched(zero, 0)
+    tq.tq_batch_set_schedule(ctx, 4, 16)
     res["saturation"] = {
         "batched_graph": {"qps": round(nq / el_g, 1), "GBps": round(total_bytes / el_g / 1e9, 1)},
         "batched_direct": {"qps": round(nq / el_d, 1), "GBps": round(total_bytes / el_d / 1e9, 1)},
         "per_query_launch": {"qps": round(nq / el_s, 1), "GBps": round(total_bytes / el_s / 1e9, 1)},
+        "batched_graph_tuned_schedule": {"qps": round(nq / el_t, 1), "GBps": round(total_bytes / el_t / 1e9, 1),
+                                         "items_per_wave": tuned[0], "min_item_work": tuned[1]},
+        "default_schedule": {"items_per_wave": 4, "min_item_work": 16},
     }
     res["latency_ms"] = {}
     base_arr = [q.arrival_s for q in qs]      # Poisson with rate 1 query/s
@@ -585,6 +594,62 @@ def time_weighted(tq, ctx, rows, r, nw, stream, steps):
     return res
 
 
+def time_autotune(tq, tqgen, r_large, rows_large, stream, steps):
+    """Threshold queries under the default launch-shape rule and under the
+    autotuner's choice (tuned on the first query of the class), for the large
+    workload and two other shapes: few inputs, and many inputs over short
+    bitmaps."""
+    import torch
+    dev = rows_large[0].device
+    shapes = [("N=256 r=2^26", rows_large, r_large, 16)]
+    small = tqgen.bernoulli_fixed(1, 16, 1 << 20, 0.05)
+    p_small = torch.empty((small.n, small.nwords), dtype=torch.int64, device=dev)
+    tqgen.fill_gpu(small, p_small.view(-1))
+    shapes.append(("N=16 r=2^20", [p_small[j] for j in range(small.n)], small.r_bits, 2))
+    wide = tqgen.bernoulli_fixed(3, 4096, 1 << 18, 0.05)
+    p_wide = torch.empty((wide.n, wide.nwords), dtype=torch.int64, device=dev)
+    tqgen.fill_gpu(wide, p_wide.view(-1))
+    shapes.append(("N=4096 r=2^18", [p_wide[j] for j in range(wide.n)], wide.r_bits, 200))
+    res = {}
+    for name, rows, r, theta in shapes:
+        nw = (r + 63) // 64
+        out = torch.empty(nw, dtype=torch.int64, device=dev)
+        ptrs = tq.ptr_array(rows)
+        ctx = tq.tq_create(0)
+        ent = {"theta": theta}
+        tq.tq_set_option(ctx, tq.TQ_OPTION_AUTOTUNE, 1)
+        with torch.cuda.stream(stream):
+            tq.raw_threshold(ctx, ptrs, len(rows), r, theta, out.data_ptr(), stream)   # tunes the class
+            torch.cuda.synchronize()
+        # enough launches for a stable mean on short queries; the two settings
+        # alternate so that clock drift affects both alike
+        reps = max(steps, int(2e-3 / max(1e-6, r * len(rows) / 8 / 6e12)))
+        reps = min(reps, 2000)
+        acc = {"default_ms": 0.0, "tuned_ms": 0.0}
+        for _ in range(3):
+            for label, auto in (("default_ms", 0), ("tuned_ms", 1)):
+                tq.tq_set_option(ctx, tq.TQ_OPTION_AUTOTUNE, auto)
+                with torch.cuda.stream(stream):
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    for _ in range(reps):
+                        tq.raw_threshold(ctx, ptrs, len(rows), r, theta, out.data_ptr(), stream)
+                    e1.record(stream)
+                    torch.cuda.synchronize()
+                acc[label] += e0.elapsed_time(e1) / reps / 3
+        ent.update({k: round(v, 4) for k, v in acc.items()})
+        ent["launches"] = 3 * reps
+        lines = tq.tq_tune_export(ctx).strip().splitlines()
+        ent["tuned_shape"] = lines[0].split(":")[1].strip() if lines else None
+        if tq.tq_ctx_check(ctx, stream) != 0:
+            raise RuntimeError("device error in the autotune timings")
+        tq.tq_destroy(ctx)
+        res[name] = ent
+    res["shape_fields"] = "words per lane, waves splitting the inputs, column groups per workgroup, 0"
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -675,6 +740,9 @@ def main():
     tq.tq_set_option(ctx, tq.TQ_OPTION_PRUNE, 1)
     consumers = None if args.no_consumers else time_consumers(tq, ctx, rows, r, nw, stream, args.steps)
     weighted = None if args.no_consumers else time_weighted(tq, ctx, rows, r, nw, stream, args.steps)
+    autotune = None
+    if args.workload == "large" and not args.no_consumers:
+        autotune = time_autotune(tq, tqgen, r, rows, stream, args.steps)
     mean_kernel_s = sum(kernel_ms) / len(kernel_ms) / 1e3
     in_bytes_query = n * nw * 8
     out_bytes_query = nw * 8
@@ -710,6 +778,7 @@ def main():
         "prune": bool(args.prune),
         "consumers": consumers,
         "weighted": weighted,
+        "autotune": autotune,
     }
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(rows, n, nw, r, queries, args.cpu_seconds)
