@@ -91,6 +91,11 @@ const char* tq_status_string(int status);
                                   them; 0 (default) picks one range per resident workgroup.  Any value
                                   gives the same results; values outside [0, 2^20] are TQ_EINVAL. */
 
+#define TQ_OPTION_RLE_COUNTERS 4  /* column counters of queries over RLE inputs: 1 = bit planes (a
+                                     tile whose columns the fills decide reads no literal word), 2 =
+                                     SWAR 16-bit counts (every literal word added once, in the first
+                                     pass, without waiting on LDS), 0 (default) = bit planes, or
+                                     the tuned choice.  Any value gives the same results. */
 #define TQ_OPTION_AUTOTUNE 3  /* value 1: the first dense or compressed-input query of each shape
                                  class (counter width, log2 N, log2 words, epilogue, pruned theta's
                                  eighth, alignment) times every launch shape of its kernel on the

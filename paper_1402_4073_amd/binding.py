@@ -178,6 +178,7 @@ def tq_destroy(ctx: int) -> None:
 TQ_OPTION_PRUNE = 1
 TQ_OPTION_RLE_TILES = 2
 TQ_OPTION_AUTOTUNE = 3
+TQ_OPTION_RLE_COUNTERS = 4
 
 
 def tq_set_option(ctx: int, option: int, value: int) -> None:

@@ -289,6 +289,10 @@ tq_status tq_set_option(tq_ctx* ctx, int option, int64_t value) {
     case TQ_OPTION_AUTOTUNE:
       ctx->autotune = value ? 1 : 0;
       return TQ_OK;
+    case TQ_OPTION_RLE_COUNTERS:
+      if (value < 0 || value > 2) return TQ_EINVAL;
+      ctx->rle_counters = (int)value;
+      return TQ_OK;
   }
   return TQ_EINVAL;
 }
@@ -457,7 +461,8 @@ bool tq::tune_entry_valid(const TuneClass& c, const TuneEntry& e) {
     if (e.p[0] == 2 && !c.aligned16) return false;
     return dense_config_valid(cfg) && e.p[3] == 0;
   }
-  if (c.family == kTuneRle) return e.p[0] >= 0 && e.p[0] <= (1 << 20) && e.p[1] == 0 && e.p[2] == 0 && e.p[3] == 0;
+  if (c.family == kTuneRle)
+    return e.p[0] >= 0 && e.p[0] <= (1 << 20) && (e.p[1] == 1 || e.p[1] == 2) && e.p[2] == 0 && e.p[3] == 0;
   return false;
 }
 

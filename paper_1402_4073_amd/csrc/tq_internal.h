@@ -120,12 +120,13 @@ struct RleSym {
   EpiParams epi;            // f(count) on the planes of the full count
 };
 
-size_t rle_tile_lds_bytes(int K);
+size_t rle_tile_lds_bytes(int K, bool swar);
 // sym == nullptr: threshold theta; otherwise the symmetric function *sym.
+// swar: SWAR column counters (every tile in one pass) instead of bit planes.
 hipError_t launch_rle_tile(const RleDesc* d_descs, uint32_t n_rle, const uint64_t* const* d_dense,
                            uint32_t n_dense, uint64_t nwords, uint64_t tail_mask, uint32_t theta,
-                           const RleSym* sym, int num_cus, uint32_t tiles_per_group, uint64_t* d_out,
-                           int* d_status, hipStream_t stream);
+                           const RleSym* sym, bool swar, int num_cus, uint32_t tiles_per_group,
+                           uint64_t* d_out, int* d_status, hipStream_t stream);
 size_t rle_encode_workspace_bytes(uint64_t nwords);
 hipError_t launch_rle_encode(const uint64_t* d_dense, uint64_t nwords, uint64_t tail_mask, uint64_t* d_out,
                              uint64_t cap, uint64_t* d_out_len, uint64_t* d_index, void* workspace,
@@ -136,7 +137,8 @@ hipError_t launch_set_u64(uint64_t* d_dst, uint64_t value, hipStream_t stream);
 
 // --------------------------------------------------------------- autotuner
 constexpr int kTuneDense = 1;   // dense_kernel: p = {wpl, split, groups}
-constexpr int kTuneRle = 2;     // rle_tile_kernel: p = {tiles per workgroup (0: one range per slot)}
+constexpr int kTuneRle = 2;     // rle_tile_kernel: p = {tiles per workgroup (0: one range per slot),
+                                //                    counters (1: bit planes, 2: SWAR)}
 
 struct TuneClass {
   int family = 0, K = 0, log_n = 0, log_words = 0, kind = 0, pruned = 0, theta_class = 0, aligned16 = 0;
@@ -188,6 +190,7 @@ struct tq_ctx {
   void* selector = nullptr;    // selector network and feature ranges
   int prune = 1;               // TQ_OPTION_PRUNE
   uint32_t rle_tiles = 0;      // TQ_OPTION_RLE_TILES (0: automatic)
+  int rle_counters = 0;        // TQ_OPTION_RLE_COUNTERS (0: automatic, 1: bit planes, 2: SWAR)
   int autotune = 0;            // TQ_OPTION_AUTOTUNE
   void* tuner = nullptr;       // tuned launch shapes by shape class
 };

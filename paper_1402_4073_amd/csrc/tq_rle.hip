@@ -29,6 +29,8 @@
 // (zero fill, ones fill, dirty), a marker starts at word 0 and at each clean
 // word after a dirty word or a different fill, and one scan of the packed pair
 // (markers, dirty words) before each word gives every output position.
+#include <type_traits>
+
 #include "tq_csa.hpp"
 
 namespace tq {
@@ -154,6 +156,35 @@ __device__ __forceinline__ uint64_t greater_than_lds(const uint64_t* planes, int
   return r;
 }
 
+// Column counters of the literal words, kept in LDS.
+//
+// Bit-sliced: K planes per column; a word is added by a ripple of atomic
+// XORs whose returned old values give the carries (see ripple_lds).  K x 4 KiB
+// per tile, but each addition waits for its LDS round trips.
+template <int K>
+struct SlicedAdd {
+  uint64_t* planes;
+  __device__ __forceinline__ void operator()(int c, uint64_t x) const { ripple_lds<K>(planes, c, x); }
+};
+
+// SWAR: 16 words per column, word q holding the 16-bit counts of positions
+// q, q + 16, q + 32 and q + 48; a word x is added with 16 atomic adds of
+// (x >> q) & E, none of which returns a value, so nothing waits on LDS.  The
+// counts never exceed the number of inputs (< 2^16), so no field carries
+// into the next.  64 KiB per tile.
+constexpr uint64_t kSwarE = 0x0001000100010001ull;
+constexpr uint64_t kSwarH = 0x8000800080008000ull;
+struct SwarAdd {
+  uint64_t* cnt;   // [16][kTile]
+  __device__ __forceinline__ void operator()(int c, uint64_t x) const {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const uint64_t v = (x >> q) & kSwarE;
+      if (v) atomicAdd((unsigned long long*)&cnt[q * kTile + c], (unsigned long long)v);
+    }
+  }
+};
+
 // Sequential reader of one stream.  A lane walking its stream one marker at a
 // time would keep a cache line of its own open for the whole walk; with every
 // lane of the device doing so, the lines no longer fit in L2 and are fetched
@@ -226,10 +257,10 @@ __device__ __forceinline__ bool read_marker(const RleDesc& dsc, Reader& rd, cons
 // into the difference array; with `lits` the literal words are also added to
 // the column counters right away (the one-pass form of a tile).  On return
 // `next` is the entry state of the following tile (the marker covering t1).
-template <int K, typename Reader>
+template <typename Add, typename Reader>
 __device__ __forceinline__ void walk_markers(const RleDesc& dsc, Reader& rd, Walk wk, uint32_t t0, uint32_t t1,
                                              uint32_t nwords, int32_t* kd, int* status, bool lits,
-                                             uint64_t* planes, Walk& next) {
+                                             const Add& add, Walk& next) {
   next = wk;
   while (wk.w < t1) {
     uint64_t m;
@@ -249,7 +280,7 @@ __device__ __forceinline__ void walk_markers(const RleDesc& dsc, Reader& rd, Wal
         atomicAdd(&kd[b - t0], -65536);
         if (lits)
           for (uint32_t col = a; col < b; ++col)
-            ripple_lds<K>(planes, (int)(col - t0), rd.at(wk.pos + 1 + (col - w1)));
+            add((int)(col - t0), rd.at(wk.pos + 1 + (col - w1)));
       }
     }
     // a marker reaching past t1 is where the next tile enters this stream
@@ -264,9 +295,9 @@ __device__ __forceinline__ void walk_markers(const RleDesc& dsc, Reader& rd, Wal
 }
 
 // Literal words of the undecided columns of [t0, t1) into the LDS counters.
-template <int K, typename Reader>
+template <typename Add, typename Reader>
 __device__ __forceinline__ void walk_literals(const RleDesc& dsc, Reader& rd, Walk wk, uint32_t t0, uint32_t t1,
-                                              uint32_t nwords, const int32_t* kd, uint64_t* planes) {
+                                              uint32_t nwords, const int32_t* kd, const Add& add) {
   while (wk.w < t1) {
     uint64_t m;
     uint32_t w1, w2;
@@ -274,7 +305,7 @@ __device__ __forceinline__ void walk_literals(const RleDesc& dsc, Reader& rd, Wa
     const uint32_t a = w1 > t0 ? w1 : t0, b = w2 < t1 ? w2 : t1;
     for (uint32_t col = a; col < b; ++col) {
       const int c = (int)(col - t0);
-      if (kd[c] < 0) ripple_lds<K>(planes, c, rd.at(wk.pos + 1 + (col - w1)));
+      if (kd[c] < 0) add(c, rd.at(wk.pos + 1 + (col - w1)));
     }
     wk.pos += 1 + (w2 - w1);
     wk.w = w2;
@@ -290,15 +321,19 @@ __device__ __forceinline__ void walk_literals(const RleDesc& dsc, Reader& rd, Wa
 // Sym = false: threshold theta (the RBMrg run cases of section 4.1: with k
 // ones fills, theta - k <= 0 gives ones and theta - k > d zeros).  Sym = true:
 // any symmetric f, decided where f is constant on [k, k + d] and otherwise
-// evaluated on k plus the counted dirty bits.
-template <int K, bool Sym>
+// evaluated on k plus the counted dirty bits.  Swar = true: SWAR column
+// counters, every tile in one pass; otherwise K bit-sliced planes.
+template <int K, bool Sym, bool Swar>
 __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(6))) void rle_tile_kernel(
     const RleDesc* __restrict__ descs, uint32_t n_rle, const uint64_t* const* __restrict__ dense,
     uint32_t n_dense, uint32_t nwords, uint64_t tail_mask, uint32_t theta, RleSym sym, uint32_t tiles_per_group,
     uint64_t* __restrict__ out, int* __restrict__ status) {
   extern __shared__ uint64_t lds[];
-  uint64_t* planes = lds;                                         // K x kTile
-  int32_t* kd = reinterpret_cast<int32_t*>(lds + K * kTile);      // kTile + 1 packed (k | d << 16)
+  constexpr int kCounterWords = Swar ? 16 : K;
+  uint64_t* planes = lds;                                         // kCounterWords x kTile
+  int32_t* kd = reinterpret_cast<int32_t*>(lds + kCounterWords * kTile);   // kTile + 1 packed (k | d << 16)
+  using Add = typename std::conditional<Swar, SwarAdd, SlicedAdd<K>>::type;
+  const Add add{planes};
   __shared__ int32_t wave_tot[kTileThreads / 64];
   __shared__ int32_t total;
 
@@ -329,13 +364,13 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(6)
   // walk at the cost of counting literal words of decided columns too.  The
   // choice follows the previous tile of the range: neighbouring tiles of a
   // bitmap tend to look alike.
-  bool one_pass = false;
+  bool one_pass = Swar;
 
   for (uint32_t tile = tile_begin; tile < tile_end; ++tile) {
     const uint32_t t0 = tile * kTile;
     const uint32_t t1 = nwords - t0 > (uint32_t)kTile ? t0 + kTile : nwords;
     if (tile != tile_begin) __syncthreads();   // the previous tile's phase 4 is done with the LDS
-    for (int i = tid; i < K * kTile; i += kTileThreads) planes[i] = 0;
+    for (int i = tid; i < kCounterWords * kTile; i += kTileThreads) planes[i] = 0;
     for (int i = tid; i <= kTile; i += kTileThreads) kd[i] = 0;
     __syncthreads();
 
@@ -350,7 +385,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(6)
         entry_ok = seek(mine, tile, t0, entry);
         if (!entry_ok) set_status(status, TQ_EFORMAT);
       }
-      if (entry_ok) walk_markers<K>(mine, rd, entry, t0, t1, nwords, kd, status, one_pass, planes, carry);
+      if (entry_ok) walk_markers(mine, rd, entry, t0, t1, nwords, kd, status, one_pass, add, carry);
       carry_ok = entry_ok;
     }
     for (uint32_t j = tid + kTileThreads; j < n_rle; j += kTileThreads) {
@@ -358,7 +393,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(6)
       Walk wk, unused;
       if (!seek(dsc, tile, t0, wk)) { set_status(status, TQ_EFORMAT); continue; }
       rx.reset(dsc.words, dsc.len);
-      walk_markers<K>(dsc, rx, wk, t0, t1, nwords, kd, status, one_pass, planes, unused);
+      walk_markers(dsc, rx, wk, t0, t1, nwords, kd, status, one_pass, add, unused);
     }
     __syncthreads();
 
@@ -385,17 +420,17 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(6)
     // a tile whose columns the fills alone decide needs no literal word
     const int need = __syncthreads_count(undecided);
     const bool walk_again = need > 0 && !one_pass;
-    one_pass = need >= kOnePassColumns;
+    one_pass = Swar || need >= kOnePassColumns;
 
     // 3. literal words of undecided columns into the per-column LDS counters
     if (walk_again) {
-      if (own && entry_ok) walk_literals<K>(mine, rd, entry, t0, t1, nwords, kd, planes);
+      if (own && entry_ok) walk_literals(mine, rd, entry, t0, t1, nwords, kd, add);
       for (uint32_t j = tid + kTileThreads; j < n_rle; j += kTileThreads) {
         const RleDesc dsc = descs[j];
         Walk wk;
         if (!seek(dsc, tile, t0, wk)) continue;
         rx.reset(dsc.words, dsc.len);
-        walk_literals<K>(dsc, rx, wk, t0, t1, nwords, kd, planes);
+        walk_literals(dsc, rx, wk, t0, t1, nwords, kd, add);
       }
     }
     __syncthreads();
@@ -415,6 +450,29 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(6)
         else
           one = k >= (int)theta;
         res = one ? ~(uint64_t)0 : 0;
+      } else if constexpr (Swar) {
+        uint64_t C[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) C[q] = planes[q * kTile + c];
+        const uint64_t col = (uint64_t)t0 + c;
+        for (uint32_t i = 0; i < n_dense; ++i) {
+          const uint64_t x = dense[i][col];
+#pragma unroll
+          for (int q = 0; q < 16; ++q) C[q] += (x >> q) & kSwarE;
+        }
+        res = 0;
+        if constexpr (!Sym) {
+          // count >= theta - k per 16-bit field: bit 15 of count + 2^15 - (theta - k)
+          const uint64_t m = (uint64_t)(0x8000u - (theta - (uint32_t)k)) * kSwarE;
+#pragma unroll
+          for (int q = 0; q < 16; ++q) res |= ((C[q] + m) & kSwarH) >> (15 - q);
+        } else {
+#pragma unroll
+          for (int p = 0; p < 64; ++p) {
+            const uint32_t tot = (uint32_t)k + (uint32_t)((C[p & 15] >> (16 * (p >> 4))) & 0xFFFF);
+            res |= ((sym.f[tot >> 6] >> (tot & 63)) & 1) << p;
+          }
+        }
       } else if (!Sym && n_dense == 0) {
         res = greater_than_lds<K>(planes, c, theta - (uint32_t)k - 1);
       } else {
@@ -646,38 +704,41 @@ typedef void (*TileFn)(const RleDesc*, uint32_t, const uint64_t* const*, uint32_
 template <bool Sym>
 TileFn pick_tile_k(int K) {
   switch (K) {
-    case 4: return rle_tile_kernel<4, Sym>;
-    case 5: return rle_tile_kernel<5, Sym>;
-    case 6: return rle_tile_kernel<6, Sym>;
-    case 7: return rle_tile_kernel<7, Sym>;
-    case 8: return rle_tile_kernel<8, Sym>;
-    case 9: return rle_tile_kernel<9, Sym>;
-    case 10: return rle_tile_kernel<10, Sym>;
-    case 11: return rle_tile_kernel<11, Sym>;
-    case 12: return rle_tile_kernel<12, Sym>;
-    case 13: return rle_tile_kernel<13, Sym>;
-    case 16: return rle_tile_kernel<16, Sym>;
+    case 4: return rle_tile_kernel<4, Sym, false>;
+    case 5: return rle_tile_kernel<5, Sym, false>;
+    case 6: return rle_tile_kernel<6, Sym, false>;
+    case 7: return rle_tile_kernel<7, Sym, false>;
+    case 8: return rle_tile_kernel<8, Sym, false>;
+    case 9: return rle_tile_kernel<9, Sym, false>;
+    case 10: return rle_tile_kernel<10, Sym, false>;
+    case 11: return rle_tile_kernel<11, Sym, false>;
+    case 12: return rle_tile_kernel<12, Sym, false>;
+    case 13: return rle_tile_kernel<13, Sym, false>;
+    case 16: return rle_tile_kernel<16, Sym, false>;
   }
   return nullptr;
 }
 
 }  // namespace
 
-size_t rle_tile_lds_bytes(int K) { return (size_t)K * kTile * 8 + (size_t)(kTile + 2) * 4; }
+size_t rle_tile_lds_bytes(int K, bool swar) {
+  return (size_t)(swar ? 16 : K) * kTile * 8 + (size_t)(kTile + 2) * 4;
+}
 
 hipError_t launch_rle_tile(const RleDesc* d_descs, uint32_t n_rle, const uint64_t* const* d_dense,
                            uint32_t n_dense, uint64_t nwords, uint64_t tail_mask, uint32_t theta,
-                           const RleSym* sym, int num_cus, uint32_t tiles_per_group, uint64_t* d_out,
-                           int* d_status, hipStream_t stream) {
+                           const RleSym* sym, bool swar, int num_cus, uint32_t tiles_per_group,
+                           uint64_t* d_out, int* d_status, hipStream_t stream) {
   const int K = dense_planes_for(n_rle + n_dense);
-  TileFn fn = sym ? pick_tile_k<true>(K) : pick_tile_k<false>(K);
+  TileFn fn = swar ? (sym ? rle_tile_kernel<16, true, true> : rle_tile_kernel<16, false, true>)
+                   : (sym ? pick_tile_k<true>(K) : pick_tile_k<false>(K));
   if (!fn) return hipErrorInvalidValue;
-  const int slot = K + (sym ? 17 : 0);
+  const int slot = swar ? 34 + (sym ? 1 : 0) : K + (sym ? 17 : 0);
   const uint64_t tiles = (nwords + kTile - 1) / kTile;
   if (tiles == 0) return hipSuccess;
-  const size_t lds = rle_tile_lds_bytes(K);
-  static bool attr_set[34] = {false};
-  static int resident[34] = {0};
+  const size_t lds = rle_tile_lds_bytes(K, swar);
+  static bool attr_set[36] = {false};
+  static int resident[36] = {0};
   if (!attr_set[slot]) {
     hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)lds);

@@ -112,9 +112,24 @@ tq_status sym_tables(tq_ctx* ctx, uint32_t n, const uint64_t* truth, const SymPl
 // Tiles per workgroup of a query over compressed inputs: the tuned value of
 // its shape class if the autotuner is on, else 0 (one range per resident
 // workgroup).
-uint32_t rle_shape(tq_ctx* ctx, uint32_t n, uint64_t nw, const RleFn& qf, const SymPlan& plan,
-                   const std::function<hipError_t(uint32_t)>& launch, hipStream_t stream) {
-  if (!ctx->autotune) return 0;
+struct RleShape {
+  uint32_t tiles = 0;   // tiles per workgroup (0: one range per resident workgroup)
+  bool swar = false;    // SWAR column counters instead of bit planes
+};
+
+// Default counters when nothing is tuned or forced: bit planes.  Measured on
+// MI355X, SWAR counters cost 16 LDS atomics per literal word where bit planes
+// take about two, which outweighs the round trips they save unless literal
+// words hold few ones (isolated bits: about 5 % faster); the tuner weighs
+// both per shape class.
+bool default_swar(const RleFn&) { return false; }
+
+RleShape rle_shape(tq_ctx* ctx, uint32_t n, uint64_t nw, const RleFn& qf, const SymPlan& plan,
+                   const std::function<hipError_t(const RleShape&)>& launch, hipStream_t stream) {
+  RleShape dflt;
+  dflt.tiles = ctx->rle_tiles;
+  dflt.swar = ctx->rle_counters ? ctx->rle_counters == 2 : default_swar(qf);
+  if (!ctx->autotune || (ctx->rle_tiles && ctx->rle_counters)) return dflt;
   TuneClass c;
   c.family = kTuneRle;
   c.K = dense_planes_for(n);
@@ -123,20 +138,33 @@ uint32_t rle_shape(tq_ctx* ctx, uint32_t n, uint64_t nw, const RleFn& qf, const 
   c.kind = qf.truth ? 1 + plan.epi.kind : 0;
   c.theta_class = qf.truth ? 0 : (int)((8ull * qf.theta) / ((uint64_t)n + 1));
   TuneEntry e;
-  if (tune_lookup(ctx, c, &e)) return (uint32_t)e.p[0];
-  if (stream_capturing(stream)) return 0;
-  static const uint32_t cand[] = {0, 1, 2, 4, 16};
-  uint32_t best = 0;
+  if (tune_lookup(ctx, c, &e)) {
+    RleShape t;
+    t.tiles = ctx->rle_tiles ? ctx->rle_tiles : (uint32_t)e.p[0];
+    t.swar = ctx->rle_counters ? ctx->rle_counters == 2 : e.p[1] == 2;
+    return t;
+  }
+  if (stream_capturing(stream)) return dflt;
+  static const uint32_t tiles[] = {0, 1, 2, 4, 16};
+  RleShape best = dflt;
   float best_us = -1.f;
-  for (uint32_t t : cand) {
-    const float us = time_launches(stream, [&]() { return launch(t); }, 3);
-    if (us > 0.f && (best_us < 0.f || us < best_us)) {
-      best = t;
-      best_us = us;
+  for (int sw = 0; sw < 2; ++sw) {
+    if (ctx->rle_counters && (ctx->rle_counters == 2) != (sw == 1)) continue;
+    for (uint32_t t : tiles) {
+      if (ctx->rle_tiles && t != ctx->rle_tiles) continue;
+      RleShape cand;
+      cand.tiles = t;
+      cand.swar = sw == 1;
+      const float us = time_launches(stream, [&]() { return launch(cand); }, 3);
+      if (us > 0.f && (best_us < 0.f || us < best_us)) {
+        best = cand;
+        best_us = us;
+      }
     }
   }
   if (best_us > 0.f) {
-    e.p[0] = (int32_t)best;
+    e.p[0] = (int32_t)best.tiles;
+    e.p[1] = best.swar ? 2 : 1;
     e.us = best_us;
     tune_store(ctx, c, e);
   }
@@ -187,14 +215,13 @@ tq_status run_rle_tiles(tq_ctx* ctx, const tq_rle* inputs, uint32_t n_rle, const
     d_dense = blob_get(ctx, reinterpret_cast<const uint64_t*>(dense_ptrs), n_dense, stream, &bp);
     if (!d_dense) return TQ_EDEVICE;
   }
-  auto launch = [&](uint32_t tiles_per_group) {
+  auto launch = [&](const RleShape& sh) {
     return launch_rle_tile(reinterpret_cast<const RleDesc*>(d_desc), n_rle,
                            reinterpret_cast<const uint64_t* const*>(d_dense), n_dense, nw, tmask, qf.theta,
-                           qf.truth ? &tabs.sym : nullptr, ctx->num_cus, tiles_per_group, d_dense_out,
+                           qf.truth ? &tabs.sym : nullptr, sh.swar, ctx->num_cus, sh.tiles, d_dense_out,
                            ctx->d_status, stream);
   };
-  const uint32_t tiles = ctx->rle_tiles ? ctx->rle_tiles : rle_shape(ctx, n, nw, qf, plan, launch, stream);
-  st = record_hip(ctx, launch(tiles));
+  st = record_hip(ctx, launch(rle_shape(ctx, n, nw, qf, plan, launch, stream)));
   blob_used(ctx, bd, stream);
   if (bp) blob_used(ctx, bp, stream);
   for (Blob* b : tabs.blobs)

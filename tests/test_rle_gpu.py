@@ -21,9 +21,11 @@ pytestmark = pytest.mark.gpu
 STRIDE = tq.TQ_RLE_INDEX_STRIDE
 
 
-@pytest.fixture(scope="module")
-def ctx():
+@pytest.fixture(scope="module", params=[1, 2], ids=["bitplanes", "swar"])
+def ctx(request):
+    """Every test runs with each kind of column counters of the tile kernel."""
     c = tq.tq_create(0)
+    tq.tq_set_option(c, tq.TQ_OPTION_RLE_COUNTERS, request.param)
     yield c
     tq.tq_destroy(c)
 
