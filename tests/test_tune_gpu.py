@@ -108,7 +108,8 @@ def test_tune_export_import_roundtrip():
     "1 9 8 20 0 1 3 1 : 2 2 1 0 : 5.0\n",            # two-word lanes are not split
     "1 7 8 20 0 1 3 1 : 1 1 1 0 : 5.0\n1 9 8 x\n",   # malformed second line
     "1 9 8 20 0 1 3 1 : 1 1 1 0\n",                  # missing time
-    "2 9 8 20 0 0 3 0 : -1 0 0 0 : 5.0\n",           # negative tiles per workgroup
+    "2 9 8 20 0 0 3 0 : -1 1 0 0 : 5.0\n",           # negative tiles per workgroup
+    "2 9 8 20 0 0 3 0 : 4 3 0 0 : 5.0\n",            # counters 3 do not exist
     "7 9 8 20 0 0 3 0 : 1 0 0 0 : 5.0\n",            # unknown family
 ])
 def test_tune_import_rejects(tctx, text):
@@ -153,7 +154,7 @@ def test_autotune_rle(tctx):
     rows = parse(tq.tq_tune_export(tctx))
     rle = [x for x in rows if x[0][0] == 2]
     assert len(rle) >= 4
-    assert all(p[0] in (0, 1, 2, 4, 16) and p[1:] == [0, 0, 0] for _, p, _ in rle)
+    assert all(p[0] in (0, 1, 2, 4, 16) and p[1] in (1, 2) and p[2:] == [0, 0] for _, p, _ in rle)
 
 
 def test_batch_tune_keeps_results(tctx):
