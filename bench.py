@@ -83,11 +83,14 @@ def load_traffic(kernel_key: str):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(pool_rows, n, nwords, r_bits, queries, target_s):
-    """The oracle as it stands, on a contiguous column sample of every bitmap."""
+def cpu_baseline(pool_rows, n, nwords, r_bits, queries, target_s, threads=None):
+    """The oracle as it stands, on a contiguous column sample of every bitmap
+    (all of the host's OpenMP threads, or `threads`)."""
     import numpy as np
     import oracle
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    if threads:
+        oracle.set_threads(threads)
+    threads = oracle.max_threads()
     m = 2048
     sample_host = None
     while True:
@@ -218,7 +221,7 @@ def bench_rle(args):
     }
     if not args.no_cpu_baseline:
         # the oracle on a prefix of every bitmap: threshold then canonical encoding
-        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+        threads = oracle.max_threads()
         cols = np.arange(sample_cols, dtype=np.uint64)
         rs = sample_cols * 64
         t0 = time.perf_counter()
@@ -782,6 +785,8 @@ def main():
     }
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(rows, n, nw, r, queries, args.cpu_seconds)
+        # one thread, as the paper's single-threaded Java measurements
+        rec["cpu_single_thread"] = cpu_baseline(rows, n, nw, r, queries, args.cpu_seconds / 3, threads=1)
     tq.tq_destroy(ctx)
     print(json.dumps(rec), flush=True)
 

@@ -55,6 +55,10 @@ def lib():
         L.oracle_rle_encode.restype = U64
         L.oracle_run_count.argtypes = [P, U64]
         L.oracle_run_count.restype = U64
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
+        L.oracle_set_threads.restype = None
+        L.oracle_max_threads.argtypes = []
+        L.oracle_max_threads.restype = ctypes.c_int
         L.oracle_count.argtypes = [P, U64]
         L.oracle_count.restype = U64
         L.oracle_weighted_threshold.argtypes = [P, U32, P, U64, U64, P]
@@ -117,6 +121,15 @@ def weighted_threshold(bitmaps, weights, r_bits: int, theta: int) -> np.ndarray:
     if rc:
         raise ValueError("oracle_weighted_threshold: %d" % rc)
     return out
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops (timing only)."""
+    lib().oracle_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(lib().oracle_max_threads())
 
 
 def count(words, r_bits: int) -> int:

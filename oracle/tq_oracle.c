@@ -37,6 +37,7 @@
  *    words are never emitted as literals.  With ceil(r/64) < 2^31 the count
  *    fields never overflow, so no run is ever split.
  */
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -182,6 +183,13 @@ uint64_t oracle_count(const uint64_t* words, uint64_t r_bits) {
   for (uint64_t p = 0; p < r_bits; ++p) c += (words[p / 64] >> (p % 64)) & 1;
   return c;
 }
+
+/* Threads of the OpenMP loops above (timing only; results do not depend on it). */
+void oracle_set_threads(int n) {
+  if (n > 0) omp_set_num_threads(n);
+}
+
+int oracle_max_threads(void) { return omp_get_max_threads(); }
 
 /* ------------------------------------------------------------------ RLE */
 
