@@ -37,6 +37,10 @@ def parse():
     ap.add_argument("--selector-out", default=None,
                     help="directory for the selector's timing dataset and trained weights (not written if unset)")
     ap.add_argument("--serving-queries", type=int, default=20000)
+    ap.add_argument("--serving-inflight", type=int, default=4,
+                    help="batches in flight at once in the serving client (1..4)")
+    ap.add_argument("--serving-shared-stream", action="store_true",
+                    help="submit every batch on one stream instead of one stream per slot")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -273,9 +277,12 @@ def bench_serving(args):
     ctx = tq.tq_create(0)
     stream = torch.cuda.Stream(device=dev)
     max_batch = 1024
-    slots = 4
-    # each batch slot gets its own stream so that small batches overlap
-    slot_streams = [torch.cuda.Stream(device=dev) for _ in range(slots)]
+    slots = max(1, min(4, args.serving_inflight))
+    # each batch slot gets its own stream so that small batches overlap (or all share one)
+    if args.serving_shared_stream:
+        slot_streams = [stream] * slots
+    else:
+        slot_streams = [torch.cuda.Stream(device=dev) for _ in range(slots)]
 
     # host pointer arrays are marshalled once, outside every timed region
     specs = [tq.PreparedQuery([rows[m] for m in q.members], r, outs[i % n_out], theta=q.theta, tag=i)
@@ -306,9 +313,12 @@ def bench_serving(args):
                 d = tq.tq_batch_poll(h)
                 if d > seen:
                     t = time.perf_counter() - t0
-                    recs = tq.tq_batch_records(h, b - a)
-                    newly = (recs["done"] != 0) & (done_at[a:b] == 0.0)
-                    done_at[a:b][newly] = t
+                    if b - a == 1:
+                        done_at[a] = t
+                    else:
+                        recs = tq.tq_batch_records(h, b - a)
+                        newly = (recs["done"] != 0) & (done_at[a:b] == 0.0)
+                        done_at[a:b][newly] = t
                     completed += d - seen
                     ent[3] = d
                 if ent[3] == b - a:
@@ -405,7 +415,8 @@ def bench_serving(args):
         "dtype": "u64 bitwise", "data": "synthetic (seeded Bernoulli pool resident in HBM)",
         "config": {"workload": "serving: pool 8192 x r=2^23 bits (8 GiB), %d queries, N log-uniform [2,1024], "
                                "theta uniform [1,N], Poisson arrivals" % nq,
-                   "logical_input_bytes": total_bytes, "max_batch": max_batch, "slots": slots},
+                   "logical_input_bytes": total_bytes, "max_batch": max_batch, "slots": slots,
+                   "shared_stream": bool(args.serving_shared_stream)},
         "serving": res,
     }
     return rec

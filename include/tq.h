@@ -320,7 +320,8 @@ typedef struct tq_query_record {
 typedef struct tq_batch tq_batch;
 
 /* Flags of tq_batch_submit. */
-#define TQ_BATCH_NO_GRAPH 1u    /* launch directly instead of replaying the slot's graph */
+#define TQ_BATCH_NO_GRAPH 1u    /* launch directly instead of replaying the slot's graph (batches of
+                                   fewer than 64 queries are always launched directly) */
 
 /* Largest batch: queries and total pointer entries (sum of n). */
 #define TQ_BATCH_MAX_QUERIES 8192u

@@ -400,9 +400,9 @@ class TqQueryRecord(ctypes.Structure):
 
 
 class PreparedQuery:
-    """A query with its host pointer array already built (marshalled once,
-    reusable across submissions)."""
-    __slots__ = ("ptrs", "n", "r_bits", "theta", "out", "tag", "truth")
+    """A query with its host pointer array and tq_query record already built
+    (marshalled once, reusable across submissions)."""
+    __slots__ = ("ptrs", "n", "r_bits", "theta", "out", "tag", "truth", "rec")
 
     def __init__(self, inputs, r_bits, out, theta=None, truth=None, tag=0):
         self.ptrs = ptr_array(inputs)
@@ -412,6 +412,19 @@ class PreparedQuery:
         self.theta = theta
         self.truth = _u64_host(truth_words(truth)) if truth is not None else None
         self.tag = int(tag)
+        q = TqQuery()
+        q.n = self.n
+        q.ptrs = ctypes.addressof(self.ptrs)
+        q.r_bits = self.r_bits
+        q.d_out = self.out
+        q.user_tag = self.tag
+        if self.truth is not None:
+            q.kind = TQ_QUERY_SYMMETRIC
+            q.h_truth = ctypes.addressof(self.truth)
+        else:
+            q.kind = TQ_QUERY_THRESHOLD
+            q.theta = theta
+        self.rec = q
 
 
 def tq_threshold_prepared(ctx: int, pq: "PreparedQuery", stream=None) -> None:
@@ -427,19 +440,10 @@ class BatchQueries:
         self = cls.__new__(cls)
         self.keep = list(prepared)
         self.arr = (TqQuery * max(1, len(prepared)))()
+        size = ctypes.sizeof(TqQuery)
+        base = ctypes.addressof(self.arr)
         for i, pq in enumerate(prepared):
-            q = self.arr[i]
-            q.n = pq.n
-            q.ptrs = ctypes.addressof(pq.ptrs)
-            q.r_bits = pq.r_bits
-            q.d_out = pq.out
-            q.user_tag = pq.tag
-            if pq.truth is not None:
-                q.kind = TQ_QUERY_SYMMETRIC
-                q.h_truth = ctypes.addressof(pq.truth)
-            else:
-                q.kind = TQ_QUERY_THRESHOLD
-                q.theta = pq.theta
+            ctypes.memmove(base + i * size, ctypes.addressof(pq.rec), size)
         self.count = len(prepared)
         return self
 

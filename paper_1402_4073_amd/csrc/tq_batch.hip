@@ -74,16 +74,16 @@ constexpr uint64_t kMinItemWork = 16;
 // query counts on shard i mod kShards) so that the items of one query, which
 // tend to finish together, do not all hit one address; the item that fills a
 // shard bumps the query's top counter, and the item that fills the last shard
-// completes the query.
+// completes the query.  A counter that has reached its final value is set
+// back to zero by the lane that saw it get there (nothing else touches it in
+// this batch), so the next batch of the slot finds them all zero without a
+// reset launch; they are zeroed once when the slot is created.
 constexpr uint32_t kShards = 64;
-
-__global__ void batch_reset_kernel(BatchHeader* hdr, uint32_t* qshard, uint32_t* qtop) {
-  const uint32_t nq = hdr->nq;
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nq * kShards; i += gridDim.x * blockDim.x)
-    qshard[i] = 0;
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nq; i += gridDim.x * blockDim.x) qtop[i] = 0;
-  if (blockIdx.x == 0 && threadIdx.x == 0) hdr->next = 0;
-}
+// Batches of fewer queries are launched directly (copy + kernel) rather than
+// by replaying the slot's graph: on this runtime a graph launch costs more
+// host time than the two direct calls, which shows in the latency of small
+// batches.
+constexpr uint32_t kGraphMinQueries = 64;
 
 // The packed batch is not written while the kernel runs (only the work
 // counter in its header is), so descriptors, item starts and pointer arrays
@@ -237,11 +237,13 @@ __global__ __launch_bounds__(64 * kItemWaves) void batch_kernel(char* buf, uint3
         const uint32_t shard = s_local[lane] % kShards;
         const uint32_t nshards = items < kShards ? items : kShards;
         const uint32_t shard_items = (items - shard + kShards - 1) / kShards;
-        bool last = __hip_atomic_fetch_add(&qshard[(uint64_t)qq * kShards + shard], 1u, __ATOMIC_RELEASE,
-                                           __HIP_MEMORY_SCOPE_AGENT) + 1 == shard_items;
+        uint32_t* sc = &qshard[(uint64_t)qq * kShards + shard];
+        bool last = __hip_atomic_fetch_add(sc, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) + 1 == shard_items;
         if (last) {
+          __hip_atomic_store(sc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
           last = __hip_atomic_fetch_add(&qtop[qq], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) + 1 == nshards;
+          if (last) __hip_atomic_store(&qtop[qq], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         if (last) {
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -320,33 +322,27 @@ tq_status slot_init(tq_ctx* ctx, BatchState* bs, BatchSlot& s) {
   s.cap_bytes = bytes;
   if ((e = hipMalloc((void**)&s.d_qdone, (size_t)kSlotQueries * (kShards + 1) * 4)) != hipSuccess)
     return record_hip(ctx, e);
+  // the completion counters start at zero and every batch leaves them at zero
+  if ((e = hipMemset(s.d_qdone, 0, (size_t)kSlotQueries * (kShards + 1) * 4)) != hipSuccess ||
+      (e = hipDeviceSynchronize()) != hipSuccess)
+    return record_hip(ctx, e);
   s.d_qstarted = s.d_qdone + (size_t)kSlotQueries * kShards;
   if ((e = hipHostMalloc((void**)&s.h_rec, kSlotQueries * sizeof(BatchRecord),
                          hipHostMallocMapped | hipHostMallocCoherent)) != hipSuccess)
     return record_hip(ctx, e);
   if ((e = hipHostGetDevicePointer((void**)&s.d_rec, s.h_rec, 0)) != hipSuccess) return record_hip(ctx, e);
   if ((e = hipEventCreateWithFlags(&s.done_ev, hipEventDisableTiming)) != hipSuccess) return record_hip(ctx, e);
-  // graph: copy the packed buffer, reset the counters, run the persistent kernel
+  // graph: copy the packed buffer, run the persistent kernel
   if ((e = hipGraphCreate(&s.graph, 0)) != hipSuccess) return record_hip(ctx, e);
   if ((e = hipGraphAddMemcpyNode1D(&s.copy_node, s.graph, nullptr, 0, s.d_buf, s.h_buf, sizeof(BatchHeader),
                                    hipMemcpyHostToDevice)) != hipSuccess)
     return record_hip(ctx, e);
   // kernel parameter values are copied when the node is created
-  BatchHeader* hdr_arg = reinterpret_cast<BatchHeader*>(s.d_buf);
   uint32_t* qd = s.d_qdone;
   uint32_t* qs = s.d_qstarted;
   char* buf = s.d_buf;
   BatchRecord* rec = s.d_rec;
-  void* rargs[3] = {&hdr_arg, &qd, &qs};
-  hipKernelNodeParams rp{};
-  rp.func = reinterpret_cast<void*>(batch_reset_kernel);
-  rp.gridDim = dim3(32);
-  rp.blockDim = dim3(256);
-  rp.sharedMemBytes = 0;
-  rp.kernelParams = rargs;
-  rp.extra = nullptr;
-  hipGraphNode_t reset_node, kernel_node;
-  if ((e = hipGraphAddKernelNode(&reset_node, s.graph, &s.copy_node, 1, &rp)) != hipSuccess) return record_hip(ctx, e);
+  hipGraphNode_t kernel_node;
   void* kargs[4] = {&buf, &qd, &qs, &rec};
   hipKernelNodeParams kp{};
   kp.func = reinterpret_cast<void*>(batch_kernel);
@@ -355,7 +351,8 @@ tq_status slot_init(tq_ctx* ctx, BatchState* bs, BatchSlot& s) {
   kp.sharedMemBytes = 0;
   kp.kernelParams = kargs;
   kp.extra = nullptr;
-  if ((e = hipGraphAddKernelNode(&kernel_node, s.graph, &reset_node, 1, &kp)) != hipSuccess) return record_hip(ctx, e);
+  if ((e = hipGraphAddKernelNode(&kernel_node, s.graph, &s.copy_node, 1, &kp)) != hipSuccess)
+    return record_hip(ctx, e);
   if ((e = hipGraphInstantiate(&s.exec, s.graph, nullptr, nullptr, 0)) != hipSuccess) return record_hip(ctx, e);
   return TQ_OK;
 }
@@ -491,11 +488,12 @@ tq_status tq_batch_submit(tq_ctx* ctx, const tq_query* queries, uint32_t count, 
   h->off_item_begin = off_ib;
   h->off_ptrs = off_p;
   hipError_t e;
-  if (flags & TQ_BATCH_NO_GRAPH) {
-    BatchHeader* dh = reinterpret_cast<BatchHeader*>(s.d_buf);
+  if ((flags & TQ_BATCH_NO_GRAPH) || count < kGraphMinQueries) {
+    // no more workgroups than rounds of items (a small batch starts no idle ones)
+    const uint64_t rounds = (items + kItemWaves - 1) / kItemWaves;
+    const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)bs->grid, rounds));
     if ((e = hipMemcpyAsync(s.d_buf, s.h_buf, used, hipMemcpyHostToDevice, stream)) == hipSuccess) {
-      hipLaunchKernelGGL(batch_reset_kernel, dim3(32), dim3(256), 0, stream, dh, s.d_qdone, s.d_qstarted);
-      hipLaunchKernelGGL(batch_kernel, dim3(bs->grid), dim3(64 * kItemWaves), 0, stream, s.d_buf, s.d_qdone,
+      hipLaunchKernelGGL(batch_kernel, dim3(grid), dim3(64 * kItemWaves), 0, stream, s.d_buf, s.d_qdone,
                          s.d_qstarted, s.d_rec);
       e = hipGetLastError();
     }
