@@ -57,12 +57,16 @@ def make_specs(rng, base, dpool, nw, count, with_symmetric=True):
     return specs, want
 
 
+@pytest.mark.parametrize("count", [60, 130])    # below and above the graph threshold (64 queries)
 @pytest.mark.parametrize("flags", [0, tq.TQ_BATCH_NO_GRAPH])
-def test_batch_matches_oracle(ctx, pool, flags):
+def test_batch_matches_oracle(ctx, pool, flags, count):
+    """Every query of random batches equals the oracle, over repeated
+    submissions on the same slot (graph replays for the larger batches): the
+    completion counters each batch leaves behind must be zero again."""
     base, dpool, nw = pool
-    rng = np.random.default_rng(7 + flags)
+    rng = np.random.default_rng(7 + flags + count)
     for rep in range(3):                      # repeated replays of the same slot graph
-        specs, want = make_specs(rng, base, dpool, nw, 60)
+        specs, want = make_specs(rng, base, dpool, nw, count)
         bq = tq.BatchQueries(specs)
         b = tq.tq_batch_submit(ctx, bq, flags)
         torch.cuda.synchronize()             # eager work between replays
