@@ -91,6 +91,11 @@ const char* tq_status_string(int status);
                                   them; 0 (default) picks one range per resident workgroup.  Any value
                                   gives the same results; values outside [0, 2^20] are TQ_EINVAL. */
 
+#define TQ_OPTION_LOOPED 5  /* value 1 (default): dense thresholds with theta <= 3 use saturating
+                              counters (Looped, section 4.5), and theta >= N - 2 the same on the
+                              complemented inputs (complement identity, section 2.3, corrected
+                              form), testing every 8 inputs whether all positions are decided;
+                              0: always the carry-save counter.  Results are identical. */
 #define TQ_OPTION_RLE_COUNTERS 4  /* column counters of queries over RLE inputs: 1 = bit planes (a
                                      tile whose columns the fills decide reads no literal word), 2 =
                                      SWAR 16-bit counts (every literal word added once, in the first

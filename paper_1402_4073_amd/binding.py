@@ -179,6 +179,7 @@ TQ_OPTION_PRUNE = 1
 TQ_OPTION_RLE_TILES = 2
 TQ_OPTION_AUTOTUNE = 3
 TQ_OPTION_RLE_COUNTERS = 4
+TQ_OPTION_LOOPED = 5
 
 
 def tq_set_option(ctx: int, option: int, value: int) -> None:

@@ -289,6 +289,9 @@ tq_status tq_set_option(tq_ctx* ctx, int option, int64_t value) {
     case TQ_OPTION_AUTOTUNE:
       ctx->autotune = value ? 1 : 0;
       return TQ_OK;
+    case TQ_OPTION_LOOPED:
+      ctx->looped = value ? 1 : 0;
+      return TQ_OK;
     case TQ_OPTION_RLE_COUNTERS:
       if (value < 0 || value > 2) return TQ_EINVAL;
       ctx->rle_counters = (int)value;
@@ -436,6 +439,15 @@ tq_status run_dense(tq_ctx* ctx, const uint64_t* const* ptrs, uint32_t n, uint64
     epi.table = reinterpret_cast<const uint32_t*>(d_t);
   }
   const uint64_t* const* dp = reinterpret_cast<const uint64_t* const*>(d_ptrs);
+  // thresholds within 3 of either end: saturating counters (no consumers)
+  uint32_t lt = 0;
+  bool lcomp = false;
+  if (ctx->looped && !fused && epi.kind == EPI_THRESH && !epi.invert && looped_applies(n, epi.theta, &lt, &lcomp)) {
+    tq_status st = record_hip(ctx, launch_looped(dp, n, nw, tmask, epi.theta, epi.prune != 0, d_out, stream));
+    blob_used(ctx, pb, stream);
+    if (tb) blob_used(ctx, tb, stream);
+    return st;
+  }
   const DenseConfig cfg = dense_shape(
       ctx, n, nw, epi, aligned16,
       [&](const DenseConfig& c) { return launch_dense(c, dp, n, nw, tmask, d_out, epi, stream); }, stream);

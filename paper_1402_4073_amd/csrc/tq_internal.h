@@ -81,6 +81,12 @@ hipError_t launch_dense(const DenseConfig& cfg, const uint64_t* const* d_ptrs, u
 hipError_t launch_fill(uint64_t* d_out, uint64_t nwords, uint64_t value, uint64_t tail_mask,
                        hipStream_t stream);
 
+// Saturating counters for theta <= 3, or theta >= n - 2 on the complemented
+// inputs (Looped, section 4.5; complement identity, section 2.3).
+bool looped_applies(uint32_t n, uint32_t theta, uint32_t* t, bool* comp);
+hipError_t launch_looped(const uint64_t* const* d_ptrs, uint32_t n, uint64_t nwords, uint64_t tail_mask,
+                         uint32_t theta, bool prune, uint64_t* d_out, hipStream_t stream);
+
 // Weighted threshold: inputs [begin, end) of the (reordered) pointer array
 // all carry `weight`.
 struct WeightClass {
@@ -192,6 +198,7 @@ struct tq_ctx {
   uint32_t rle_tiles = 0;      // TQ_OPTION_RLE_TILES (0: automatic)
   int rle_counters = 0;        // TQ_OPTION_RLE_COUNTERS (0: automatic, 1: bit planes, 2: SWAR)
   int autotune = 0;            // TQ_OPTION_AUTOTUNE
+  int looped = 1;              // TQ_OPTION_LOOPED
   void* tuner = nullptr;       // tuned launch shapes by shape class
 };
 

@@ -29,6 +29,7 @@
 // (zero fill, ones fill, dirty), a marker starts at word 0 and at each clean
 // word after a dirty word or a different fill, and one scan of the packed pair
 // (markers, dirty words) before each word gives every output position.
+#include <mutex>
 #include <type_traits>
 
 #include "tq_csa.hpp"
@@ -737,20 +738,29 @@ hipError_t launch_rle_tile(const RleDesc* d_descs, uint32_t n_rle, const uint64_
   const uint64_t tiles = (nwords + kTile - 1) / kTile;
   if (tiles == 0) return hipSuccess;
   const size_t lds = rle_tile_lds_bytes(K, swar);
-  static bool attr_set[36] = {false};
-  static int resident[36] = {0};
-  if (!attr_set[slot]) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)lds);
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(fn), kTileThreads,
-                                                     lds) != hipSuccess || per_cu < 1)
-      per_cu = 1;
-    resident[slot] = per_cu;
-    attr_set[slot] = true;
+  // LDS limit and resident workgroups per CU, set and measured once per device
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static int resident[kMaxDevices][36] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  int per_cu = 0;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    if (dev >= 0 && dev < kMaxDevices) per_cu = resident[dev][slot];
+    if (per_cu == 0) {
+      e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+      if (e != hipSuccess) return e;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(fn), kTileThreads,
+                                                       lds) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+      if (dev >= 0 && dev < kMaxDevices) resident[dev][slot] = per_cu;
+    }
   }
   // by default one range of consecutive tiles per resident workgroup
-  const uint64_t slots = (uint64_t)(num_cus > 0 ? num_cus : 1) * (uint64_t)resident[slot];
+  const uint64_t slots = (uint64_t)(num_cus > 0 ? num_cus : 1) * (uint64_t)per_cu;
   uint64_t per_group = tiles_per_group ? tiles_per_group : (tiles + slots - 1) / slots;
   if (per_group > tiles) per_group = tiles;
   const uint64_t ranges = (tiles + per_group - 1) / per_group;

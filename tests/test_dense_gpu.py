@@ -304,3 +304,45 @@ def test_complement_identity_gpu(ctx):
         tq.tq_threshold_rle_dense(ctx, enc, r, n - theta + 1, c)
         assert tq.tq_ctx_check(ctx) == 0
         assert np.array_equal(a, ~to_host(c)[:nw] & mask), theta
+
+
+@pytest.mark.parametrize("p", [0.02, 0.5, 0.97])
+def test_looped_extreme_thresholds(ctx, p):
+    """Thresholds within 3 of either end run on saturating counters (directly,
+    or on the complemented inputs); they must equal the oracle and the
+    carry-save kernel, with and without early exit, over ragged tails."""
+    rng = np.random.default_rng(int(p * 100))
+    for n, r in ((1, 64 * 70 + 3), (2, 640), (3, 64 * 129), (4, 64 * 200 + 1), (5, 64 * 65),
+                 (16, 64 * 300 + 17), (40, 64 * 128), (300, 64 * 70 + 63)):
+        nw = (r + 63) // 64
+        host = rand_words(rng, n, nw, p)
+        pool = dev_pool(host)
+        rows = [pool[j] for j in range(n)]
+        for theta in sorted({t for t in (1, 2, 3, n - 2, n - 1, n) if 1 <= t <= n}):
+            want = oracle.threshold(list(host), r, theta)
+            for looped, prune in ((1, 1), (1, 0), (0, 1)):
+                tq.tq_set_option(ctx, tq.TQ_OPTION_LOOPED, looped)
+                tq.tq_set_option(ctx, tq.TQ_OPTION_PRUNE, prune)
+                got = run_threshold(ctx, rows, r, theta)
+                assert np.array_equal(got, want), (n, theta, looped, prune)
+    tq.tq_set_option(ctx, tq.TQ_OPTION_LOOPED, 1)
+    tq.tq_set_option(ctx, tq.TQ_OPTION_PRUNE, 1)
+
+
+def test_looped_exhaustive():
+    """On the exhaustive fixture (every input combination once) each extreme
+    threshold selects exactly the positions with popcount >= theta."""
+    c = tq.tq_create(0)
+    try:
+        for n in (3, 6, 9):
+            r = 1 << n
+            host = [tqgen.exhaustive_words(j, n) for j in range(n)]
+            pool = dev_pool(host)
+            rows = [pool[j] for j in range(n)]
+            pc = np.array([bin(q).count("1") for q in range(r)])
+            for theta in sorted({t for t in (1, 2, 3, n - 2, n - 1, n) if t >= 1}):
+                got = run_threshold(c, rows, r, theta)
+                bits = np.unpackbits(got.view(np.uint8), bitorder="little")[:r]
+                assert np.array_equal(bits, (pc >= theta).astype(np.uint8)), (n, theta)
+    finally:
+        tq.tq_destroy(c)
