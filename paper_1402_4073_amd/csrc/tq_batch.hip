@@ -117,10 +117,20 @@ __device__ __forceinline__ void run_group(CBatchQuery& Q, CPtrArr ptrs, uint64_t
     Vec<1> P[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) P[k].w[0] = 0;
-    if (base + 64 <= Q.nwords)
-      accumulate<K, 1, false>(P, ptrs, 0, Q.n, w, Q.nwords);
-    else
-      accumulate<K, 1, true>(P, ptrs, 0, Q.n, w, Q.nwords);
+    // a threshold item stops reading once its positions are decided, as in
+    // the single-query kernel
+    const bool prune = Q.epi.kind == EPI_THRESH && Q.epi.prune && Q.epi.theta >= 1 && Q.epi.theta <= Q.n;
+    if (base + 64 <= Q.nwords) {
+      if (prune)
+        accumulate_pruned<K, 1, false>(P, ptrs, Q.n, w, Q.nwords, Q.epi.theta);
+      else
+        accumulate<K, 1, false>(P, ptrs, 0, Q.n, w, Q.nwords);
+    } else {
+      if (prune)
+        accumulate_pruned<K, 1, true>(P, ptrs, Q.n, w, Q.nwords, Q.epi.theta);
+      else
+        accumulate<K, 1, true>(P, ptrs, 0, Q.n, w, Q.nwords);
+    }
     r = epilogue<K, 1>(P, Q.epi, Q.n, nullptr);
   }
   store_word<K>(Q, w, r.w[0]);
@@ -467,6 +477,7 @@ tq_status tq_batch_submit(tq_ctx* ctx, const tq_query* queries, uint32_t count, 
     d.item_begin = (uint32_t)items;
     d.constant = plan.constant ? (plan.const_word ? 1u : 2u) : 0u;
     d.epi = plan.epi;
+    d.epi.prune = ctx->prune ? 1u : 0u;
     ib[i] = (uint32_t)items;
     items += d.items;
     memcpy(pa + pcur, q.ptrs, (size_t)q.n * 8);
