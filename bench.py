@@ -112,11 +112,24 @@ def cpu_baseline(pool_rows, n, nwords, r_bits, queries, target_s, threads=None):
             break
         m = int(min(nwords, max(2 * m, m * target_s / max(dt, 1e-3) * 1.1)))
     m, dt = sample_host
-    in_bytes = len(queries) * n * m * 8
+    reps = 1
+    if dt < target_s:
+        # the whole workload took less than the target: repeat it (adaptive
+        # repetition, as the paper times its runs)
+        reps = max(1, int(target_s / max(dt, 1e-3)))
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            for kind, arg in queries:
+                if kind == "threshold":
+                    oracle.threshold_cols(words, cols, r_bits, arg)
+                else:
+                    oracle.symmetric_cols(words, cols, r_bits, arg)
+        dt = time.perf_counter() - t0
+    in_bytes = reps * len(queries) * n * m * 8
     return {"value": round(in_bytes / dt / 1e9, 4), "unit": "GB/s", "cores": threads,
             "kind": "oracle",
-            "sample": "%d of %d word columns of all %d bitmaps, %d queries, %.1f s"
-                      % (m, nwords, n, len(queries), dt)}
+            "sample": "%d of %d word columns of all %d bitmaps, %d queries x %d passes, %.1f s"
+                      % (m, nwords, n, len(queries), reps, dt)}
 
 
 def bench_rle(args):
