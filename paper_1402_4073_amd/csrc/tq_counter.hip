@@ -50,10 +50,11 @@ __device__ __forceinline__ void count_inputs(uint64_t (&C)[W], const uint64_t* c
 template <int W>
 __global__ __launch_bounds__(256) void counter_kernel(const uint64_t* const* __restrict__ ptrs, uint32_t n,
                                                      uint64_t nwords, uint64_t tail_mask, uint32_t theta,
-                                                     const uint32_t* __restrict__ table, uint64_t* __restrict__ out) {
+                                                     const uint32_t* __restrict__ table, uint64_t* __restrict__ out,
+                                                     uint64_t block0) {
   constexpr int F = Packed<W>::F;
   constexpr uint64_t M = (W == 8) ? 0xFFull : 0xFFFFull;
-  const uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t w = (block0 + blockIdx.x) * blockDim.x + threadIdx.x;
   const uint64_t wave_base = w & ~(uint64_t)63;
   uint64_t C[W];
 #pragma unroll
@@ -117,14 +118,19 @@ __global__ void zero2_kernel(unsigned long long* a, unsigned long long* b) {
 hipError_t launch_counter(const uint64_t* const* d_ptrs, uint32_t n, uint64_t nwords, uint64_t tail_mask,
                           uint32_t theta, const uint32_t* d_table, uint64_t* d_out, hipStream_t stream) {
   const uint64_t blocks = (nwords + 255) / 256;
-  if (blocks == 0) return hipSuccess;
-  if (n <= 255)
-    hipLaunchKernelGGL(counter_kernel<8>, dim3((uint32_t)blocks), dim3(256), 0, stream, d_ptrs, n, nwords,
-                       tail_mask, theta, d_table, d_out);
-  else
-    hipLaunchKernelGGL(counter_kernel<16>, dim3((uint32_t)blocks), dim3(256), 0, stream, d_ptrs, n, nwords,
-                       tail_mask, theta, d_table, d_out);
-  return hipGetLastError();
+  const uint64_t per_launch = kMaxLaunchItems / 256;
+  for (uint64_t b0 = 0; b0 < blocks; b0 += per_launch) {
+    const uint64_t nb = blocks - b0 < per_launch ? blocks - b0 : per_launch;
+    if (n <= 255)
+      hipLaunchKernelGGL(counter_kernel<8>, dim3((uint32_t)nb), dim3(256), 0, stream, d_ptrs, n, nwords,
+                         tail_mask, theta, d_table, d_out, b0);
+    else
+      hipLaunchKernelGGL(counter_kernel<16>, dim3((uint32_t)nb), dim3(256), 0, stream, d_ptrs, n, nwords,
+                         tail_mask, theta, d_table, d_out, b0);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_stats(const uint64_t* d_dense, uint64_t r_bits, uint64_t* d_ones, uint64_t* d_runs,

@@ -35,13 +35,14 @@ using namespace csa;
 template <int K, int WPL, int S, int G>
 __global__ __launch_bounds__(64 * S * G) void dense_kernel(
     const uint64_t* const* __restrict__ ptrs, uint32_t n, uint64_t nwords, uint64_t tail_mask,
-    uint64_t* __restrict__ out, EpiParams epi, Sink sink) {
+    uint64_t* __restrict__ out, EpiParams epi, Sink sink, uint64_t block0) {
   extern __shared__ uint64_t lds[];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int g = wave / S;
   const int s = wave - g * S;
-  const uint64_t base = ((uint64_t)blockIdx.x * G + g) * (64 * WPL);
+  const uint64_t group = (block0 + blockIdx.x) * G + g;   // column group of this wave
+  const uint64_t base = group * (64 * WPL);
   const uint64_t w = base + (uint64_t)lane * WPL;
 
   // truth table for the generic epilogue, staged once per workgroup
@@ -149,7 +150,7 @@ __global__ __launch_bounds__(64 * S * G) void dense_kernel(
     for (int i = 0; i < WPL; ++i) c += (uint32_t)__popcll(v.w[i]);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
-    if (lane == 0) sink.partial[(uint64_t)blockIdx.x * G + g] = c;
+    if (lane == 0) sink.partial[group] = c;
   }
 }
 
@@ -164,9 +165,11 @@ constexpr int kFillBlock = 256;
 
 // one word per thread: out = value AND filter, popcount per block
 __global__ __launch_bounds__(kFillBlock) void fill_sink_kernel(uint64_t* __restrict__ out, uint64_t nwords,
-                                                               uint64_t value, uint64_t tail_mask, Sink sink) {
+                                                               uint64_t value, uint64_t tail_mask, Sink sink,
+                                                               uint64_t block0) {
   __shared__ uint32_t wave_sum[kFillBlock / 64];
-  const uint64_t w = (uint64_t)blockIdx.x * kFillBlock + threadIdx.x;
+  const uint64_t block = block0 + blockIdx.x;
+  const uint64_t w = block * kFillBlock + threadIdx.x;
   uint64_t v = 0;
   if (w < nwords) {
     v = (w == nwords - 1) ? (value & tail_mask) : value;
@@ -183,7 +186,7 @@ __global__ __launch_bounds__(kFillBlock) void fill_sink_kernel(uint64_t* __restr
       uint32_t t = 0;
 #pragma unroll
       for (int i = 0; i < kFillBlock / 64; ++i) t += wave_sum[i];
-      sink.partial[blockIdx.x] = t;
+      sink.partial[block] = t;
     }
   }
 }
@@ -207,7 +210,8 @@ __global__ __launch_bounds__(kReduceBlock) void count_reduce_kernel(const uint32
   }
 }
 
-typedef void (*DenseFn)(const uint64_t* const*, uint32_t, uint64_t, uint64_t, uint64_t*, EpiParams, Sink);
+typedef void (*DenseFn)(const uint64_t* const*, uint32_t, uint64_t, uint64_t, uint64_t*, EpiParams, Sink,
+                        uint64_t);
 
 // Instantiated shapes: one word per lane with S in {1,2,4,8} and G = 1 (the
 // default family), plus two-word lanes and four-wave workgroups for the tuner.
@@ -292,13 +296,18 @@ hipError_t launch_dense(const DenseConfig& cfg, const uint64_t* const* d_ptrs, u
   const uint64_t cols_per_block = (uint64_t)64 * cfg.wpl * G;
   const uint64_t blocks = (nwords + cols_per_block - 1) / cols_per_block;
   if (blocks == 0) return hipSuccess;
-  if (blocks > 0x7FFFFFFFull) return hipErrorInvalidValue;
   size_t lds = 0;
   if (epi.kind == EPI_TABLE) lds += ((size_t)epi.table_words + 1) / 2 * 8;
   if (cfg.split > 1) lds += (size_t)G * (cfg.split / 2) * cfg.K * cfg.wpl * 64 * 8;
-  hipLaunchKernelGGL(fn, dim3((uint32_t)blocks), dim3(64 * cfg.split * G), lds, stream, d_ptrs, n,
-                     nwords, tail_mask, d_out, epi, sink);
-  return hipGetLastError();
+  const uint64_t per_launch = kMaxLaunchItems / (64ull * cfg.split * G);
+  for (uint64_t b0 = 0; b0 < blocks; b0 += per_launch) {
+    const uint64_t nb = blocks - b0 < per_launch ? blocks - b0 : per_launch;
+    hipLaunchKernelGGL(fn, dim3((uint32_t)nb), dim3(64 * cfg.split * G), lds, stream, d_ptrs, n, nwords,
+                       tail_mask, d_out, epi, sink, b0);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_fill(uint64_t* d_out, uint64_t nwords, uint64_t value, uint64_t tail_mask,
@@ -316,11 +325,15 @@ uint64_t fill_groups(uint64_t nwords) { return (nwords + kFillBlock - 1) / kFill
 hipError_t launch_fill_sink(uint64_t* d_out, uint64_t nwords, uint64_t value, uint64_t tail_mask,
                             const Sink& sink, hipStream_t stream) {
   const uint64_t blocks = fill_groups(nwords);
-  if (blocks == 0) return hipSuccess;
-  if (blocks > 0x7FFFFFFFull) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(fill_sink_kernel, dim3((uint32_t)blocks), dim3(kFillBlock), 0, stream, d_out, nwords, value,
-                     tail_mask, sink);
-  return hipGetLastError();
+  const uint64_t per_launch = kMaxLaunchItems / kFillBlock;
+  for (uint64_t b0 = 0; b0 < blocks; b0 += per_launch) {
+    const uint64_t nb = blocks - b0 < per_launch ? blocks - b0 : per_launch;
+    hipLaunchKernelGGL(fill_sink_kernel, dim3((uint32_t)nb), dim3(kFillBlock), 0, stream, d_out, nwords, value,
+                       tail_mask, sink, b0);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_count_reduce(const uint32_t* d_partial, uint64_t m, uint64_t* d_count, hipStream_t stream) {

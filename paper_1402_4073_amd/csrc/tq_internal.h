@@ -63,6 +63,11 @@ int dense_planes_for(uint32_t n);
 
 DenseConfig choose_dense_config(uint32_t n, uint64_t nwords, bool aligned16, int num_cus);
 
+// Work-items of one launch stay below this: the dispatch packet holds the
+// grid size in 32 bits, and a larger launch is silently cut short.  Longer
+// bitmaps are processed by several launches over consecutive word ranges.
+constexpr uint64_t kMaxLaunchItems = 1ull << 31;
+
 // Consumers fused into the store of a result word: AND with a filter bitmap
 // (nullable) and per-column-group popcounts of the stored word (nullable;
 // one uint32 per column group, summed afterwards by launch_count_reduce).

@@ -50,8 +50,8 @@ __device__ __forceinline__ void looped_accumulate(uint64_t (&B)[T], const uint64
 template <int T, bool Comp>
 __global__ __launch_bounds__(64) void looped_kernel(const uint64_t* const* __restrict__ ptrs, uint32_t n,
                                                     uint64_t nwords, uint64_t tail_mask, uint32_t prune,
-                                                    uint64_t* __restrict__ out) {
-  const uint64_t base = (uint64_t)blockIdx.x * 64;
+                                                    uint64_t* __restrict__ out, uint64_t block0) {
+  const uint64_t base = (block0 + blockIdx.x) * 64;
   const uint64_t w = base + threadIdx.x;
   const uint64_t valid = w < nwords ? (w == nwords - 1 ? tail_mask : ~(uint64_t)0) : 0;
   uint64_t B[T];
@@ -66,7 +66,7 @@ __global__ __launch_bounds__(64) void looped_kernel(const uint64_t* const* __res
   out[w] = r & valid;
 }
 
-typedef void (*LoopedFn)(const uint64_t* const*, uint32_t, uint64_t, uint64_t, uint32_t, uint64_t*);
+typedef void (*LoopedFn)(const uint64_t* const*, uint32_t, uint64_t, uint64_t, uint32_t, uint64_t*, uint64_t);
 
 LoopedFn pick_looped(int t, bool comp) {
   switch (t) {
@@ -101,11 +101,15 @@ hipError_t launch_looped(const uint64_t* const* d_ptrs, uint32_t n, uint64_t nwo
   if (!looped_applies(n, theta, &t, &comp)) return hipErrorInvalidValue;
   LoopedFn fn = pick_looped((int)t, comp);
   const uint64_t blocks = (nwords + 63) / 64;
-  if (blocks == 0) return hipSuccess;
-  if (blocks > 0x7FFFFFFFull) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(fn, dim3((uint32_t)blocks), dim3(64), 0, stream, d_ptrs, n, nwords, tail_mask,
-                     prune ? 1u : 0u, d_out);
-  return hipGetLastError();
+  const uint64_t per_launch = kMaxLaunchItems / 64;
+  for (uint64_t b0 = 0; b0 < blocks; b0 += per_launch) {
+    const uint64_t nb = blocks - b0 < per_launch ? blocks - b0 : per_launch;
+    hipLaunchKernelGGL(fn, dim3((uint32_t)nb), dim3(64), 0, stream, d_ptrs, n, nwords, tail_mask,
+                       prune ? 1u : 0u, d_out, b0);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace tq

@@ -23,9 +23,10 @@ template <int KC, int KT>
 __global__ __launch_bounds__(64) void weighted_kernel(const uint64_t* const* __restrict__ ptrs,
                                                       const WeightClass* __restrict__ classes, uint32_t nclasses,
                                                       uint64_t nwords, uint64_t tail_mask, uint32_t theta,
-                                                      uint32_t total_weight, uint64_t* __restrict__ out) {
+                                                      uint32_t total_weight, uint64_t* __restrict__ out,
+                                                      uint64_t block0) {
   const int lane = threadIdx.x;
-  const uint64_t base = (uint64_t)blockIdx.x * 64;
+  const uint64_t base = (block0 + blockIdx.x) * 64;
   const uint64_t w = base + lane;
   const bool full = base + 64 <= nwords;
   Vec<1> T[KT];
@@ -63,7 +64,7 @@ __global__ __launch_bounds__(64) void weighted_kernel(const uint64_t* const* __r
 }
 
 typedef void (*WeightedFn)(const uint64_t* const*, const WeightClass*, uint32_t, uint64_t, uint64_t, uint32_t,
-                           uint32_t, uint64_t*);
+                           uint32_t, uint64_t*, uint64_t);
 
 template <int KC>
 WeightedFn pick_kt(int kt) {
@@ -106,11 +107,15 @@ hipError_t launch_weighted(const uint64_t* const* d_ptrs, const WeightClass* d_c
   WeightedFn fn = pick_weighted(kc, kt);
   if (!fn) return hipErrorInvalidValue;
   const uint64_t blocks = (nwords + 63) / 64;
-  if (blocks == 0) return hipSuccess;
-  if (blocks > 0x7FFFFFFFull) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(fn, dim3((uint32_t)blocks), dim3(64), 0, stream, d_ptrs, d_classes, nclasses, nwords,
-                     tail_mask, theta, total_weight, d_out);
-  return hipGetLastError();
+  const uint64_t per_launch = kMaxLaunchItems / 64;
+  for (uint64_t b0 = 0; b0 < blocks; b0 += per_launch) {
+    const uint64_t nb = blocks - b0 < per_launch ? blocks - b0 : per_launch;
+    hipLaunchKernelGGL(fn, dim3((uint32_t)nb), dim3(64), 0, stream, d_ptrs, d_classes, nclasses, nwords,
+                       tail_mask, theta, total_weight, d_out, b0);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace tq

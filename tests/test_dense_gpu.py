@@ -346,3 +346,41 @@ def test_looped_exhaustive():
                 assert np.array_equal(bits, (pc >= theta).astype(np.uint8)), (n, theta)
     finally:
         tq.tq_destroy(c)
+
+
+def test_max_size_beyond_32bit_word_index(ctx):
+    """Bitmaps of 2^32 + 101 words (32 GiB each, r = 64 (2^32 + 100) + 7 bits):
+    word indices past 32 bits and a ragged last word.  Sampled columns against
+    the oracle, and the whole output against torch's OR / AND of the two
+    inputs (theta = 1 / 2), chunk by chunk."""
+    nw = (1 << 32) + 101
+    r = 64 * ((1 << 32) + 100) + 7
+    free, _ = torch.cuda.mem_get_info()
+    need = 3 * nw * 8 + (4 << 30)
+    if free < need:
+        pytest.skip("needs %d GiB of free device memory" % (need >> 30))
+    bs = tqgen.bernoulli_fixed(9, 2, r, 0.5)
+    assert bs.nwords == nw
+    pool = torch.empty((2, nw), dtype=torch.int64, device="cuda")
+    tqgen.fill_gpu(bs, pool.view(-1))
+    rows = [pool[0], pool[1]]
+    out = torch.empty(nw, dtype=torch.int64, device="cuda")
+    rng = np.random.default_rng(3)
+    cols = np.unique(np.concatenate([[0, 1, (1 << 32) - 1, 1 << 32, (1 << 32) + 1, nw - 2, nw - 1],
+                                     rng.integers(0, nw, 24)])).astype(np.int64)
+    words = np.stack([np.concatenate([bs.words(j, int(c), int(c) + 1) for c in cols]) for j in range(2)])
+    tail = np.uint64(tail_mask(r))
+    chunk = 1 << 28
+    for theta in (1, 2):
+        tq.tq_threshold(ctx, rows, r, theta, out)
+        assert tq.tq_ctx_check(ctx) == 0
+        got = out[torch.from_numpy(cols).cuda()].cpu().numpy().view(np.uint64)
+        assert np.array_equal(got, oracle.threshold_cols(words, cols, r, theta)), theta
+        for c0 in range(0, nw, chunk):
+            c1 = min(nw, c0 + chunk)
+            a, b = pool[0, c0:c1], pool[1, c0:c1]
+            ref = (a | b) if theta == 1 else (a & b)
+            if c1 == nw:
+                ref = ref.clone()
+                ref[-1] = ref[-1] & torch.tensor(np.array([tail]).view(np.int64)[0], device="cuda")
+            assert torch.equal(out[c0:c1], ref), (theta, c0)
