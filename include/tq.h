@@ -331,6 +331,7 @@ typedef struct tq_batch tq_batch;
 /* Largest batch: queries and total pointer entries (sum of n). */
 #define TQ_BATCH_MAX_QUERIES 8192u
 #define TQ_BATCH_MAX_POINTERS 2097152u
+#define TQ_BATCH_MAX_TABLE_BYTES 1048576u
 
 /*
  * Submit `count` queries as one batch on `stream`.  Each query has the
@@ -340,8 +341,10 @@ typedef struct tq_batch tq_batch;
  * Admission: a context holds a fixed number of batch slots; when none is free
  * the call returns TQ_EBUSY and queues nothing (retry after releasing a
  * batch).  count in [1, TQ_BATCH_MAX_QUERIES]; sum of n at most
- * TQ_BATCH_MAX_POINTERS; a symmetric function that needs a lookup table
- * (more than 8 runs of ones and of zeros in f) returns TQ_ENOTSUP.  All
+ * TQ_BATCH_MAX_POINTERS.  A symmetric function with more than 8 runs of ones
+ * and of zeros in f is evaluated through a lookup table of 2^K bits (K the
+ * counter width, bit_length(n)); the tables of one batch may take at most
+ * TQ_BATCH_MAX_TABLE_BYTES (each rounded up to 8 bytes), else TQ_EINVAL.  All
  * pointer arrays and truth tables are copied; *out receives the batch.
  */
 tq_status tq_batch_submit(tq_ctx* ctx, const tq_query* queries, uint32_t count, uint32_t flags,

@@ -388,6 +388,7 @@ TQ_QUERY_SYMMETRIC = 1
 TQ_BATCH_NO_GRAPH = 1
 TQ_BATCH_MAX_QUERIES = 8192
 TQ_BATCH_MAX_POINTERS = 2097152
+TQ_BATCH_MAX_TABLE_BYTES = 1048576
 
 
 class TqQuery(ctypes.Structure):

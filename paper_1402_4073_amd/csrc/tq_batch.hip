@@ -66,6 +66,8 @@ struct BatchRecord {    // in pinned host memory, one per query
 
 constexpr uint32_t kSlotQueries = 8192;
 constexpr uint64_t kSlotPtrs = 1u << 21;
+// room for the truth tables of a batch's arbitrary symmetric functions
+constexpr uint64_t kSlotTableBytes = TQ_BATCH_MAX_TABLE_BYTES;
 constexpr int kSlots = 4;
 constexpr int kBatchWavesPerCU = 16;
 constexpr uint64_t kMinItemWork = 16;
@@ -107,7 +109,7 @@ __device__ __forceinline__ void store_word(CBatchQuery& Q, uint64_t w, uint64_t 
 
 // N >= 16: one column group (64 words) per wave, 16 inputs folded per step
 template <int K>
-__device__ __forceinline__ void run_group(CBatchQuery& Q, CPtrArr ptrs, uint64_t base) {
+__device__ __forceinline__ void run_group(CBatchQuery& Q, CPtrArr ptrs, uint64_t base, const uint32_t* table) {
   const int lane = threadIdx.x & 63;
   const uint64_t w = base + lane;
   Vec<1> r;
@@ -131,7 +133,7 @@ __device__ __forceinline__ void run_group(CBatchQuery& Q, CPtrArr ptrs, uint64_t
       else
         accumulate<K, 1, true>(P, ptrs, 0, Q.n, w, Q.nwords);
     }
-    r = epilogue<K, 1>(P, Q.epi, Q.n, nullptr);
+    r = epilogue<K, 1>(P, Q.epi, Q.n, table);
   }
   store_word<K>(Q, w, r.w[0]);
 }
@@ -141,7 +143,7 @@ __device__ __forceinline__ void run_group(CBatchQuery& Q, CPtrArr ptrs, uint64_t
 // loads in flight as with larger N
 constexpr int kSmallGroups = 4;
 
-__device__ __forceinline__ void run_small(CBatchQuery& Q, CPtrArr ptrs, uint64_t base) {
+__device__ __forceinline__ void run_small(CBatchQuery& Q, CPtrArr ptrs, uint64_t base, const uint32_t* table) {
   const int lane = threadIdx.x & 63;
   Vec<kSmallGroups> r;
   if (Q.constant) {
@@ -167,7 +169,7 @@ __device__ __forceinline__ void run_small(CBatchQuery& Q, CPtrArr ptrs, uint64_t
       }
       add_block_l<2, 4, kSmallGroups>(P, x);
     }
-    r = epilogue<4, kSmallGroups>(P, Q.epi, Q.n, nullptr);
+    r = epilogue<4, kSmallGroups>(P, Q.epi, Q.n, table);
   }
 #pragma unroll
   for (int g = 0; g < kSmallGroups; ++g) store_word<4>(Q, base + (uint64_t)g * 64 + lane, r.w[g]);
@@ -180,12 +182,17 @@ __device__ __forceinline__ void run_small(CBatchQuery& Q, CPtrArr ptrs, uint64_t
 // one write-back instead of one per wave.  The barrier orders every wave's
 // output stores before that release.
 constexpr int kItemWaves = 8;
+// Truth tables (arbitrary symmetric functions) of up to this many 32-bit
+// words, i.e. counters of up to 11 bits (n < 2048), are staged in LDS by the
+// wave that uses them; larger ones are read from the packed batch.
+constexpr uint32_t kWaveTableWords = 64;
 
 __global__ __launch_bounds__(64 * kItemWaves) void batch_kernel(char* buf, uint32_t* qshard, uint32_t* qtop,
                                                                BatchRecord* rec) {
   __shared__ uint32_t s_q[kItemWaves];
   __shared__ uint32_t s_local[kItemWaves];
   __shared__ uint32_t s_next;
+  __shared__ uint32_t s_table[kItemWaves][kWaveTableWords];
   BatchHeader* hdr = reinterpret_cast<BatchHeader*>(buf);
   const BatchHeader TQ_CONST* chdr = as_const<BatchHeader>(buf);
   const BatchQuery TQ_CONST* qs = as_const<BatchQuery>(buf + chdr->off_queries);
@@ -195,6 +202,7 @@ __global__ __launch_bounds__(64 * kItemWaves) void batch_kernel(char* buf, uint3
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   uint32_t q = 0;
+  uint32_t staged = 0xFFFFFFFFu;   // query whose truth table this wave holds in s_table
   // the first round of every workgroup is its own index; later ones come from the counter
   uint32_t round = blockIdx.x;
   while (round < nrounds) {
@@ -214,22 +222,37 @@ __global__ __launch_bounds__(64 * kItemWaves) void batch_kernel(char* buf, uint3
       const uint64_t local = item - Q.item_begin;
       if (lane == 0 && local == 0) rec[q].t_start = wall_clock64();
       CPtrArr ptrs = as_const<const uint64_t*>(reinterpret_cast<const void*>(Q.ptrs));
+      const uint32_t* table = nullptr;
+      if (!Q.constant && Q.epi.kind == EPI_TABLE) {
+        table = Q.epi.table;
+        if (Q.epi.table_words <= kWaveTableWords) {
+          if (staged != q) {
+            for (uint32_t t = lane; t < Q.epi.table_words; t += 64) s_table[wave][t] = table[t];
+            // the other lanes of this wave read what this wave wrote
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            staged = q;
+          }
+          table = s_table[wave];
+        }
+      }
       const uint32_t step = Q.K == 4 ? kSmallGroups : 1;
       for (uint32_t g = 0; g < Q.groups; g += step) {
         const uint64_t base = (local * Q.groups + g) * 64;
         if (base >= Q.nwords) break;
         switch (Q.K) {
-          case 4: run_small(Q, ptrs, base); break;
-          case 5: run_group<5>(Q, ptrs, base); break;
-          case 6: run_group<6>(Q, ptrs, base); break;
-          case 7: run_group<7>(Q, ptrs, base); break;
-          case 8: run_group<8>(Q, ptrs, base); break;
-          case 9: run_group<9>(Q, ptrs, base); break;
-          case 10: run_group<10>(Q, ptrs, base); break;
-          case 11: run_group<11>(Q, ptrs, base); break;
-          case 12: run_group<12>(Q, ptrs, base); break;
-          case 13: run_group<13>(Q, ptrs, base); break;
-          default: run_group<16>(Q, ptrs, base); break;
+          case 4: run_small(Q, ptrs, base, table); break;
+          case 5: run_group<5>(Q, ptrs, base, table); break;
+          case 6: run_group<6>(Q, ptrs, base, table); break;
+          case 7: run_group<7>(Q, ptrs, base, table); break;
+          case 8: run_group<8>(Q, ptrs, base, table); break;
+          case 9: run_group<9>(Q, ptrs, base, table); break;
+          case 10: run_group<10>(Q, ptrs, base, table); break;
+          case 11: run_group<11>(Q, ptrs, base, table); break;
+          case 12: run_group<12>(Q, ptrs, base, table); break;
+          case 13: run_group<13>(Q, ptrs, base, table); break;
+          default: run_group<16>(Q, ptrs, base, table); break;
         }
       }
       my_q = q;
@@ -325,7 +348,8 @@ BatchState* batch_state(tq_ctx* ctx) {
 
 tq_status slot_init(tq_ctx* ctx, BatchState* bs, BatchSlot& s) {
   if (s.d_buf) return TQ_OK;
-  const size_t bytes = sizeof(BatchHeader) + kSlotQueries * (sizeof(BatchQuery) + 4) + kSlotPtrs * 8 + 4096;
+  const size_t bytes =
+      sizeof(BatchHeader) + kSlotQueries * (sizeof(BatchQuery) + 4) + kSlotPtrs * 8 + kSlotTableBytes + 4096;
   hipError_t e;
   if ((e = hipMalloc((void**)&s.d_buf, bytes)) != hipSuccess) return record_hip(ctx, e);
   if ((e = hipHostMalloc((void**)&s.h_buf, bytes, hipHostMallocDefault)) != hipSuccess) return record_hip(ctx, e);
@@ -416,6 +440,21 @@ tq_status tq_batch_submit(tq_ctx* ctx, const tq_query* queries, uint32_t count, 
     nptrs += q.n;
   }
   if (nptrs > kSlotPtrs) return TQ_EINVAL;
+  // plans (arbitrary truth tables are packed with the batch)
+  std::vector<SymPlan> plans;
+  try {
+    plans.reserve(count);
+    for (uint32_t i = 0; i < count; ++i) {
+      const tq_query& q = queries[i];
+      plans.push_back(q.kind == TQ_QUERY_THRESHOLD ? plan_threshold(q.n, q.theta) : plan_symmetric(q.n, q.h_truth));
+    }
+  } catch (const std::bad_alloc&) {
+    return TQ_ENOMEM;
+  }
+  uint64_t table_bytes = 0;
+  for (const SymPlan& p : plans)
+    if (!p.constant && p.epi.kind == EPI_TABLE) table_bytes += align_up(p.table.size() * 4, 8);
+  if (table_bytes > kSlotTableBytes) return TQ_EINVAL;
   int si = -1;
   for (int k = 0; k < kSlots; ++k)
     if (!bs->slots[k].in_use) { si = k; break; }
@@ -428,13 +467,15 @@ tq_status tq_batch_submit(tq_ctx* ctx, const tq_query* queries, uint32_t count, 
   const size_t off_q = align_up(sizeof(BatchHeader), 256);
   const size_t off_ib = align_up(off_q + (size_t)count * sizeof(BatchQuery), 256);
   const size_t off_p = align_up(off_ib + (size_t)count * 4, 256);
-  const size_t used = off_p + nptrs * 8;
+  const size_t off_t = align_up(off_p + nptrs * 8, 256);
+  const size_t used = off_t + table_bytes;
   if (used > s.cap_bytes) return TQ_EINVAL;
   BatchHeader* h = reinterpret_cast<BatchHeader*>(s.h_buf);
   BatchQuery* qd = reinterpret_cast<BatchQuery*>(s.h_buf + off_q);
   uint32_t* ib = reinterpret_cast<uint32_t*>(s.h_buf + off_ib);
   uint64_t* pa = reinterpret_cast<uint64_t*>(s.h_buf + off_p);
   uint64_t pcur = 0;
+  size_t tcur = off_t;
   uint64_t items = 0;
   // Item size: enough items to give every wave of the grid several, but no
   // item smaller than kMinItemWork group-inputs (64 words x 1 input each).
@@ -454,11 +495,7 @@ tq_status tq_batch_submit(tq_ctx* ctx, const tq_query* queries, uint32_t count, 
   for (uint32_t i = 0; i < count; ++i) {
     const tq_query& q = queries[i];
     const uint64_t nw = words_for_bits(q.r_bits);
-    SymPlan plan = q.kind == TQ_QUERY_THRESHOLD ? plan_threshold(q.n, q.theta) : plan_symmetric(q.n, q.h_truth);
-    if (!plan.constant && plan.epi.kind == EPI_TABLE) {
-      delete b;
-      return TQ_ENOTSUP;
-    }
+    const SymPlan& plan = plans[i];
     BatchQuery& d = qd[i];
     memset(&d, 0, sizeof(d));
     d.ptrs = (uint64_t)(uintptr_t)(reinterpret_cast<uint64_t*>(s.d_buf + off_p) + pcur);
@@ -478,6 +515,11 @@ tq_status tq_batch_submit(tq_ctx* ctx, const tq_query* queries, uint32_t count, 
     d.constant = plan.constant ? (plan.const_word ? 1u : 2u) : 0u;
     d.epi = plan.epi;
     d.epi.prune = ctx->prune ? 1u : 0u;
+    if (!plan.constant && plan.epi.kind == EPI_TABLE) {
+      memcpy(s.h_buf + tcur, plan.table.data(), plan.table.size() * 4);
+      d.epi.table = reinterpret_cast<const uint32_t*>(s.d_buf + tcur);
+      tcur += align_up(plan.table.size() * 4, 8);
+    }
     ib[i] = (uint32_t)items;
     items += d.items;
     memcpy(pa + pcur, q.ptrs, (size_t)q.n * 8);

@@ -31,6 +31,16 @@ def pool():
     return base, dev_pool(list(base)), nw
 
 
+def table_truth(n, salt=0):
+    """A truth table with many runs of ones and of zeros and not a parity
+    function, so that only the lookup-table epilogue can evaluate it."""
+    c = np.arange(n + 1, dtype=np.uint64)
+    f = (((c + np.uint64(salt)) * np.uint64(2654435761)) >> np.uint64(9)) & np.uint64(1)
+    f = f.astype(np.uint8)
+    f[:20] = [1, 0, 1, 0, 1, 1, 0, 1, 0, 1, 0, 0, 1, 0, 1, 0, 1, 0, 1, 0][:min(20, n + 1)]
+    return f
+
+
 def make_specs(rng, base, dpool, nw, count, with_symmetric=True):
     specs, want = [], []
     for i in range(count):
@@ -40,8 +50,12 @@ def make_specs(rng, base, dpool, nw, count, with_symmetric=True):
         out = empty_words((r + 63) // 64)
         host = [base[m] for m in members]
         sp = {"inputs": [dpool[int(m)] for m in members], "r_bits": r, "out": out, "tag": 1000 + i}
-        kind = rng.integers(0, 4) if with_symmetric else 0
-        if kind == 1:
+        kind = rng.integers(0, 5) if with_symmetric else 0
+        if kind == 4 and n >= 19:
+            f = table_truth(n, salt=i)
+            sp["truth"] = f
+            want.append(oracle.symmetric(host, r, f))
+        elif kind == 1:
             f = oracle.truth_parity(n)
             sp["truth"] = f
             want.append(oracle.symmetric(host, r, f))
@@ -114,15 +128,59 @@ def test_batch_admission_and_errors(ctx, pool):
         tq.tq_batch_release(h)
     for sp, w in zip(specs, want):
         assert np.array_equal(to_host(sp["out"])[:(sp["r_bits"] + 63) // 64], w)
-    # a truth table that needs a lookup table is not served by the batch kernel
-    n = 40
-    f = np.zeros(n + 1, dtype=np.uint8)
-    f[::2] = 1
-    f[1] = 1
-    sp = {"inputs": [dpool[j] for j in range(n)], "r_bits": 640, "out": empty_words(10), "truth": f}
-    st, h = tq.raw_batch_submit(ctx, tq.BatchQueries([sp]))
-    assert st == tq.TQ_ENOTSUP
+    # the lookup tables of one batch are bounded (nothing is launched here):
+    # 129 functions of 8192 inputs need 129 tables of 2^16 bits
+    n = 8192
+    f = table_truth(n)
+    out = empty_words(1)
+    specs = [{"inputs": [dpool[j % 300] for j in range(n)], "r_bits": 64, "out": out, "truth": f}
+             for _ in range(tq.TQ_BATCH_MAX_TABLE_BYTES // 8192 + 1)]
+    st, h = tq.raw_batch_submit(ctx, tq.BatchQueries(specs))
+    assert st == tq.TQ_EINVAL and not h
     sp = {"inputs": [], "r_bits": 640, "out": empty_words(10), "theta": 1}
     st, h = tq.raw_batch_submit(ctx, tq.BatchQueries([sp]))
     assert st == tq.TQ_EINVAL
+    assert tq.tq_ctx_check(ctx) == 0
+
+
+@pytest.mark.parametrize("count", [20, 70])     # direct launch and graph replay
+def test_batch_truth_tables(ctx, pool, count):
+    """Arbitrary symmetric functions in a batch (lookup-table epilogue), with
+    tables small enough to be staged per wave (n < 2048) and larger ones read
+    from the packed batch (n = 2500 and 9000, inputs repeated), mixed with
+    thresholds; every output equals the oracle's, over repeated submissions."""
+    base, dpool, nw = pool
+    rng = np.random.default_rng(11 + count)
+    for rep in range(2):
+        specs, want = [], []
+        for i in range(count):
+            big = i % 9 == 4
+            n = int(rng.choice([2500, 9000])) if big else int(rng.choice([19, 40, 130, 299]))
+            r = int(rng.integers(1, (nw * 64 if not big else 64 * 300) + 1))
+            members = rng.integers(0, base.shape[0], size=n) if big else rng.choice(base.shape[0], n, replace=False)
+            host = [base[m] for m in members]
+            sp = {"inputs": [dpool[int(m)] for m in members], "r_bits": r, "out": empty_words((r + 63) // 64),
+                  "tag": i}
+            if i % 3 == 2:
+                theta = int(rng.integers(1, n + 1))
+                sp["theta"] = theta
+                want.append(oracle.threshold(host, r, theta))
+            else:
+                f = table_truth(n, salt=97 * rep + i)
+                sp["truth"] = f
+                want.append(oracle.symmetric(host, r, f))
+            specs.append(sp)
+        b = tq.tq_batch_submit(ctx, tq.BatchQueries(specs))
+        tq.tq_batch_wait(b)
+        recs = tq.tq_batch_records(b, len(specs))
+        for i, (sp, w) in enumerate(zip(specs, want)):
+            assert np.array_equal(to_host(sp["out"])[:(sp["r_bits"] + 63) // 64], w), (rep, i, len(sp["inputs"]))
+            assert recs[i]["status"] == 0 and recs[i]["done"] == 1
+        tq.tq_batch_release(b)
+        # the same functions through the single-query call
+        for sp in specs[:6]:
+            if "truth" in sp:
+                single = empty_words((sp["r_bits"] + 63) // 64)
+                tq.tq_symmetric(ctx, sp["inputs"], sp["r_bits"], sp["truth"], single)
+                assert torch.equal(single, sp["out"])
     assert tq.tq_ctx_check(ctx) == 0
