@@ -43,31 +43,42 @@ def lib():
     if _lib is None:
         if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build(force=True)
-        L = ctypes.CDLL(_LIB)
-        P = ctypes.c_void_p
-        U32, U64 = ctypes.c_uint32, ctypes.c_uint64
-        L.oracle_threshold_cols.argtypes = [P, U32, U64, P, U64, U32, P]
-        L.oracle_symmetric_cols.argtypes = [P, U32, U64, P, U64, P, P]
-        L.oracle_threshold.argtypes = [P, U32, U64, U32, P]
-        L.oracle_symmetric.argtypes = [P, U32, U64, P, P]
-        L.oracle_rle_decode.argtypes = [P, U64, U64, P]
-        L.oracle_rle_encode.argtypes = [P, U64, P, U64]
-        L.oracle_rle_encode.restype = U64
-        L.oracle_run_count.argtypes = [P, U64]
-        L.oracle_run_count.restype = U64
-        L.oracle_set_threads.argtypes = [ctypes.c_int]
-        L.oracle_set_threads.restype = None
-        L.oracle_max_threads.argtypes = []
-        L.oracle_max_threads.restype = ctypes.c_int
-        L.oracle_count.argtypes = [P, U64]
-        L.oracle_count.restype = U64
-        L.oracle_weighted_threshold.argtypes = [P, U32, P, U64, U64, P]
-        L.oracle_weighted_threshold.restype = ctypes.c_int
-        for f in ("oracle_threshold_cols", "oracle_symmetric_cols", "oracle_threshold",
-                  "oracle_symmetric", "oracle_rle_decode"):
-            getattr(L, f).restype = ctypes.c_int
-        _lib = L
+        _lib = _load(_LIB)
     return _lib
+
+
+def use_library(path: str) -> None:
+    """Point this module at another build of the C oracle (the planted-mistake
+    tests load deliberately broken copies through this)."""
+    global _lib
+    _lib = _load(path)
+
+
+def _load(path: str):
+    L = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    U32, U64 = ctypes.c_uint32, ctypes.c_uint64
+    L.oracle_threshold_cols.argtypes = [P, U32, U64, P, U64, U32, P]
+    L.oracle_symmetric_cols.argtypes = [P, U32, U64, P, U64, P, P]
+    L.oracle_threshold.argtypes = [P, U32, U64, U32, P]
+    L.oracle_symmetric.argtypes = [P, U32, U64, P, P]
+    L.oracle_rle_decode.argtypes = [P, U64, U64, P]
+    L.oracle_rle_encode.argtypes = [P, U64, P, U64]
+    L.oracle_rle_encode.restype = U64
+    L.oracle_run_count.argtypes = [P, U64]
+    L.oracle_run_count.restype = U64
+    L.oracle_set_threads.argtypes = [ctypes.c_int]
+    L.oracle_set_threads.restype = None
+    L.oracle_max_threads.argtypes = []
+    L.oracle_max_threads.restype = ctypes.c_int
+    L.oracle_count.argtypes = [P, U64]
+    L.oracle_count.restype = U64
+    L.oracle_weighted_threshold.argtypes = [P, U32, P, U64, U64, P]
+    L.oracle_weighted_threshold.restype = ctypes.c_int
+    for f in ("oracle_threshold_cols", "oracle_symmetric_cols", "oracle_threshold",
+              "oracle_symmetric", "oracle_rle_decode"):
+        getattr(L, f).restype = ctypes.c_int
+    return L
 
 
 def _u64(a) -> np.ndarray:

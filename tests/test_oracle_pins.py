@@ -314,6 +314,33 @@ def test_rle_malformed_rejected(orc):
             orc.rle_decode(np.array(s, dtype=np.uint64), r)
 
 
+def test_rle_encode_ignores_tail(orc):
+    """Bits at positions >= r are not part of the bitmap: a dense input with
+    garbage past r encodes to the stream of its masked words, and the tail
+    word is classified (zero fill, ones fill, literal) after masking."""
+    rng = np.random.default_rng(29)
+    for r in (1, 37, 64 * 3 + 1, 64 * 9 + 63):
+        nw = (r + 63) // 64
+        mask = tail_mask_words(r)
+        for tail in ("zeros", "ones", "mixed"):
+            bits = np.zeros(nw * 64, dtype=np.uint8)
+            bits[:r] = {"zeros": 0, "ones": 1}.get(tail, 0)
+            if tail == "mixed":
+                bits[:r] = rng.random(r) < 0.5
+            clean = pack(bits)
+            dirty = clean | (~mask & np.uint64(0xA5A5A5A5A5A5A5A5))
+            s = orc.rle_encode(dirty, r)
+            assert np.array_equal(s, orc.rle_encode(clean, r)), (r, tail)
+            assert np.array_equal(orc.rle_decode(s, r), clean), (r, tail)
+            if tail == "zeros":
+                assert len(s) == 1 and int(s[0]) == (nw << 1)
+            if tail == "ones":
+                # full words are a ones fill; a ragged last word holds ones
+                # below r only, so it is a literal (an empty fill has fill bit 0)
+                full = r // 64
+                assert int(s[0]) == ((1 if full else 0) | (full << 1) | ((nw - full) << 33))
+
+
 def test_run_count(orc):
     assert orc.run_count(np.zeros(2, dtype=np.uint64), 100) == 1
     alt = np.full(2, np.uint64(0xAAAAAAAAAAAAAAAA))
