@@ -8,6 +8,20 @@ def test_param_count():
     assert M.N_PARAMS == 4996
 
 
+def test_parameter_layout():
+    # the layout the library's header states: W1[64][8] b1[64] W2[64][64]
+    # b2[64] W3[4][64] b3[4], row-major (out x in), in that order
+    p = np.arange(M.N_PARAMS, dtype=np.float64)
+    d = M.unpack(p)
+    assert d["W1"][5, 3] == 5 * 8 + 3
+    assert d["b1"][0] == 512 and d["b1"][63] == 575
+    assert d["W2"][2, 7] == 576 + 2 * 64 + 7
+    assert d["b2"][0] == 4672
+    assert d["W3"][3, 63] == 4736 + 3 * 64 + 63
+    assert list(d["b3"]) == [4992, 4993, 4994, 4995]
+    assert np.array_equal(M.pack(d), p)
+
+
 def test_gradient_matches_finite_differences():
     rng = np.random.default_rng(1)
     p = M.init_params(3) + rng.standard_normal(M.N_PARAMS) * 0.05
