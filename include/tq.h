@@ -418,7 +418,9 @@ typedef struct tq_bitmap {
 
 /* Flags of tq_threshold_auto and bits of its *chosen report. */
 #define TQ_AUTO_FALLBACK 1u            /* time every variant when the prediction is uncertain */
-#define TQ_AUTO_CHOSE_BY_TIMING 0x100u /* set in *chosen when the fallback decided */
+#define TQ_AUTO_RETIME 2u              /* with TQ_AUTO_FALLBACK: time again even if a decision is remembered */
+#define TQ_AUTO_CHOSE_BY_TIMING 0x100u /* set in *chosen when the fallback timed the variants */
+#define TQ_AUTO_CHOSE_BY_CACHE 0x200u  /* set in *chosen when a remembered decision was used */
 
 /* Cardinality and run count of a dense bitmap (metadata registered with it,
  * section 2.1: RunCount).  Both results are device uint64. */
@@ -452,7 +454,13 @@ tq_status tq_selector_predict(tq_ctx* ctx, const float* features, float* predict
  * the inputs allow.  With TQ_AUTO_FALLBACK, an uncertain prediction (top two
  * within the margin, or features outside the training range) makes the call
  * time every available variant once and keep the fastest; that path
- * synchronises the stream.  *chosen (nullable) receives the variant. */
+ * synchronises the stream.  The decision is remembered for the query's cell
+ * (each feature in quarters of its training standard deviation, and the set
+ * of variants the inputs allow; up to 65536 cells, forgotten by
+ * tq_selector_set): a later uncertain query of the same cell runs that
+ * variant without timing (TQ_AUTO_CHOSE_BY_CACHE) unless TQ_AUTO_RETIME is
+ * given.  All variants give the same bits, so a remembered decision changes
+ * only the time.  *chosen (nullable) receives the variant. */
 tq_status tq_threshold_auto(tq_ctx* ctx, const tq_bitmap* inputs, uint32_t n, uint64_t r_bits, uint32_t theta,
                             uint64_t* d_out, uint32_t flags, uint32_t* chosen, hipStream_t stream);
 

@@ -553,7 +553,9 @@ TQ_SEL_PARAMS = 4996
 TQ_VARIANT_CSA, TQ_VARIANT_COUNTER, TQ_VARIANT_RLE, TQ_VARIANT_HYBRID = 0, 1, 2, 3
 VARIANT_NAMES = ("csa", "counter", "rle", "hybrid")
 TQ_AUTO_FALLBACK = 1
+TQ_AUTO_RETIME = 2
 TQ_AUTO_CHOSE_BY_TIMING = 0x100
+TQ_AUTO_CHOSE_BY_CACHE = 0x200
 
 
 class TqBitmap(ctypes.Structure):

@@ -12,6 +12,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <new>
+#include <unordered_map>
 #include <vector>
 
 #include "tq_internal.h"
@@ -37,6 +39,8 @@ struct Selector {
   std::vector<float> params;   // TQ_SEL_PARAMS
   float mean[TQ_SEL_FEATURES], stdev[TQ_SEL_FEATURES], lo[TQ_SEL_FEATURES], hi[TQ_SEL_FEATURES];
   float margin = 0.f;
+  // decisions of the timing fallback by feature cell (see decision_key)
+  std::unordered_map<uint64_t, uint8_t> decided;
 };
 
 namespace {
@@ -81,6 +85,24 @@ void host_forward(const Selector& s, const float* f, float* y) {
     for (int i = 0; i < kHid; ++i) z += W3[k * kHid + i] * h2[i];
     y[k] = z;
   }
+}
+
+// Cell of a query for the fallback's remembered decisions: each feature in
+// quarters of its training standard deviation (raw quarters without weights),
+// and which variants the inputs allow.  Keys are FNV-1a hashes; two cells
+// sharing a key only share a choice of variant, and every variant gives the
+// same bits.
+constexpr size_t kMaxDecisions = 1u << 16;
+
+uint64_t decision_key(const Selector& s, const float* f, uint32_t avail) {
+  uint64_t h = 1469598103934665603ull ^ avail;
+  for (int i = 0; i < kIn; ++i) {
+    float z = s.ready ? (f[i] - s.mean[i]) / s.stdev[i] : f[i];
+    z = std::min(std::max(z * 4.f, -1e6f), 1e6f);
+    const uint32_t q = (uint32_t)(int32_t)lrintf(z);
+    for (int b = 0; b < 4; ++b) h = (h ^ ((q >> (8 * b)) & 0xFFu)) * 1099511628211ull;
+  }
+  return h;
 }
 
 }  // namespace
@@ -199,6 +221,7 @@ tq_status tq_selector_set(tq_ctx* ctx, const float* params, const float* feat_me
   }
   s->margin = margin;
   s->ready = true;
+  s->decided.clear();   // cells are defined by the normalisation just set
   return TQ_OK;
 }
 
@@ -217,7 +240,8 @@ tq_status tq_threshold_auto(tq_ctx* ctx, const tq_bitmap* inputs, uint32_t n, ui
   float f[kIn], y[kOut];
   int best = -1, second = -1;
   bool uncertain = true;
-  if (s && s->ready && r_bits > 0 && tq_query_features(inputs, n, r_bits, theta, f) == TQ_OK) {
+  const bool have_f = r_bits > 0 && tq_query_features(inputs, n, r_bits, theta, f) == TQ_OK;
+  if (s && s->ready && have_f) {
     host_forward(*s, f, y);
     for (int v = 0; v < kOut; ++v) {
       if (!variant_available(inputs, n, v)) continue;
@@ -234,6 +258,22 @@ tq_status tq_threshold_auto(tq_ctx* ctx, const tq_bitmap* inputs, uint32_t n, ui
     uncertain = true;
   }
   if ((flags & TQ_AUTO_FALLBACK) && uncertain) {
+    uint32_t avail = 0;
+    for (int v = 0; v < kOut; ++v)
+      if (variant_available(inputs, n, v)) avail |= 1u << v;
+    if (!s && have_f) {
+      s = new (std::nothrow) Selector();   // holds the remembered decisions only
+      ctx->selector = s;
+    }
+    const bool cache = s && have_f;
+    const uint64_t key = cache ? decision_key(*s, f, avail) : 0;
+    if (cache && !(flags & TQ_AUTO_RETIME)) {
+      auto it = s->decided.find(key);
+      if (it != s->decided.end() && ((avail >> it->second) & 1u)) {
+        if (chosen) *chosen = (uint32_t)it->second | TQ_AUTO_CHOSE_BY_CACHE;
+        return tq_threshold_variant(ctx, inputs, n, r_bits, theta, it->second, d_out, stream);
+      }
+    }
     // exhaustive fallback: time every available variant once on this query
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return TQ_EDEVICE;
@@ -252,6 +292,10 @@ tq_status tq_threshold_auto(tq_ctx* ctx, const tq_bitmap* inputs, uint32_t n, ui
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
+    if (cache && fastest >= 0) {
+      if (s->decided.size() >= kMaxDecisions) s->decided.clear();
+      s->decided[key] = (uint8_t)fastest;
+    }
     if (chosen) *chosen = (uint32_t)fastest | TQ_AUTO_CHOSE_BY_TIMING;
     // every variant wrote the same bits into d_out; nothing more to run
     return TQ_OK;

@@ -149,6 +149,24 @@ def test_auto_dispatch(ctx):
     chosen = tq.tq_threshold_auto(ctx, arr, r, 3, out2, tq.TQ_AUTO_FALLBACK)
     assert chosen & tq.TQ_AUTO_CHOSE_BY_TIMING and (chosen & 0xFF) < 4
     assert np.array_equal(to_host(out2), oracle.threshold(dense, r, 3))
+    # the decision is remembered for the query's cell: no timing the second time
+    timed = chosen & 0xFF
+    for flags, bit in ((tq.TQ_AUTO_FALLBACK, tq.TQ_AUTO_CHOSE_BY_CACHE),
+                       (tq.TQ_AUTO_FALLBACK | tq.TQ_AUTO_RETIME, tq.TQ_AUTO_CHOSE_BY_TIMING)):
+        out3 = empty_words((r + 63) // 64)
+        chosen = tq.tq_threshold_auto(ctx, arr, r, 3, out3, flags)
+        assert chosen & bit and (chosen & 0xFF) < 4, (flags, chosen)
+        if bit == tq.TQ_AUTO_CHOSE_BY_CACHE:
+            assert chosen & 0xFF == timed
+        assert np.array_equal(to_host(out3), oracle.threshold(dense, r, 3))
+    # a neighbouring query (another threshold) falls in another cell
+    chosen = tq.tq_threshold_auto(ctx, arr, r, 12, out3, tq.TQ_AUTO_FALLBACK)
+    assert chosen & tq.TQ_AUTO_CHOSE_BY_TIMING
+    assert np.array_equal(to_host(out3), oracle.threshold(dense, r, 12))
+    # new weights forget the remembered decisions
+    tq.tq_selector_set(ctx, p, np.zeros(8), np.ones(8), f - 100, f + 100, 1e9)
+    chosen = tq.tq_threshold_auto(ctx, arr, r, 3, out3, tq.TQ_AUTO_FALLBACK)
+    assert chosen & tq.TQ_AUTO_CHOSE_BY_TIMING
 
 
 def test_default_weights_dispatch(ctx):
