@@ -109,6 +109,22 @@ __device__ __forceinline__ void ripple_lds(uint64_t* planes, int col, uint64_t x
   }
 }
 
+// The same with a sticky top plane: planes 0..K-2 count exactly up to
+// 2^(K-1) - 1, and the carry out of them sets plane K-1 for good, which then
+// means "at least 2^(K-1)".  A threshold query needs nothing more when every
+// column's threshold theta - k stays below 2^(K-1): a set top plane answers
+// yes, a clear one leaves an exact count.
+template <int K>
+__device__ __forceinline__ void ripple_lds_sat(uint64_t* planes, int col, uint64_t x) {
+#pragma unroll
+  for (int k = 0; k < K - 1; ++k) {
+    const uint64_t old = atomicXor((unsigned long long*)&planes[k * kTile + col], (unsigned long long)x);
+    x &= old;
+    if (!x) return;
+  }
+  atomicOr((unsigned long long*)&planes[(K - 1) * kTile + col], (unsigned long long)x);
+}
+
 // kd word of a column after the scan: bits 0..15 k (ones fills), bits 16..30
 // d (dirty inputs), bit 31 set when the column is undecided
 __device__ __forceinline__ void unpack_kd(int32_t v, int& k, int& d) {
@@ -166,6 +182,12 @@ template <int K>
 struct SlicedAdd {
   uint64_t* planes;
   __device__ __forceinline__ void operator()(int c, uint64_t x) const { ripple_lds<K>(planes, c, x); }
+};
+
+template <int K>
+struct SaturatingAdd {
+  uint64_t* planes;
+  __device__ __forceinline__ void operator()(int c, uint64_t x) const { ripple_lds_sat<K>(planes, c, x); }
 };
 
 // SWAR: 16 words per column, word q holding the 16-bit counts of positions
@@ -323,9 +345,13 @@ __device__ __forceinline__ void walk_literals(const RleDesc& dsc, Reader& rd, Wa
 // ones fills, theta - k <= 0 gives ones and theta - k > d zeros).  Sym = true:
 // any symmetric f, decided where f is constant on [k, k + d] and otherwise
 // evaluated on k plus the counted dirty bits.  Swar = true: SWAR column
-// counters, every tile in one pass; otherwise K bit-sliced planes.
-template <int K, bool Sym, bool Swar>
-__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(6))) void rle_tile_kernel(
+// counters, every tile in one pass; otherwise K bit-sliced planes.  Sat =
+// true (thresholds only): the top plane is sticky (see ripple_lds_sat), so
+// K = bit_length(theta) + 1 planes suffice; with K <= 4 the kernel is built
+// for 8 waves per SIMD, which its small LDS footprint allows, at the cost of
+// a few spilled registers (measured: faster there, slower for larger K).
+template <int K, bool Sym, bool Swar, bool Sat = false>
+__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu((Sat && K <= 4) ? 8 : 6))) void rle_tile_kernel(
     const RleDesc* __restrict__ descs, uint32_t n_rle, const uint64_t* const* __restrict__ dense,
     uint32_t n_dense, uint32_t nwords, uint64_t tail_mask, uint32_t theta, RleSym sym, uint32_t tiles_per_group,
     uint64_t* __restrict__ out, int* __restrict__ status) {
@@ -333,7 +359,9 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(6)
   constexpr int kCounterWords = Swar ? 16 : K;
   uint64_t* planes = lds;                                         // kCounterWords x kTile
   int32_t* kd = reinterpret_cast<int32_t*>(lds + kCounterWords * kTile);   // kTile + 1 packed (k | d << 16)
-  using Add = typename std::conditional<Swar, SwarAdd, SlicedAdd<K>>::type;
+  static_assert(!Sat || (!Sym && !Swar), "saturating planes serve thresholds only");
+  using Add = typename std::conditional<Swar, SwarAdd,
+                                        typename std::conditional<Sat, SaturatingAdd<K>, SlicedAdd<K>>::type>::type;
   const Add add{planes};
   __shared__ int32_t wave_tot[kTileThreads / 64];
   __shared__ int32_t total;
@@ -484,11 +512,12 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(6)
         for (uint32_t i = 0; i < n_dense; ++i) {
           uint64_t x = dense[i][col];
 #pragma unroll
-          for (int q = 0; q < K; ++q) {
+          for (int q = 0; q < (Sat ? K - 1 : K); ++q) {
             const uint64_t t = P[q] & x;
             P[q] ^= x;
             x = t;
           }
+          if constexpr (Sat) P[K - 1] |= x;
         }
         if constexpr (Sym) {
           // the full count of the column: its ones fills plus the counted bits
@@ -720,6 +749,26 @@ TileFn pick_tile_k(int K) {
   return nullptr;
 }
 
+// thresholds with bit_length(theta) exact planes and a sticky one
+TileFn pick_sat_k(int K) {
+  switch (K) {
+    case 2: return rle_tile_kernel<2, false, false, true>;
+    case 3: return rle_tile_kernel<3, false, false, true>;
+    case 4: return rle_tile_kernel<4, false, false, true>;
+    case 5: return rle_tile_kernel<5, false, false, true>;
+    case 6: return rle_tile_kernel<6, false, false, true>;
+    case 7: return rle_tile_kernel<7, false, false, true>;
+    case 8: return rle_tile_kernel<8, false, false, true>;
+    case 9: return rle_tile_kernel<9, false, false, true>;
+    case 10: return rle_tile_kernel<10, false, false, true>;
+    case 11: return rle_tile_kernel<11, false, false, true>;
+    case 12: return rle_tile_kernel<12, false, false, true>;
+    case 13: return rle_tile_kernel<13, false, false, true>;
+  }
+  return nullptr;
+}
+
+
 }  // namespace
 
 size_t rle_tile_lds_bytes(int K, bool swar) {
@@ -730,18 +779,29 @@ hipError_t launch_rle_tile(const RleDesc* d_descs, uint32_t n_rle, const uint64_
                            uint32_t n_dense, uint64_t nwords, uint64_t tail_mask, uint32_t theta,
                            const RleSym* sym, bool swar, int num_cus, uint32_t tiles_per_group,
                            uint64_t* d_out, int* d_status, hipStream_t stream) {
-  const int K = dense_planes_for(n_rle + n_dense);
+  int K = dense_planes_for(n_rle + n_dense);
   TileFn fn = swar ? (sym ? rle_tile_kernel<16, true, true> : rle_tile_kernel<16, false, true>)
                    : (sym ? pick_tile_k<true>(K) : pick_tile_k<false>(K));
+  int slot = swar ? 34 + (sym ? 1 : 0) : K + (sym ? 17 : 0);
+  // A threshold compares each column's count with theta - k <= theta, so
+  // bit_length(theta) exact planes and a sticky one decide it: less LDS per
+  // workgroup, and more workgroups per CU, when that is fewer planes.
+  if (!sym && !swar && theta >= 1) {
+    const int ks = bit_length(theta) + 1;
+    if (ks < K && ks <= 13) {
+      K = ks;
+      fn = pick_sat_k(K);
+      slot = 36 + K;
+    }
+  }
   if (!fn) return hipErrorInvalidValue;
-  const int slot = swar ? 34 + (sym ? 1 : 0) : K + (sym ? 17 : 0);
   const uint64_t tiles = (nwords + kTile - 1) / kTile;
   if (tiles == 0) return hipSuccess;
   const size_t lds = rle_tile_lds_bytes(K, swar);
   // LDS limit and resident workgroups per CU, set and measured once per device
   constexpr int kMaxDevices = 64;
   static std::mutex mu;
-  static int resident[kMaxDevices][36] = {};
+  static int resident[kMaxDevices][50] = {};
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;

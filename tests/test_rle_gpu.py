@@ -402,6 +402,41 @@ def test_more_inputs_than_lanes(ctx, tiles_option, tiles):
         assert np.array_equal(to_host(out), oracle.threshold(dense, r, theta)), theta
 
 
+@pytest.mark.parametrize("n_rle,n_dense,tiles", [(300, 0, 0), (300, 0, 2), (40, 30, 0), (600, 0, 0)])
+def test_threshold_counts_beyond_narrow_counters(ctx, tiles_option, n_rle, n_dense, tiles):
+    """Small thresholds keep bit_length(theta) exact counter planes and a
+    sticky one, so columns where hundreds of inputs are dirty overflow the
+    exact planes many times over: every theta around the powers of two (and
+    its complement-side neighbours) must still equal the oracle, with dense
+    inputs added in the same column (hybrid) and with one-pass tiles."""
+    rng = np.random.default_rng(300 + n_rle + n_dense)
+    r = 64 * STRIDE * 3 + 29
+    nw = (r + 63) // 64
+    dense = []
+    for j in range(n_rle + n_dense):
+        # almost every word dirty, density varying by input so counts spread
+        p = 0.02 + 0.9 * (j % 17) / 17.0
+        bits = rng.random(nw * 64) < p
+        w = np.packbits(bits.astype(np.uint8), bitorder="little").view("<u8").astype(np.uint64)
+        if j % 5 == 0:
+            w[100:300] = 0                        # fills among the dirty words
+        if j % 7 == 0:
+            w[400:700] = np.uint64(0xFFFFFFFFFFFFFFFF)
+        dense.append(w)
+    assert tiles_option(tiles) == tq.TQ_OK
+    inputs, keep = rle_inputs(ctx, dense[:n_rle], r)
+    drows = [to_dev(d) for d in dense[n_rle:]]
+    n = n_rle + n_dense
+    for theta in (1, 2, 3, 4, 5, 7, 8, 9, 15, 16, 17, 31, 32, 63, 64, 65, 127, 128, n // 2, n - 1, n):
+        out = empty_words(nw)
+        if n_dense:
+            tq.tq_threshold_hybrid(ctx, inputs, drows, r, theta, out)
+        else:
+            tq.tq_threshold_rle_dense(ctx, inputs, r, theta, out)
+        assert tq.tq_ctx_check(ctx) == 0
+        assert np.array_equal(to_host(out), oracle.threshold(dense, r, theta)), theta
+
+
 # ------------------------------------------- symmetric functions over RLE
 def sym_tables(n, rng):
     t = [oracle.truth_parity(n), oracle.truth_interval(n, 2, min(n, 10)),
