@@ -129,6 +129,8 @@ struct RleSym {
   const uint32_t* run_end;  // per count c in [0, n]: last count of the run of equal f values from c
   const uint64_t* f;        // f(c) is bit c of this array, c in [0, n]
   EpiParams epi;            // f(count) on the planes of the full count
+  uint32_t tail_from;       // f is constant (tail_value) on [tail_from, n]
+  uint32_t tail_value;
 };
 
 size_t rle_tile_lds_bytes(int K, bool swar);

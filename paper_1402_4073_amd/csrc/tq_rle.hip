@@ -190,6 +190,21 @@ struct SaturatingAdd {
   __device__ __forceinline__ void operator()(int c, uint64_t x) const { ripple_lds_sat<K>(planes, c, x); }
 };
 
+// Parity needs only bit 0 of each count: one plane, one XOR per word, and no
+// old value to wait for.
+struct ParityAdd {
+  uint64_t* planes;
+  __device__ __forceinline__ void operator()(int c, uint64_t x) const {
+    atomicXor((unsigned long long*)&planes[c], (unsigned long long)x);
+  }
+};
+
+// Counter forms of the plane kernels (Swar = false)
+constexpr int kFullPlanes = 0;    // K planes holding the exact count
+constexpr int kSaturating = 1;    // top plane sticky (ripple_lds_sat): thresholds, and
+                                  // symmetric f constant from some count on
+constexpr int kParityPlane = 2;   // parity: one plane, the count modulo 2
+
 // SWAR: 16 words per column, word q holding the 16-bit counts of positions
 // q, q + 16, q + 32 and q + 48; a word x is added with 16 atomic adds of
 // (x >> q) & E, none of which returns a value, so nothing waits on LDS.  The
@@ -345,13 +360,15 @@ __device__ __forceinline__ void walk_literals(const RleDesc& dsc, Reader& rd, Wa
 // ones fills, theta - k <= 0 gives ones and theta - k > d zeros).  Sym = true:
 // any symmetric f, decided where f is constant on [k, k + d] and otherwise
 // evaluated on k plus the counted dirty bits.  Swar = true: SWAR column
-// counters, every tile in one pass; otherwise K bit-sliced planes.  Sat =
-// true (thresholds only): the top plane is sticky (see ripple_lds_sat), so
-// K = bit_length(theta) + 1 planes suffice; with K <= 4 the kernel is built
-// for 8 waves per SIMD, which its small LDS footprint allows, at the cost of
-// a few spilled registers (measured: faster there, slower for larger K).
-template <int K, bool Sym, bool Swar, bool Sat = false>
-__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu((Sat && K <= 4) ? 8 : 6))) void rle_tile_kernel(
+// counters, every tile in one pass; otherwise K bit-sliced planes in the
+// form Form: kSaturating (thresholds only) makes the top plane sticky (see
+// ripple_lds_sat), so K = bit_length(theta) + 1 planes suffice; kParityPlane
+// (the parity function and its complement) keeps one plane, the count modulo
+// 2.  With K <= 4 planes the kernel is built for 8 waves per SIMD, which its
+// small LDS footprint allows, at the cost of a few spilled registers
+// (measured: faster there, slower for larger K).
+template <int K, bool Sym, bool Swar, int Form = kFullPlanes>
+__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu((Form != kFullPlanes && K <= 4) ? 8 : 6))) void rle_tile_kernel(
     const RleDesc* __restrict__ descs, uint32_t n_rle, const uint64_t* const* __restrict__ dense,
     uint32_t n_dense, uint32_t nwords, uint64_t tail_mask, uint32_t theta, RleSym sym, uint32_t tiles_per_group,
     uint64_t* __restrict__ out, int* __restrict__ status) {
@@ -359,9 +376,13 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu((S
   constexpr int kCounterWords = Swar ? 16 : K;
   uint64_t* planes = lds;                                         // kCounterWords x kTile
   int32_t* kd = reinterpret_cast<int32_t*>(lds + kCounterWords * kTile);   // kTile + 1 packed (k | d << 16)
-  static_assert(!Sat || (!Sym && !Swar), "saturating planes serve thresholds only");
-  using Add = typename std::conditional<Swar, SwarAdd,
-                                        typename std::conditional<Sat, SaturatingAdd<K>, SlicedAdd<K>>::type>::type;
+  constexpr bool Sat = Form == kSaturating, Par = Form == kParityPlane;
+  static_assert(!Sat || !Swar, "saturating planes are bit planes");
+  static_assert(!Par || (Sym && !Swar && K == 1), "the parity plane serves the parity function only");
+  using Add = typename std::conditional<
+      Swar, SwarAdd,
+      typename std::conditional<Sat, SaturatingAdd<K>,
+                                typename std::conditional<Par, ParityAdd, SlicedAdd<K>>::type>::type>::type;
   const Add add{planes};
   __shared__ int32_t wave_tot[kTileThreads / 64];
   __shared__ int32_t total;
@@ -519,7 +540,24 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu((S
           }
           if constexpr (Sat) P[K - 1] |= x;
         }
-        if constexpr (Sym) {
+        if constexpr (Par) {
+          // bit 0 of the count: the ones fills' parity and the counted bits'
+          res = P[0] ^ ((k & 1) ? ~(uint64_t)0 : 0);
+          if (sym.epi.invert) res = ~res;
+        } else if constexpr (Sym && Sat) {
+          // An undecided column has k < tail_from, so with the sticky plane
+          // clear the count k + (exact planes) is below 2^K and exact; a set
+          // sticky plane means at least 2^(K-1) > tail_from counted bits,
+          // where f is tail_value.
+          const uint64_t sticky = P[K - 1];
+          P[K - 1] = 0;
+          add_constant<K>(P, (uint32_t)k);
+          csa::Vec<1> V[K];
+#pragma unroll
+          for (int q = 0; q < K; ++q) V[q].w[0] = P[q];
+          res = csa::epilogue<K, 1>(V, sym.epi, n_rle + n_dense, sym.epi.table).w[0];
+          res = (res & ~sticky) | (sym.tail_value ? sticky : 0);
+        } else if constexpr (Sym) {
           // the full count of the column: its ones fills plus the counted bits
           add_constant<K>(P, (uint32_t)k);
           csa::Vec<1> V[K];
@@ -749,21 +787,23 @@ TileFn pick_tile_k(int K) {
   return nullptr;
 }
 
-// thresholds with bit_length(theta) exact planes and a sticky one
+// thresholds with bit_length(theta) exact planes and a sticky one, or
+// symmetric functions with bit_length(tail_from) exact planes and a sticky one
+template <bool Sym>
 TileFn pick_sat_k(int K) {
   switch (K) {
-    case 2: return rle_tile_kernel<2, false, false, true>;
-    case 3: return rle_tile_kernel<3, false, false, true>;
-    case 4: return rle_tile_kernel<4, false, false, true>;
-    case 5: return rle_tile_kernel<5, false, false, true>;
-    case 6: return rle_tile_kernel<6, false, false, true>;
-    case 7: return rle_tile_kernel<7, false, false, true>;
-    case 8: return rle_tile_kernel<8, false, false, true>;
-    case 9: return rle_tile_kernel<9, false, false, true>;
-    case 10: return rle_tile_kernel<10, false, false, true>;
-    case 11: return rle_tile_kernel<11, false, false, true>;
-    case 12: return rle_tile_kernel<12, false, false, true>;
-    case 13: return rle_tile_kernel<13, false, false, true>;
+    case 2: return rle_tile_kernel<2, Sym, false, kSaturating>;
+    case 3: return rle_tile_kernel<3, Sym, false, kSaturating>;
+    case 4: return rle_tile_kernel<4, Sym, false, kSaturating>;
+    case 5: return rle_tile_kernel<5, Sym, false, kSaturating>;
+    case 6: return rle_tile_kernel<6, Sym, false, kSaturating>;
+    case 7: return rle_tile_kernel<7, Sym, false, kSaturating>;
+    case 8: return rle_tile_kernel<8, Sym, false, kSaturating>;
+    case 9: return rle_tile_kernel<9, Sym, false, kSaturating>;
+    case 10: return rle_tile_kernel<10, Sym, false, kSaturating>;
+    case 11: return rle_tile_kernel<11, Sym, false, kSaturating>;
+    case 12: return rle_tile_kernel<12, Sym, false, kSaturating>;
+    case 13: return rle_tile_kernel<13, Sym, false, kSaturating>;
   }
   return nullptr;
 }
@@ -790,9 +830,25 @@ hipError_t launch_rle_tile(const RleDesc* d_descs, uint32_t n_rle, const uint64_
     const int ks = bit_length(theta) + 1;
     if (ks < K && ks <= 13) {
       K = ks;
-      fn = pick_sat_k(K);
+      fn = pick_sat_k<false>(K);
       slot = 36 + K;
     }
+  }
+  // A symmetric f that is constant from tail_from on needs the count exactly
+  // only below tail_from: bit_length(tail_from) exact planes and a sticky one.
+  if (sym && !swar && sym->epi.kind != EPI_PARITY && sym->tail_from >= 1) {
+    const int ks = bit_length(sym->tail_from) + 1;
+    if (ks < K && ks <= 13) {
+      K = ks;
+      fn = pick_sat_k<true>(K);
+      slot = 51 + K;
+    }
+  }
+  // the parity function (or its complement) needs the count modulo 2 only
+  if (sym && !swar && sym->epi.kind == EPI_PARITY) {
+    K = 1;
+    fn = rle_tile_kernel<1, true, false, kParityPlane>;
+    slot = 50;
   }
   if (!fn) return hipErrorInvalidValue;
   const uint64_t tiles = (nwords + kTile - 1) / kTile;
@@ -801,7 +857,7 @@ hipError_t launch_rle_tile(const RleDesc* d_descs, uint32_t n_rle, const uint64_
   // LDS limit and resident workgroups per CU, set and measured once per device
   constexpr int kMaxDevices = 64;
   static std::mutex mu;
-  static int resident[kMaxDevices][50] = {};
+  static int resident[kMaxDevices][65] = {};
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;

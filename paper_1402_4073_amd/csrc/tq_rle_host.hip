@@ -99,6 +99,10 @@ tq_status sym_tables(tq_ctx* ctx, uint32_t n, const uint64_t* truth, const SymPl
   t->sym.f = static_cast<const uint64_t*>(d_f);
   t->sym.run_end = static_cast<const uint32_t*>(d_re);
   t->sym.epi = plan.epi;
+  uint32_t tail = n;
+  while (tail > 0 && run_end[tail - 1] == n) --tail;
+  t->sym.tail_from = tail;
+  t->sym.tail_value = (uint32_t)((f[n / 64] >> (n % 64)) & 1);
   if (plan.epi.kind == EPI_TABLE) {
     std::vector<uint64_t> t64((plan.table.size() + 1) / 2, 0);
     memcpy(t64.data(), plan.table.data(), plan.table.size() * 4);

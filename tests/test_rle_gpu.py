@@ -435,11 +435,24 @@ def test_threshold_counts_beyond_narrow_counters(ctx, tiles_option, n_rle, n_den
             tq.tq_threshold_rle_dense(ctx, inputs, r, theta, out)
         assert tq.tq_ctx_check(ctx) == 0
         assert np.array_equal(to_host(out), oracle.threshold(dense, r, theta)), theta
+    # symmetric functions constant from a small count on (narrow counters with
+    # a sticky plane), and their complements
+    tables = [oracle.truth_interval(n, 2, 10), oracle.truth_interval(n, 3, 3), 1 - oracle.truth_threshold(n, 5),
+              1 - oracle.truth_interval(n, 5, 9), oracle.truth_interval(n, 1, 1) | oracle.truth_interval(n, 6, 14)]
+    for t in tables:
+        t = np.asarray(t, dtype=np.uint8)
+        out = empty_words(nw)
+        if n_dense:
+            tq.tq_symmetric_hybrid(ctx, inputs, drows, r, t, out)
+        else:
+            tq.tq_symmetric_rle_dense(ctx, inputs, r, t, out)
+        assert tq.tq_ctx_check(ctx) == 0
+        assert np.array_equal(to_host(out), oracle.symmetric(dense, r, t)), list(np.nonzero(t)[0][:12])
 
 
 # ------------------------------------------- symmetric functions over RLE
 def sym_tables(n, rng):
-    t = [oracle.truth_parity(n), oracle.truth_interval(n, 2, min(n, 10)),
+    t = [oracle.truth_parity(n), 1 - oracle.truth_parity(n), oracle.truth_interval(n, 2, min(n, 10)),
          oracle.truth_interval(n, min(n, 3), min(n, 3)),                     # delta: count == 3
          1 - oracle.truth_threshold(n, max(1, n // 2)),                       # count < n/2
          rng.integers(0, 2, n + 1).astype(np.uint8),
