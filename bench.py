@@ -204,6 +204,19 @@ def bench_rle(args):
             b.record(stream)
             torch.cuda.synchronize()
             sym_ms[name] = round(a.elapsed_time(b) / args.steps, 4)
+    # fused consumer: the count of each threshold result, nothing stored
+    count_ms = {}
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda:0")
+    with torch.cuda.stream(stream):
+        for t in thetas:
+            tq.tq_threshold_rle_fused(ctx, inputs, r, t, None, None, cnt, stream)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(args.steps):
+                tq.tq_threshold_rle_fused(ctx, inputs, r, t, None, None, cnt, stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+            count_ms[str(t)] = round(a.elapsed_time(b) / args.steps, 4)
     st = tq.tq_ctx_check(ctx, stream)
     if st != 0:
         raise RuntimeError("device error: %s" % tq.status_string(st))
@@ -229,6 +242,7 @@ def bench_rle(args):
         "per_query_ms": [round(sum(full_ms[i::q]) / args.steps, 4) for i in range(q)],
         "tile_kernel_ms": [round(sum(tile_ms[i::q]) / args.steps, 4) for i in range(q)],
         "symmetric_query_ms": sym_ms,
+        "count_only_query_ms": count_ms,
         "roofline": {"bound": "hbm", "achieved": round(alg / tile_s / 1e9, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(alg / tile_s / 1e9 / HBM_PEAK_GBS, 4),
                      "traffic": load_traffic("rle_tile_kernel/rle-thresholds"),

@@ -296,6 +296,21 @@ tq_status tq_symmetric_hybrid(tq_ctx* ctx, const tq_rle* rle_inputs, uint32_t n_
                               const uint64_t* const* dense_ptrs, uint32_t n_dense, uint64_t r_bits,
                               const uint64_t* h_truth, uint64_t* d_out, hipStream_t stream);
 
+/*
+ * Fused consumers over compressed inputs (the result is again a bitmap to be
+ * combined or counted: abstract and introduction), as tq_threshold_fused /
+ * tq_symmetric_fused: R = f(inputs) AND filter; d_out = R (dense, nullable),
+ * *d_count = |R| below r_bits (nullable).  The filter is dense, ceil(r/64)
+ * words (NULL: none), and may be d_out itself.  The count uses the context's
+ * workspace (one uint32 per wave of each TQ_RLE_INDEX_STRIDE-word tile, and
+ * the indexes the inputs lack).  Inputs and errors as tq_threshold_rle_dense.
+ */
+tq_status tq_threshold_rle_fused(tq_ctx* ctx, const tq_rle* inputs, uint32_t n, uint64_t r_bits, uint32_t theta,
+                                 const uint64_t* d_filter, uint64_t* d_out, uint64_t* d_count, hipStream_t stream);
+tq_status tq_symmetric_rle_fused(tq_ctx* ctx, const tq_rle* inputs, uint32_t n, uint64_t r_bits,
+                                 const uint64_t* h_truth, const uint64_t* d_filter, uint64_t* d_out,
+                                 uint64_t* d_count, hipStream_t stream);
+
 /* ------------------------------------------------------------------------
  * Batched queries: many threshold / symmetric queries of uneven N, r and
  * theta served by one persistent kernel launch, replayed from a graph.

@@ -66,6 +66,8 @@ def _load():
         "tq_rle_decode": (_INT, [_P, _P, _U64, _P, _P]),
         "tq_threshold_rle": (_INT, [_P, _P, _U32, _U64, _U32, _P, _U64, _P, _P]),
         "tq_threshold_rle_dense": (_INT, [_P, _P, _U32, _U64, _U32, _P, _P]),
+        "tq_threshold_rle_fused": (_INT, [_P, _P, _U32, _U64, _U32, _P, _P, _P, _P]),
+        "tq_symmetric_rle_fused": (_INT, [_P, _P, _U32, _U64, _P, _P, _P, _P, _P]),
         "tq_threshold_hybrid": (_INT, [_P, _P, _U32, _P, _U32, _U64, _U32, _P, _P]),
         "tq_symmetric_rle": (_INT, [_P, _P, _U32, _U64, _P, _P, _U64, _P, _P]),
         "tq_symmetric_rle_dense": (_INT, [_P, _P, _U32, _U64, _P, _P, _P]),
@@ -318,6 +320,22 @@ def tq_threshold_rle_dense(ctx: int, inputs, r_bits: int, theta: int, out, strea
            "tq_threshold_rle_dense")
 
 
+def tq_threshold_rle_fused(ctx: int, inputs, r_bits: int, theta: int, filt=None, out=None, count=None,
+                           stream=None) -> None:
+    """out = T_theta(compressed inputs) AND filt; count[0] = popcount(out) (each optional)."""
+    arr = rle_array(inputs)
+    _check(_lib.tq_threshold_rle_fused(ctx, arr, len(inputs), r_bits, theta, _optr(filt), _optr(out), _optr(count),
+                                       _stream(stream)), "tq_threshold_rle_fused")
+
+
+def tq_symmetric_rle_fused(ctx: int, inputs, r_bits: int, truth, filt=None, out=None, count=None,
+                           stream=None) -> None:
+    arr = rle_array(inputs)
+    tw = _u64_host(truth_words(truth))
+    _check(_lib.tq_symmetric_rle_fused(ctx, arr, len(inputs), r_bits, tw, _optr(filt), _optr(out), _optr(count),
+                                       _stream(stream)), "tq_symmetric_rle_fused")
+
+
 def tq_threshold_hybrid(ctx: int, rle_inputs, dense_inputs, r_bits: int, theta: int, out, stream=None) -> None:
     arr = rle_array(rle_inputs)
     ptrs = ptr_array(dense_inputs)
@@ -346,6 +364,14 @@ def tq_symmetric_hybrid(ctx: int, rle_inputs, dense_inputs, r_bits: int, truth, 
     tw = _u64_host(truth_words(truth))
     _check(_lib.tq_symmetric_hybrid(ctx, arr, len(rle_inputs), ptrs, len(dense_inputs), r_bits, tw, _ptr(out),
                                     _stream(stream)), "tq_symmetric_hybrid")
+
+
+def raw_threshold_rle_fused(ctx: int, inputs, r_bits: int, theta: int, filt_ptr, out_ptr, count_ptr,
+                            stream=None) -> int:
+    """Status code of tq_threshold_rle_fused with raw device addresses (0 = NULL)."""
+    arr = rle_array(inputs)
+    return _lib.tq_threshold_rle_fused(ctx, arr, len(inputs), r_bits, theta, filt_ptr or None, out_ptr or None,
+                                       count_ptr or None, _stream(stream))
 
 
 def raw_threshold_rle(ctx: int, inputs, r_bits: int, theta: int, out_ptr: int, out_cap: int, out_len_ptr: int,

@@ -193,7 +193,8 @@ __global__ __launch_bounds__(kFillBlock) void fill_sink_kernel(uint64_t* __restr
 
 constexpr int kReduceBlock = 1024;
 
-__global__ __launch_bounds__(kReduceBlock) void count_reduce_kernel(const uint32_t* __restrict__ partial,
+template <typename T>
+__global__ __launch_bounds__(kReduceBlock) void count_reduce_kernel(const T* __restrict__ partial,
                                                                     uint64_t m, uint64_t* __restrict__ count) {
   __shared__ uint64_t wave_sum[kReduceBlock / 64];
   uint64_t c = 0;
@@ -337,7 +338,12 @@ hipError_t launch_fill_sink(uint64_t* d_out, uint64_t nwords, uint64_t value, ui
 }
 
 hipError_t launch_count_reduce(const uint32_t* d_partial, uint64_t m, uint64_t* d_count, hipStream_t stream) {
-  hipLaunchKernelGGL(count_reduce_kernel, dim3(1), dim3(kReduceBlock), 0, stream, d_partial, m, d_count);
+  hipLaunchKernelGGL(count_reduce_kernel<uint32_t>, dim3(1), dim3(kReduceBlock), 0, stream, d_partial, m, d_count);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_reduce(const uint64_t* d_partial, uint64_t m, uint64_t* d_count, hipStream_t stream) {
+  hipLaunchKernelGGL(count_reduce_kernel<uint64_t>, dim3(1), dim3(kReduceBlock), 0, stream, d_partial, m, d_count);
   return hipGetLastError();
 }
 

@@ -215,6 +215,23 @@ SymPlan plan_symmetric(uint32_t n, const uint64_t* truth) {
   return p;
 }
 
+// Arguments of the fused-consumer calls (filter, output, count).
+tq_status check_sink_args(uint64_t r_bits, const uint64_t* d_filter, const uint64_t* d_out,
+                          const uint64_t* d_count) {
+  if (!d_out && !d_count) return TQ_EINVAL;
+  if (((uintptr_t)d_filter & 7) || ((uintptr_t)d_count & 7)) return TQ_EINVAL;
+  const uint64_t nw = words_for_bits(r_bits);
+  if (d_filter && d_out && d_filter != d_out) {
+    const uintptr_t f0 = (uintptr_t)d_filter, o0 = (uintptr_t)d_out;
+    if (f0 < o0 + nw * 8 && o0 < f0 + nw * 8) return TQ_EINVAL;
+  }
+  if (d_count && d_out) {
+    const uintptr_t c0 = (uintptr_t)d_count, o0 = (uintptr_t)d_out;
+    if (c0 < o0 + nw * 8 && o0 < c0 + 8) return TQ_EINVAL;
+  }
+  return TQ_OK;
+}
+
 }  // namespace tq
 
 using namespace tq;
@@ -346,21 +363,6 @@ tq_status check_dense_args(const uint64_t* const* ptrs, uint32_t n, uint64_t r_b
 // Arguments of the fused consumers: the filter is nullable and may be the
 // output itself but must not overlap it otherwise; the count is nullable;
 // at least one of output and count is given.
-tq_status check_sink_args(uint64_t r_bits, const uint64_t* d_filter, const uint64_t* d_out,
-                          const uint64_t* d_count) {
-  if (!d_out && !d_count) return TQ_EINVAL;
-  if (((uintptr_t)d_filter & 7) || ((uintptr_t)d_count & 7)) return TQ_EINVAL;
-  const uint64_t nw = words_for_bits(r_bits);
-  if (d_filter && d_out && d_filter != d_out) {
-    const uintptr_t f0 = (uintptr_t)d_filter, o0 = (uintptr_t)d_out;
-    if (f0 < o0 + nw * 8 && o0 < f0 + nw * 8) return TQ_EINVAL;
-  }
-  if (d_count && d_out) {
-    const uintptr_t c0 = (uintptr_t)d_count, o0 = (uintptr_t)d_out;
-    if (c0 < o0 + nw * 8 && o0 < c0 + 8) return TQ_EINVAL;
-  }
-  return TQ_OK;
-}
 
 // The launch shape of a dense query: the tuned shape of its class if the
 // autotuner is on (timing every candidate on the first query of the class),

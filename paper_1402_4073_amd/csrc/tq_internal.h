@@ -73,7 +73,8 @@ constexpr uint64_t kMaxLaunchItems = 1ull << 31;
 // one uint32 per column group, summed afterwards by launch_count_reduce).
 struct Sink {
   const uint64_t* filter = nullptr;
-  uint32_t* partial = nullptr;
+  uint32_t* partial = nullptr;     // dense kernels: one count per column group
+  uint64_t* partial64 = nullptr;   // tile kernel over compressed inputs: one per wave of each workgroup
 };
 
 // Column groups (= partial slots) of a dense launch over nwords words.
@@ -109,6 +110,13 @@ hipError_t launch_fill_sink(uint64_t* d_out, uint64_t nwords, uint64_t value, ui
 
 // *d_count = sum of partial[0..m)
 hipError_t launch_count_reduce(const uint32_t* d_partial, uint64_t m, uint64_t* d_count, hipStream_t stream);
+hipError_t launch_count_reduce(const uint64_t* d_partial, uint64_t m, uint64_t* d_count, hipStream_t stream);
+
+// Arguments of the fused-consumer calls: at least one of d_out / d_count,
+// 8-byte alignment, a filter equal to d_out or disjoint from it, d_count
+// outside d_out.
+tq_status check_sink_args(uint64_t r_bits, const uint64_t* d_filter, const uint64_t* d_out,
+                          const uint64_t* d_count);
 
 // -------------------------------------------------------------------- RLE
 // Device-side description of one compressed input (3 words, staged as a blob).
@@ -136,10 +144,16 @@ struct RleSym {
 size_t rle_tile_lds_bytes(int K, bool swar);
 // sym == nullptr: threshold theta; otherwise the symmetric function *sym.
 // swar: SWAR column counters (every tile in one pass) instead of bit planes.
+// sink (filter and/or partial64 set): consumers of each result word (AND
+// filter; popcounts into sink.partial64, one slot per wave of each
+// workgroup: *slots_used slots, at most rle_tile_partials(nwords)); d_out may
+// then be null.
 hipError_t launch_rle_tile(const RleDesc* d_descs, uint32_t n_rle, const uint64_t* const* d_dense,
                            uint32_t n_dense, uint64_t nwords, uint64_t tail_mask, uint32_t theta,
                            const RleSym* sym, bool swar, int num_cus, uint32_t tiles_per_group,
-                           uint64_t* d_out, int* d_status, hipStream_t stream);
+                           uint64_t* d_out, int* d_status, hipStream_t stream, const Sink& sink = Sink(),
+                           uint64_t* slots_used = nullptr);
+uint64_t rle_tile_partials(uint64_t nwords);
 size_t rle_encode_workspace_bytes(uint64_t nwords);
 hipError_t launch_rle_encode(const uint64_t* d_dense, uint64_t nwords, uint64_t tail_mask, uint64_t* d_out,
                              uint64_t cap, uint64_t* d_out_len, uint64_t* d_index, void* workspace,

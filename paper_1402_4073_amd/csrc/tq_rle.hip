@@ -367,11 +367,15 @@ __device__ __forceinline__ void walk_literals(const RleDesc& dsc, Reader& rd, Wa
 // 2.  With K <= 4 planes the kernel is built for 8 waves per SIMD, which its
 // small LDS footprint allows, at the cost of a few spilled registers
 // (measured: faster there, slower for larger K).
-template <int K, bool Sym, bool Swar, int Form = kFullPlanes>
+//
+// Fused = true: consumers of each result word (sink): AND with a filter, and a
+// count; each thread sums the popcounts of its words over the range, and each
+// wave writes one partial count per workgroup (blockIdx.x * 8 + wave).
+template <int K, bool Sym, bool Swar, int Form = kFullPlanes, bool Fused = false>
 __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu((Form != kFullPlanes && K <= 4) ? 8 : 6))) void rle_tile_kernel(
     const RleDesc* __restrict__ descs, uint32_t n_rle, const uint64_t* const* __restrict__ dense,
     uint32_t n_dense, uint32_t nwords, uint64_t tail_mask, uint32_t theta, RleSym sym, uint32_t tiles_per_group,
-    uint64_t* __restrict__ out, int* __restrict__ status) {
+    uint64_t* out, int* __restrict__ status, Sink sink) {
   extern __shared__ uint64_t lds[];
   constexpr int kCounterWords = Swar ? 16 : K;
   uint64_t* planes = lds;                                         // kCounterWords x kTile
@@ -394,7 +398,12 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu((F
   const uint32_t ranges = (tiles + tiles_per_group - 1) / tiles_per_group;
   const uint32_t per_xcd = (ranges + kXcds - 1) / kXcds;
   const uint32_t range = (blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
-  if (range >= ranges) return;
+  if (range >= ranges) {
+    if (Fused && sink.partial64 && (threadIdx.x & 63) == 0)
+      sink.partial64[(uint64_t)blockIdx.x * (kTileThreads / 64) + (threadIdx.x >> 6)] = 0;
+    return;
+  }
+  uint64_t popcount_sum = 0;   // Fused: ones of this thread's result words
   const uint32_t tile_begin = range * tiles_per_group;
   const uint32_t tile_end = tiles - tile_begin > tiles_per_group ? tile_begin + tiles_per_group : tiles;
   const int tid = threadIdx.x;
@@ -568,7 +577,24 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu((F
           res = greater_than_lane<K>(P, theta - (uint32_t)k - 1);
         }
       }
-      out[(uint64_t)t0 + c] = res & valid_mask_dev((uint64_t)t0 + c, nwords, tail_mask);
+      uint64_t word = res & valid_mask_dev((uint64_t)t0 + c, nwords, tail_mask);
+      if constexpr (Fused) {
+        // consumers: AND filter (it may be out itself: read before the store)
+        if (sink.filter) word &= sink.filter[(uint64_t)t0 + c];
+        if (out) out[(uint64_t)t0 + c] = word;
+        popcount_sum += (uint64_t)__popcll(word);
+      } else {
+        out[(uint64_t)t0 + c] = word;
+      }
+    }
+  }
+  if constexpr (Fused) {
+    if (sink.partial64) {
+      // a wave's range may hold up to 2^34 ones: 64-bit partial counts
+      uint64_t pc = popcount_sum;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) pc += __shfl_xor(pc, off, 64);
+      if ((tid & 63) == 0) sink.partial64[(uint64_t)blockIdx.x * (kTileThreads / 64) + (tid >> 6)] = pc;
     }
   }
 }
@@ -767,47 +793,95 @@ uint32_t grid_cap(uint64_t want, uint32_t cap) {
 }
 
 typedef void (*TileFn)(const RleDesc*, uint32_t, const uint64_t* const*, uint32_t, uint32_t, uint64_t,
-                       uint32_t, RleSym, uint32_t, uint64_t*, int*);
+                       uint32_t, RleSym, uint32_t, uint64_t*, int*, Sink);
 
-template <bool Sym>
+template <bool Sym, bool Fused>
 TileFn pick_tile_k(int K) {
   switch (K) {
-    case 4: return rle_tile_kernel<4, Sym, false>;
-    case 5: return rle_tile_kernel<5, Sym, false>;
-    case 6: return rle_tile_kernel<6, Sym, false>;
-    case 7: return rle_tile_kernel<7, Sym, false>;
-    case 8: return rle_tile_kernel<8, Sym, false>;
-    case 9: return rle_tile_kernel<9, Sym, false>;
-    case 10: return rle_tile_kernel<10, Sym, false>;
-    case 11: return rle_tile_kernel<11, Sym, false>;
-    case 12: return rle_tile_kernel<12, Sym, false>;
-    case 13: return rle_tile_kernel<13, Sym, false>;
-    case 16: return rle_tile_kernel<16, Sym, false>;
+    case 4: return rle_tile_kernel<4, Sym, false, kFullPlanes, Fused>;
+    case 5: return rle_tile_kernel<5, Sym, false, kFullPlanes, Fused>;
+    case 6: return rle_tile_kernel<6, Sym, false, kFullPlanes, Fused>;
+    case 7: return rle_tile_kernel<7, Sym, false, kFullPlanes, Fused>;
+    case 8: return rle_tile_kernel<8, Sym, false, kFullPlanes, Fused>;
+    case 9: return rle_tile_kernel<9, Sym, false, kFullPlanes, Fused>;
+    case 10: return rle_tile_kernel<10, Sym, false, kFullPlanes, Fused>;
+    case 11: return rle_tile_kernel<11, Sym, false, kFullPlanes, Fused>;
+    case 12: return rle_tile_kernel<12, Sym, false, kFullPlanes, Fused>;
+    case 13: return rle_tile_kernel<13, Sym, false, kFullPlanes, Fused>;
+    case 16: return rle_tile_kernel<16, Sym, false, kFullPlanes, Fused>;
   }
   return nullptr;
 }
 
 // thresholds with bit_length(theta) exact planes and a sticky one, or
 // symmetric functions with bit_length(tail_from) exact planes and a sticky one
-template <bool Sym>
+template <bool Sym, bool Fused>
 TileFn pick_sat_k(int K) {
   switch (K) {
-    case 2: return rle_tile_kernel<2, Sym, false, kSaturating>;
-    case 3: return rle_tile_kernel<3, Sym, false, kSaturating>;
-    case 4: return rle_tile_kernel<4, Sym, false, kSaturating>;
-    case 5: return rle_tile_kernel<5, Sym, false, kSaturating>;
-    case 6: return rle_tile_kernel<6, Sym, false, kSaturating>;
-    case 7: return rle_tile_kernel<7, Sym, false, kSaturating>;
-    case 8: return rle_tile_kernel<8, Sym, false, kSaturating>;
-    case 9: return rle_tile_kernel<9, Sym, false, kSaturating>;
-    case 10: return rle_tile_kernel<10, Sym, false, kSaturating>;
-    case 11: return rle_tile_kernel<11, Sym, false, kSaturating>;
-    case 12: return rle_tile_kernel<12, Sym, false, kSaturating>;
-    case 13: return rle_tile_kernel<13, Sym, false, kSaturating>;
+    case 2: return rle_tile_kernel<2, Sym, false, kSaturating, Fused>;
+    case 3: return rle_tile_kernel<3, Sym, false, kSaturating, Fused>;
+    case 4: return rle_tile_kernel<4, Sym, false, kSaturating, Fused>;
+    case 5: return rle_tile_kernel<5, Sym, false, kSaturating, Fused>;
+    case 6: return rle_tile_kernel<6, Sym, false, kSaturating, Fused>;
+    case 7: return rle_tile_kernel<7, Sym, false, kSaturating, Fused>;
+    case 8: return rle_tile_kernel<8, Sym, false, kSaturating, Fused>;
+    case 9: return rle_tile_kernel<9, Sym, false, kSaturating, Fused>;
+    case 10: return rle_tile_kernel<10, Sym, false, kSaturating, Fused>;
+    case 11: return rle_tile_kernel<11, Sym, false, kSaturating, Fused>;
+    case 12: return rle_tile_kernel<12, Sym, false, kSaturating, Fused>;
+    case 13: return rle_tile_kernel<13, Sym, false, kSaturating, Fused>;
   }
   return nullptr;
 }
 
+// The kernel of a query: its counter form and width (K), and a key of that
+// choice for the per-device occupancy table.
+struct TileChoice {
+  TileFn fn = nullptr;
+  int K = 0;
+  int key = 0;
+};
+
+template <bool Fused>
+TileChoice choose_tile(int K, uint32_t theta, const RleSym* sym, bool swar) {
+  TileChoice c;
+  c.K = K;
+  if (swar) {
+    c.fn = sym ? rle_tile_kernel<16, true, true, kFullPlanes, Fused> : rle_tile_kernel<16, false, true, kFullPlanes, Fused>;
+    c.key = 34 + (sym ? 1 : 0);
+    return c;
+  }
+  c.fn = sym ? pick_tile_k<true, Fused>(K) : pick_tile_k<false, Fused>(K);
+  c.key = K + (sym ? 17 : 0);
+  // A threshold compares each column's count with theta - k <= theta, so
+  // bit_length(theta) exact planes and a sticky one decide it: less LDS per
+  // workgroup, and more workgroups per CU, when that is fewer planes.
+  if (!sym && theta >= 1) {
+    const int ks = bit_length(theta) + 1;
+    if (ks < K && ks <= 13) {
+      c.K = ks;
+      c.fn = pick_sat_k<false, Fused>(ks);
+      c.key = 36 + ks;
+    }
+  }
+  // A symmetric f that is constant from tail_from on needs the count exactly
+  // only below tail_from: bit_length(tail_from) exact planes and a sticky one.
+  if (sym && sym->epi.kind != EPI_PARITY && sym->tail_from >= 1) {
+    const int ks = bit_length(sym->tail_from) + 1;
+    if (ks < K && ks <= 13) {
+      c.K = ks;
+      c.fn = pick_sat_k<true, Fused>(ks);
+      c.key = 51 + ks;
+    }
+  }
+  // the parity function (or its complement) needs the count modulo 2 only
+  if (sym && sym->epi.kind == EPI_PARITY) {
+    c.K = 1;
+    c.fn = rle_tile_kernel<1, true, false, kParityPlane, Fused>;
+    c.key = 50;
+  }
+  return c;
+}
 
 }  // namespace
 
@@ -818,38 +892,14 @@ size_t rle_tile_lds_bytes(int K, bool swar) {
 hipError_t launch_rle_tile(const RleDesc* d_descs, uint32_t n_rle, const uint64_t* const* d_dense,
                            uint32_t n_dense, uint64_t nwords, uint64_t tail_mask, uint32_t theta,
                            const RleSym* sym, bool swar, int num_cus, uint32_t tiles_per_group,
-                           uint64_t* d_out, int* d_status, hipStream_t stream) {
-  int K = dense_planes_for(n_rle + n_dense);
-  TileFn fn = swar ? (sym ? rle_tile_kernel<16, true, true> : rle_tile_kernel<16, false, true>)
-                   : (sym ? pick_tile_k<true>(K) : pick_tile_k<false>(K));
-  int slot = swar ? 34 + (sym ? 1 : 0) : K + (sym ? 17 : 0);
-  // A threshold compares each column's count with theta - k <= theta, so
-  // bit_length(theta) exact planes and a sticky one decide it: less LDS per
-  // workgroup, and more workgroups per CU, when that is fewer planes.
-  if (!sym && !swar && theta >= 1) {
-    const int ks = bit_length(theta) + 1;
-    if (ks < K && ks <= 13) {
-      K = ks;
-      fn = pick_sat_k<false>(K);
-      slot = 36 + K;
-    }
-  }
-  // A symmetric f that is constant from tail_from on needs the count exactly
-  // only below tail_from: bit_length(tail_from) exact planes and a sticky one.
-  if (sym && !swar && sym->epi.kind != EPI_PARITY && sym->tail_from >= 1) {
-    const int ks = bit_length(sym->tail_from) + 1;
-    if (ks < K && ks <= 13) {
-      K = ks;
-      fn = pick_sat_k<true>(K);
-      slot = 51 + K;
-    }
-  }
-  // the parity function (or its complement) needs the count modulo 2 only
-  if (sym && !swar && sym->epi.kind == EPI_PARITY) {
-    K = 1;
-    fn = rle_tile_kernel<1, true, false, kParityPlane>;
-    slot = 50;
-  }
+                           uint64_t* d_out, int* d_status, hipStream_t stream, const Sink& sink,
+                           uint64_t* slots_used) {
+  const bool fused = sink.filter != nullptr || sink.partial64 != nullptr;
+  const int K0 = dense_planes_for(n_rle + n_dense);
+  const TileChoice ch = fused ? choose_tile<true>(K0, theta, sym, swar) : choose_tile<false>(K0, theta, sym, swar);
+  TileFn fn = ch.fn;
+  const int K = ch.K;
+  const int slot = ch.key + (fused ? 65 : 0);
   if (!fn) return hipErrorInvalidValue;
   const uint64_t tiles = (nwords + kTile - 1) / kTile;
   if (tiles == 0) return hipSuccess;
@@ -857,7 +907,7 @@ hipError_t launch_rle_tile(const RleDesc* d_descs, uint32_t n_rle, const uint64_
   // LDS limit and resident workgroups per CU, set and measured once per device
   constexpr int kMaxDevices = 64;
   static std::mutex mu;
-  static int resident[kMaxDevices][65] = {};
+  static int resident[kMaxDevices][130] = {};
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
@@ -883,8 +933,14 @@ hipError_t launch_rle_tile(const RleDesc* d_descs, uint32_t n_rle, const uint64_
   const uint64_t grid = (ranges + kXcds - 1) / kXcds * kXcds;
   hipLaunchKernelGGL(fn, dim3((uint32_t)grid), dim3(kTileThreads), lds, stream, d_descs, n_rle, d_dense,
                      n_dense, (uint32_t)nwords, tail_mask, theta, sym ? *sym : RleSym{}, (uint32_t)per_group,
-                     d_out, d_status);
+                     d_out, d_status, sink);
+  if (slots_used) *slots_used = grid * (kTileThreads / 64);
   return hipGetLastError();
+}
+
+// workgroups of a launch are at most its tiles rounded up to a multiple of kXcds
+uint64_t rle_tile_partials(uint64_t nwords) {
+  return ((nwords + kTile - 1) / kTile + kXcds - 1) / kXcds * kXcds * (kTileThreads / 64);
 }
 
 size_t rle_encode_workspace_bytes(uint64_t nwords) {

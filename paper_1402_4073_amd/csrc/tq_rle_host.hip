@@ -181,7 +181,8 @@ RleShape rle_shape(tq_ctx* ctx, uint32_t n, uint64_t nw, const RleFn& qf, const 
 // workspace is taken.
 tq_status run_rle_tiles(tq_ctx* ctx, const tq_rle* inputs, uint32_t n_rle, const uint64_t* const* dense_ptrs,
                         uint32_t n_dense, uint64_t r_bits, const RleFn& qf, uint64_t* d_dense_out,
-                        uint64_t* idx_area, hipStream_t stream) {
+                        uint64_t* idx_area, hipStream_t stream, const Sink& sink = Sink(),
+                        uint64_t* slots_used = nullptr) {
   const uint64_t nw = words_for_bits(r_bits);
   const uint64_t tmask = tail_mask_for(r_bits);
   const uint32_t n = n_rle + n_dense;
@@ -223,7 +224,7 @@ tq_status run_rle_tiles(tq_ctx* ctx, const tq_rle* inputs, uint32_t n_rle, const
     return launch_rle_tile(reinterpret_cast<const RleDesc*>(d_desc), n_rle,
                            reinterpret_cast<const uint64_t* const*>(d_dense), n_dense, nw, tmask, qf.theta,
                            qf.truth ? &tabs.sym : nullptr, sh.swar, ctx->num_cus, sh.tiles, d_dense_out,
-                           ctx->d_status, stream);
+                           ctx->d_status, stream, sink, slots_used);
   };
   st = record_hip(ctx, launch(rle_shape(ctx, n, nw, qf, plan, launch, stream)));
   blob_used(ctx, bd, stream);
@@ -274,6 +275,52 @@ tq_status hybrid_entry(tq_ctx* ctx, const tq_rle* rle_inputs, uint32_t n_rle, co
     if (p < (uintptr_t)(d_out + nw) && (uintptr_t)d_out < p + nw * 8) return TQ_EINVAL;
   }
   return rle_query_dense(ctx, rle_inputs, n_rle, dense_ptrs, n_dense, r_bits, qf, d_out, stream);
+}
+
+// Dense query with fused consumers (filter AND, count) over compressed or
+// hybrid inputs.
+tq_status rle_fused_entry(tq_ctx* ctx, const tq_rle* inputs, uint32_t n, uint64_t r_bits, const RleFn& qf,
+                          const uint64_t* d_filter, uint64_t* d_out, uint64_t* d_count, hipStream_t stream) {
+  if (!ctx || !inputs || n == 0 || n > TQ_RLE_MAX_INPUTS) return TQ_EINVAL;
+  const uint64_t nw = words_for_bits(r_bits);
+  if (nw >= (1ull << 31)) return TQ_EINVAL;
+  tq_status st = check_sink_args(r_bits, d_filter, d_out, d_count);
+  if (st != TQ_OK) return st;
+  if ((uintptr_t)d_out & 7) return TQ_EINVAL;
+  if (nw == 0) return d_count ? record_hip(ctx, launch_set_u64(d_count, 0, stream)) : TQ_OK;
+  size_t idx_bytes = 0;
+  st = missing_index_bytes(inputs, n, nw, &idx_bytes);
+  if (st != TQ_OK) return st;
+  const SymPlan plan = qf.truth ? plan_symmetric(n, qf.truth) : plan_threshold(n, qf.theta);
+  const uint64_t tmask = tail_mask_for(r_bits);
+  Sink sink;
+  sink.filter = d_filter;
+  // partial counts: uint32 per 256-word block for a constant result, uint64
+  // per wave of each tile-kernel workgroup otherwise
+  const size_t part_bytes =
+      !d_count ? 0 : align256(plan.constant ? fill_groups(nw) * sizeof(uint32_t) : rle_tile_partials(nw) * 8);
+  // workspace: [partial counts | built indexes], sized before any pointer into it is taken
+  char* ws = nullptr;
+  if (part_bytes + idx_bytes) {
+    ws = static_cast<char*>(workspace(ctx, part_bytes + idx_bytes));
+    if (!ws) return TQ_ENOMEM;
+  }
+  if (plan.constant) {
+    if (d_count) sink.partial = reinterpret_cast<uint32_t*>(ws);
+    st = record_hip(ctx, launch_fill_sink(d_out, nw, plan.const_word, tmask, sink, stream));
+    if (st == TQ_OK && d_count)
+      st = record_hip(ctx, launch_count_reduce(sink.partial, fill_groups(nw), d_count, stream));
+    return st;
+  }
+  if (d_count) sink.partial64 = reinterpret_cast<uint64_t*>(ws);
+  uint64_t* idx_area = idx_bytes ? reinterpret_cast<uint64_t*>(ws + part_bytes) : nullptr;
+  uint64_t slots = 0;
+  st = run_rle_tiles(ctx, inputs, n, nullptr, 0, r_bits, qf, d_out, idx_area, stream, sink, &slots);
+  if (st == TQ_OK && d_count) {
+    const uint64_t* partial = sink.partial64;
+    st = record_hip(ctx, launch_count_reduce(partial, slots, d_count, stream));
+  }
+  return st;
 }
 
 // Query with a canonical RLE result.
@@ -378,6 +425,18 @@ tq_status tq_symmetric_rle(tq_ctx* ctx, const tq_rle* inputs, uint32_t n, uint64
                            uint64_t* d_out, uint64_t out_cap_words, uint64_t* d_out_len, hipStream_t stream) {
   if (!h_truth) return TQ_EINVAL;
   return rle_rle_entry(ctx, inputs, n, r_bits, RleFn{0, h_truth}, d_out, out_cap_words, d_out_len, stream);
+}
+
+tq_status tq_threshold_rle_fused(tq_ctx* ctx, const tq_rle* inputs, uint32_t n, uint64_t r_bits, uint32_t theta,
+                                 const uint64_t* d_filter, uint64_t* d_out, uint64_t* d_count, hipStream_t stream) {
+  return rle_fused_entry(ctx, inputs, n, r_bits, RleFn{theta, nullptr}, d_filter, d_out, d_count, stream);
+}
+
+tq_status tq_symmetric_rle_fused(tq_ctx* ctx, const tq_rle* inputs, uint32_t n, uint64_t r_bits,
+                                 const uint64_t* h_truth, const uint64_t* d_filter, uint64_t* d_out,
+                                 uint64_t* d_count, hipStream_t stream) {
+  if (!h_truth) return TQ_EINVAL;
+  return rle_fused_entry(ctx, inputs, n, r_bits, RleFn{0, h_truth}, d_filter, d_out, d_count, stream);
 }
 
 }  // extern "C"

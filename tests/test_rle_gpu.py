@@ -450,6 +450,70 @@ def test_threshold_counts_beyond_narrow_counters(ctx, tiles_option, n_rle, n_den
         assert np.array_equal(to_host(out), oracle.symmetric(dense, r, t)), list(np.nonzero(t)[0][:12])
 
 
+# ------------------------------------------- fused consumers over RLE
+def count_dev():
+    return torch.full((1,), -1, dtype=torch.int64, device="cuda")
+
+
+@pytest.mark.parametrize("n,r,tiles", [(1, 64 * 700 + 9, 0), (37, 64 * STRIDE * 3 + 17, 2), (300, 64 * 2100 + 1, 0)])
+def test_rle_fused_consumers(ctx, tiles_option, n, r, tiles):
+    """tq_threshold_rle_fused / tq_symmetric_rle_fused: the result AND a
+    filter, and its count, equal the oracle's result, AND and position count,
+    for thresholds (constant ones included), symmetric functions (parity,
+    interval, random and constant tables), with and without filter, stored
+    and count-only, filtered in place, with and without indexes."""
+    rng = np.random.default_rng(70 + n)
+    nw = (r + 63) // 64
+    dense = markov_bitmaps(1700 + n, n, r, float(rng.integers(20, 300)), float(rng.integers(100, 3000)))
+    fhost = np.packbits((rng.random(nw * 64) < 0.7).astype(np.uint8), bitorder="little").view("<u8").astype(np.uint64)
+    assert tiles_option(tiles) == tq.TQ_OK
+    for with_index in (True, False):
+        inputs, keep = rle_inputs(ctx, dense, r, with_index=with_index)
+        cases = [("t", t) for t in (0, 1, 2, max(1, n // 3), n, n + 1)]
+        cases += [("s", t) for t in sym_tables(n, rng)]
+        for kind, arg in cases:
+            want = oracle.threshold(dense, r, arg) if kind == "t" else oracle.symmetric(dense, r, arg)
+            for use_filter in (False, True):
+                w_out, w_cnt = oracle.consume(want, r, fhost if use_filter else None)
+                filt = to_dev(fhost) if use_filter else None
+                out, cnt = empty_words(nw), count_dev()
+                if kind == "t":
+                    tq.tq_threshold_rle_fused(ctx, inputs, r, arg, filt, out, cnt)
+                else:
+                    tq.tq_symmetric_rle_fused(ctx, inputs, r, arg, filt, out, cnt)
+                assert tq.tq_ctx_check(ctx) == 0
+                assert np.array_equal(to_host(out), w_out), (kind, use_filter)
+                assert int(cnt.item()) == w_cnt, (kind, use_filter)
+                cnt2 = count_dev()                       # count only
+                if kind == "t":
+                    tq.tq_threshold_rle_fused(ctx, inputs, r, arg, filt, None, cnt2)
+                else:
+                    tq.tq_symmetric_rle_fused(ctx, inputs, r, arg, filt, None, cnt2)
+                assert int(cnt2.item()) == w_cnt
+            # in place: the filter is the output buffer
+            buf = to_dev(fhost)
+            if kind == "t":
+                tq.tq_threshold_rle_fused(ctx, inputs, r, arg, buf, buf, None)
+            else:
+                tq.tq_symmetric_rle_fused(ctx, inputs, r, arg, buf, buf, None)
+            assert np.array_equal(to_host(buf), oracle.consume(want, r, fhost)[0])
+
+
+def test_rle_fused_errors_and_empty(ctx):
+    r = 64 * 40
+    dense = markov_bitmaps(1800, 3, r, 30.0, 300.0)
+    inputs, keep = rle_inputs(ctx, dense, r)
+    out = empty_words(40)
+    cnt = count_dev()
+    assert tq.raw_threshold_rle_fused(ctx, inputs, r, 2, 0, 0, 0) == tq.TQ_EINVAL          # nothing to produce
+    assert tq.raw_threshold_rle_fused(ctx, inputs, r, 2, 0, out.data_ptr() + 4, 0) == tq.TQ_EINVAL
+    assert tq.raw_threshold_rle_fused(ctx, inputs, r, 2, 0, out.data_ptr(), out.data_ptr() + 16) == tq.TQ_EINVAL
+    assert tq.raw_threshold_rle_fused(ctx, inputs, r, 2, out.data_ptr() + 8, out.data_ptr(), 0) == tq.TQ_EINVAL
+    assert tq.raw_threshold_rle_fused(ctx, inputs, 0, 2, 0, 0, cnt.data_ptr()) == tq.TQ_OK  # r = 0 counts zero
+    assert tq.tq_ctx_check(ctx) == 0
+    assert int(cnt.item()) == 0
+
+
 # ------------------------------------------- symmetric functions over RLE
 def sym_tables(n, rng):
     t = [oracle.truth_parity(n), 1 - oracle.truth_parity(n), oracle.truth_interval(n, 2, min(n, 10)),
