@@ -361,10 +361,11 @@ __device__ __forceinline__ void walk_literals(const RleDesc& dsc, Reader& rd, Wa
 // any symmetric f, decided where f is constant on [k, k + d] and otherwise
 // evaluated on k plus the counted dirty bits.  Swar = true: SWAR column
 // counters, every tile in one pass; otherwise K bit-sliced planes in the
-// form Form: kSaturating (thresholds only) makes the top plane sticky (see
-// ripple_lds_sat), so K = bit_length(theta) + 1 planes suffice; kParityPlane
-// (the parity function and its complement) keeps one plane, the count modulo
-// 2.  With K <= 4 planes the kernel is built for 8 waves per SIMD, which its
+// form Form: kSaturating makes the top plane sticky (see ripple_lds_sat), so
+// K = bit_length(theta) + 1 planes suffice for a threshold, and
+// bit_length(tail_from) + 1 for a symmetric f constant from tail_from on;
+// kParityPlane (the parity function and its complement) keeps one plane, the
+// count modulo 2.  With K <= 4 planes the kernel is built for 8 waves per SIMD, which its
 // small LDS footprint allows, at the cost of a few spilled registers
 // (measured: faster there, slower for larger K).
 //
