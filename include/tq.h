@@ -129,6 +129,23 @@ tq_status tq_tune_clear(tq_ctx* ctx);
 tq_status tq_ctx_check(tq_ctx* ctx, hipStream_t stream);
 
 /*
+ * Stream capture.  The query calls may be made on a stream that is being
+ * captured into a HIP graph; the graph then replays them with the arguments
+ * of the capture.  During capture the library copies and allocates nothing:
+ * the host arrays a call stages (pointer arrays, truth tables, compressed-
+ * input descriptors) must have been staged by an earlier call with the same
+ * contents on the same stream, and the context's workspace must already be
+ * large enough; otherwise the call returns TQ_EINVAL and records nothing.
+ * What a captured call uses is kept for the context's lifetime (staged arrays
+ * are never evicted, a workspace a graph refers to is never freed while the
+ * context lives), so replays stay valid whatever eager calls run between
+ * them.  Replays and other calls that use the workspace must be ordered, as
+ * for eager calls.  The autotuner does not time under capture, the
+ * selector's timing fallback is skipped, and tq_batch_submit returns
+ * TQ_EINVAL (a batch replays its own graph).
+ */
+
+/*
  * Threshold query (section 2.3, the function written there as
  * theta(T, {B_1..B_N})):
  *   d_out bit p = [ #{ j : bit p of ptrs[j] is set } >= theta ]   for p < r_bits,

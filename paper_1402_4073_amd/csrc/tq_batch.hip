@@ -420,6 +420,9 @@ tq_status tq_batch_submit(tq_ctx* ctx, const tq_query* queries, uint32_t count, 
                           hipStream_t stream, tq_batch** out) {
   if (!ctx || !out || (count && !queries)) return TQ_EINVAL;
   *out = nullptr;
+  // a batch replays its slot's own graph and reports through host memory:
+  // it cannot be captured into another graph
+  if (stream_capturing(stream)) return TQ_EINVAL;
   if (count == 0 || count > kSlotQueries) return TQ_EINVAL;
   BatchState* bs = batch_state(ctx);
   if (!bs) return TQ_ENOMEM;

@@ -56,27 +56,43 @@ void blob_release(Blob& b) {
 
 const void* blob_get(tq_ctx* ctx, const uint64_t* words, size_t count, hipStream_t stream,
                      Blob** which) {
+  // Under stream capture nothing is copied: the array must have been staged
+  // by an earlier call on the same stream, and it is then frozen (kept as it
+  // is for the captured graph, which reads it at every replay).
+  const bool capturing = stream_capturing(stream);
   const uint64_t h = hash_words(words, count);
   for (auto& b : ctx->blobs) {
     if (b.valid && b.hash == h && b.content.size() == count &&
         memcmp(b.content.data(), words, count * 8) == 0) {
       if (b.copy_stream != stream) {
+        if (capturing) {
+          ctx->staging_status = TQ_EINVAL;
+          return nullptr;
+        }
         hipError_t e = hipStreamWaitEvent(stream, b.copied, 0);
         if (e != hipSuccess) { record_hip(ctx, e); return nullptr; }
       }
+      if (capturing) b.frozen = true;
       b.lru = ++ctx->lru_clock;
       *which = &b;
       return b.d;
     }
+  }
+  if (capturing) {
+    ctx->staging_status = TQ_EINVAL;
+    return nullptr;
   }
   Blob* victim = nullptr;
   if (ctx->blobs.size() < kMaxBlobs) {
     ctx->blobs.emplace_back();
     victim = &ctx->blobs.back();
   } else {
-    victim = &ctx->blobs[0];
     for (auto& b : ctx->blobs)
-      if (b.lru < victim->lru) victim = &b;
+      if (!b.frozen && (!victim || b.lru < victim->lru)) victim = &b;
+    if (!victim) {   // every slot holds an array of a captured graph
+      ctx->staging_status = TQ_ENOMEM;
+      return nullptr;
+    }
   }
   hipError_t e = blob_wait_idle(*victim);
   if (e != hipSuccess) { record_hip(ctx, e); return nullptr; }
@@ -118,6 +134,9 @@ const void* blob_get(tq_ctx* ctx, const uint64_t* words, size_t count, hipStream
 }
 
 void blob_used(tq_ctx* ctx, Blob* b, hipStream_t stream) {
+  // a frozen array is never rewritten, so its readers need no tracking (and
+  // an event recorded under capture is not one the host could wait for)
+  if (b->frozen) return;
   for (auto& u : b->uses) {
     if (u.first == stream) {
       record_hip(ctx, hipEventRecord(u.second, stream));
@@ -288,6 +307,7 @@ tq_status tq_destroy(tq_ctx* ctx) {
   tuner_destroy(ctx);
   for (auto& b : ctx->blobs) blob_release(b);
   if (ctx->ws) hipFree(ctx->ws);
+  for (void* p : ctx->ws_retired) hipFree(p);
   if (ctx->d_status) hipFree(ctx->d_status);
   delete ctx;
   return TQ_OK;
@@ -420,8 +440,8 @@ tq_status run_dense(tq_ctx* ctx, const uint64_t* const* ptrs, uint32_t n, uint64
     if (!fused) return record_hip(ctx, launch_fill(d_out, nw, plan.const_word, tmask, stream));
     const uint64_t slots = fill_groups(nw);
     if (d_count) {
-      sink.partial = static_cast<uint32_t*>(workspace(ctx, slots * sizeof(uint32_t)));
-      if (!sink.partial) return TQ_ENOMEM;
+      sink.partial = static_cast<uint32_t*>(workspace(ctx, slots * sizeof(uint32_t), stream));
+      if (!sink.partial) return staging_error(ctx, TQ_ENOMEM);
     }
     tq_status st = record_hip(ctx, launch_fill_sink(d_out, nw, plan.const_word, tmask, sink, stream));
     if (st == TQ_OK && d_count) st = record_hip(ctx, launch_count_reduce(sink.partial, slots, d_count, stream));
@@ -429,7 +449,7 @@ tq_status run_dense(tq_ctx* ctx, const uint64_t* const* ptrs, uint32_t n, uint64
   }
   Blob* pb = nullptr;
   const void* d_ptrs = blob_get(ctx, reinterpret_cast<const uint64_t*>(ptrs), n, stream, &pb);
-  if (!d_ptrs) return TQ_EDEVICE;
+  if (!d_ptrs) return staging_error(ctx, TQ_EDEVICE);
   EpiParams epi = plan.epi;
   epi.prune = ctx->prune ? 1u : 0u;
   Blob* tb = nullptr;
@@ -437,7 +457,7 @@ tq_status run_dense(tq_ctx* ctx, const uint64_t* const* ptrs, uint32_t n, uint64
     std::vector<uint64_t> t64((plan.table.size() + 1) / 2, 0);
     memcpy(t64.data(), plan.table.data(), plan.table.size() * 4);
     const void* d_t = blob_get(ctx, t64.data(), t64.size(), stream, &tb);
-    if (!d_t) return TQ_EDEVICE;
+    if (!d_t) return staging_error(ctx, TQ_EDEVICE);
     epi.table = reinterpret_cast<const uint32_t*>(d_t);
   }
   const uint64_t* const* dp = reinterpret_cast<const uint64_t* const*>(d_ptrs);
@@ -454,8 +474,8 @@ tq_status run_dense(tq_ctx* ctx, const uint64_t* const* ptrs, uint32_t n, uint64
       ctx, n, nw, epi, aligned16,
       [&](const DenseConfig& c) { return launch_dense(c, dp, n, nw, tmask, d_out, epi, stream); }, stream);
   if (d_count) {
-    sink.partial = static_cast<uint32_t*>(workspace(ctx, dense_groups(cfg, nw) * sizeof(uint32_t)));
-    if (!sink.partial) return TQ_ENOMEM;
+    sink.partial = static_cast<uint32_t*>(workspace(ctx, dense_groups(cfg, nw) * sizeof(uint32_t), stream));
+    if (!sink.partial) return staging_error(ctx, TQ_ENOMEM);
   }
   tq_status st = record_hip(ctx, launch_dense(cfg, dp, n, nw, tmask, d_out, epi, stream, sink));
   if (st == TQ_OK && d_count)
@@ -535,10 +555,10 @@ tq_status tq_threshold_weighted(tq_ctx* ctx, const uint64_t* const* ptrs, uint32
   Blob* pb = nullptr;
   Blob* cb = nullptr;
   const void* d_ptrs = blob_get(ctx, sorted.data(), sorted.size(), stream, &pb);
-  if (!d_ptrs) return TQ_EDEVICE;
+  if (!d_ptrs) return staging_error(ctx, TQ_EDEVICE);
   const void* d_cls = blob_get(ctx, reinterpret_cast<const uint64_t*>(classes.data()), classes.size() * 2, stream,
                                &cb);
-  if (!d_cls) return TQ_EDEVICE;
+  if (!d_cls) return staging_error(ctx, TQ_EDEVICE);
   st = record_hip(ctx, launch_weighted(reinterpret_cast<const uint64_t* const*>(d_ptrs),
                                        reinterpret_cast<const WeightClass*>(d_cls), (uint32_t)classes.size(),
                                        max_class, nw, tmask, (uint32_t)theta, (uint32_t)total, d_out, stream));

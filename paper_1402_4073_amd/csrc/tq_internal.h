@@ -200,6 +200,7 @@ struct Blob {
   std::vector<std::pair<hipStream_t, hipEvent_t>> uses;
   uint64_t lru = 0;
   bool valid = false;
+  bool frozen = false;   // staged for a captured graph: never evicted or rewritten
 };
 
 }  // namespace tq
@@ -213,6 +214,9 @@ struct tq_ctx {
   uint64_t lru_clock = 0;
   void* ws = nullptr;          // grow-only device workspace (RLE paths)
   size_t ws_bytes = 0;
+  bool ws_frozen = false;      // ws is referenced by a captured graph: retire it instead of freeing
+  std::vector<void*> ws_retired;   // workspaces of captured graphs, freed with the context
+  tq_status staging_status = TQ_OK;   // why the last blob_get / workspace call failed
   void* batch = nullptr;       // batch slots (created on first submission)
   void* selector = nullptr;    // selector network and feature ranges
   int prune = 1;               // TQ_OPTION_PRUNE
@@ -249,6 +253,11 @@ void batch_destroy(tq_ctx* ctx);
 void selector_destroy(tq_ctx* ctx);
 
 // Device workspace of at least `bytes` (grown with a device synchronisation).
-void* workspace(tq_ctx* ctx, size_t bytes);
+// Grow-only device workspace.  Under stream capture it cannot grow (nullptr,
+// staging_status = TQ_EINVAL) and is kept alive for the captured graph.
+void* workspace(tq_ctx* ctx, size_t bytes, hipStream_t stream);
+// Status to return after blob_get or workspace failed: TQ_EINVAL when stream
+// capture refused the staging, else dflt.
+tq_status staging_error(tq_ctx* ctx, tq_status dflt);
 
 }  // namespace tq

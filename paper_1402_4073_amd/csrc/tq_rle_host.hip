@@ -23,14 +23,28 @@ hipError_t launch_set_u64(uint64_t* d_dst, uint64_t value, hipStream_t stream) {
   return hipGetLastError();
 }
 
-void* workspace(tq_ctx* ctx, size_t bytes) {
-  if (bytes <= ctx->ws_bytes && ctx->ws) return ctx->ws;
+void* workspace(tq_ctx* ctx, size_t bytes, hipStream_t stream) {
+  const bool capturing = stream_capturing(stream);
+  if (bytes <= ctx->ws_bytes && ctx->ws) {
+    if (capturing) ctx->ws_frozen = true;   // a captured graph now refers to it
+    return ctx->ws;
+  }
+  if (capturing) {   // no allocation under capture
+    ctx->staging_status = TQ_EINVAL;
+    return nullptr;
+  }
   // the old buffer may still be read by queued work
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) { record_hip(ctx, e); return nullptr; }
-  if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->ws) {
+    if (ctx->ws_frozen)
+      ctx->ws_retired.push_back(ctx->ws);   // captured graphs still read it
+    else
+      (void)hipFree(ctx->ws);
+  }
   ctx->ws = nullptr;
   ctx->ws_bytes = 0;
+  ctx->ws_frozen = false;
   size_t want = align256(bytes + bytes / 4);
   if ((e = hipMalloc(&ctx->ws, want)) != hipSuccess) {
     record_hip(ctx, e);
@@ -39,6 +53,12 @@ void* workspace(tq_ctx* ctx, size_t bytes) {
   }
   ctx->ws_bytes = want;
   return ctx->ws;
+}
+
+tq_status staging_error(tq_ctx* ctx, tq_status dflt) {
+  const tq_status st = ctx->staging_status;
+  ctx->staging_status = TQ_OK;
+  return st != TQ_OK ? st : dflt;
 }
 
 namespace {
@@ -95,7 +115,7 @@ tq_status sym_tables(tq_ctx* ctx, uint32_t n, const uint64_t* truth, const SymPl
   memcpy(re64.data(), run_end.data(), (size_t)(n + 1) * 4);
   const void* d_f = blob_get(ctx, f.data(), f.size(), stream, &t->blobs[0]);
   const void* d_re = blob_get(ctx, re64.data(), re64.size(), stream, &t->blobs[1]);
-  if (!d_f || !d_re) return TQ_EDEVICE;
+  if (!d_f || !d_re) return staging_error(ctx, TQ_EDEVICE);
   t->sym.f = static_cast<const uint64_t*>(d_f);
   t->sym.run_end = static_cast<const uint32_t*>(d_re);
   t->sym.epi = plan.epi;
@@ -107,7 +127,7 @@ tq_status sym_tables(tq_ctx* ctx, uint32_t n, const uint64_t* truth, const SymPl
     std::vector<uint64_t> t64((plan.table.size() + 1) / 2, 0);
     memcpy(t64.data(), plan.table.data(), plan.table.size() * 4);
     const void* d_t = blob_get(ctx, t64.data(), t64.size(), stream, &t->blobs[2]);
-    if (!d_t) return TQ_EDEVICE;
+    if (!d_t) return staging_error(ctx, TQ_EDEVICE);
     t->sym.epi.table = static_cast<const uint32_t*>(d_t);
   }
   return TQ_OK;
@@ -213,12 +233,12 @@ tq_status run_rle_tiles(tq_ctx* ctx, const tq_rle* inputs, uint32_t n_rle, const
   }
   Blob* bd = nullptr;
   const void* d_desc = blob_get(ctx, desc.data(), desc.size(), stream, &bd);
-  if (!d_desc) return TQ_EDEVICE;
+  if (!d_desc) return staging_error(ctx, TQ_EDEVICE);
   Blob* bp = nullptr;
   const void* d_dense = nullptr;
   if (n_dense) {
     d_dense = blob_get(ctx, reinterpret_cast<const uint64_t*>(dense_ptrs), n_dense, stream, &bp);
-    if (!d_dense) return TQ_EDEVICE;
+    if (!d_dense) return staging_error(ctx, TQ_EDEVICE);
   }
   auto launch = [&](const RleShape& sh) {
     return launch_rle_tile(reinterpret_cast<const RleDesc*>(d_desc), n_rle,
@@ -243,8 +263,8 @@ tq_status rle_query_dense(tq_ctx* ctx, const tq_rle* inputs, uint32_t n_rle, con
   if (st != TQ_OK) return st;
   uint64_t* idx_area = nullptr;
   if (idx_bytes) {
-    idx_area = static_cast<uint64_t*>(workspace(ctx, idx_bytes));
-    if (!idx_area) return TQ_ENOMEM;
+    idx_area = static_cast<uint64_t*>(workspace(ctx, idx_bytes, stream));
+    if (!idx_area) return staging_error(ctx, TQ_ENOMEM);
   }
   return run_rle_tiles(ctx, inputs, n_rle, dense_ptrs, n_dense, r_bits, qf, d_out, idx_area, stream);
 }
@@ -302,8 +322,8 @@ tq_status rle_fused_entry(tq_ctx* ctx, const tq_rle* inputs, uint32_t n, uint64_
   // workspace: [partial counts | built indexes], sized before any pointer into it is taken
   char* ws = nullptr;
   if (part_bytes + idx_bytes) {
-    ws = static_cast<char*>(workspace(ctx, part_bytes + idx_bytes));
-    if (!ws) return TQ_ENOMEM;
+    ws = static_cast<char*>(workspace(ctx, part_bytes + idx_bytes, stream));
+    if (!ws) return staging_error(ctx, TQ_ENOMEM);
   }
   if (plan.constant) {
     if (d_count) sink.partial = reinterpret_cast<uint32_t*>(ws);
@@ -338,8 +358,8 @@ tq_status rle_rle_entry(tq_ctx* ctx, const tq_rle* inputs, uint32_t n, uint64_t 
   size_t idx_bytes = 0;
   tq_status st = missing_index_bytes(inputs, n, nw, &idx_bytes);
   if (st != TQ_OK) return st;
-  char* ws = static_cast<char*>(workspace(ctx, dense_bytes + enc_bytes + idx_bytes));
-  if (!ws) return TQ_ENOMEM;
+  char* ws = static_cast<char*>(workspace(ctx, dense_bytes + enc_bytes + idx_bytes, stream));
+  if (!ws) return staging_error(ctx, TQ_ENOMEM);
   uint64_t* dense = reinterpret_cast<uint64_t*>(ws);
   uint64_t* idx_area = idx_bytes ? reinterpret_cast<uint64_t*>(ws + dense_bytes + enc_bytes) : nullptr;
   st = run_rle_tiles(ctx, inputs, n, nullptr, 0, r_bits, qf, dense, idx_area, stream);
@@ -368,8 +388,8 @@ tq_status tq_rle_encode(tq_ctx* ctx, const uint64_t* d_dense, uint64_t r_bits, u
   if (nw == 0) return record_hip(ctx, launch_set_u64(d_out_len, 0, stream));
   if (!d_dense || (!d_out && out_cap > 0)) return TQ_EINVAL;
   if (((uintptr_t)d_dense & 7) || ((uintptr_t)d_out & 7) || ((uintptr_t)d_index & 7)) return TQ_EINVAL;
-  void* ws = workspace(ctx, rle_encode_workspace_bytes(nw));
-  if (!ws) return TQ_ENOMEM;
+  void* ws = workspace(ctx, rle_encode_workspace_bytes(nw), stream);
+  if (!ws) return staging_error(ctx, TQ_ENOMEM);
   return record_hip(ctx, launch_rle_encode(d_dense, nw, tail_mask_for(r_bits), d_out, out_cap, d_out_len, d_index,
                                            ws, ctx->d_status, stream));
 }

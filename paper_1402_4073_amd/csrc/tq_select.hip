@@ -178,7 +178,7 @@ tq_status tq_threshold_variant(tq_ctx* ctx, const tq_bitmap* inputs, uint32_t n,
         return record_hip(ctx, launch_fill(d_out, nw, theta == 0 ? ~(uint64_t)0 : 0, tail_mask_for(r_bits), stream));
       Blob* pb = nullptr;
       const void* d_ptrs = blob_get(ctx, reinterpret_cast<const uint64_t*>(dense.data()), n, stream, &pb);
-      if (!d_ptrs) return TQ_EDEVICE;
+      if (!d_ptrs) return staging_error(ctx, TQ_EDEVICE);
       tq_status st = record_hip(ctx, launch_counter(reinterpret_cast<const uint64_t* const*>(d_ptrs), n, nw,
                                                     tail_mask_for(r_bits), theta, nullptr, d_out, stream));
       blob_used(ctx, pb, stream);
@@ -257,7 +257,8 @@ tq_status tq_threshold_auto(tq_ctx* ctx, const tq_bitmap* inputs, uint32_t n, ui
     best = variant_available(inputs, n, TQ_VARIANT_CSA) ? TQ_VARIANT_CSA : TQ_VARIANT_HYBRID;
     uncertain = true;
   }
-  if ((flags & TQ_AUTO_FALLBACK) && uncertain) {
+  // the fallback times the variants and synchronises: not under stream capture
+  if ((flags & TQ_AUTO_FALLBACK) && uncertain && !stream_capturing(stream)) {
     uint32_t avail = 0;
     for (int v = 0; v < kOut; ++v)
       if (variant_available(inputs, n, v)) avail |= 1u << v;
@@ -314,8 +315,8 @@ tq_status tq_mlp_grad(tq_ctx* ctx, const float* d_params, const float* d_x, cons
                       uint32_t batch, float mask_count, float* d_y, float* d_grad, float* d_loss,
                       hipStream_t stream) {
   if (!ctx || !d_params || !d_grad || batch == 0 || !d_x || !d_t || !(mask_count > 0.f)) return TQ_EINVAL;
-  void* ws = workspace(ctx, mlp_grad_workspace_bytes(batch));
-  if (!ws) return TQ_ENOMEM;
+  void* ws = workspace(ctx, mlp_grad_workspace_bytes(batch), stream);
+  if (!ws) return staging_error(ctx, TQ_ENOMEM);
   return record_hip(ctx, launch_mlp_grad(d_params, d_x, d_t, d_mask, batch, 1.f / mask_count, d_y, d_grad, d_loss,
                                          ws, stream));
 }
