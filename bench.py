@@ -575,6 +575,26 @@ def bench_selector(args):
     }
 
 
+def time_graph_step(torch, one_step, stream, steps):
+    """The step's queries captured once into a HIP graph (every array they
+    stage was staged by the eager passes on the same stream) and replayed:
+    launch-bound small queries lose most of their per-call host cost."""
+    g = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=stream):
+        one_step(None)
+    g.replay()
+    torch.cuda.synchronize()
+    reps = max(steps, 20)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.replay()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"ms_per_step": round(dt / reps * 1e3, 4), "steps": reps,
+            "note": "the same queries captured into one graph and replayed (wall time per replay)"}
+
+
 def time_consumers(tq, ctx, rows, r, nw, stream, steps):
     """Fused consumers of a result (threshold 16): the plain query, the query
     with an AND filter and a count in the same pass, and the count alone."""
@@ -783,6 +803,7 @@ def main():
     _, kernel_ms = timed_pass(0)
     tq.tq_set_option(ctx, tq.TQ_OPTION_PRUNE, 1)
     tq.tq_set_option(ctx, tq.TQ_OPTION_LOOPED, 1)
+    graph = time_graph_step(torch, one_step, stream, args.steps) if args.workload == "small" else None
     consumers = None if args.no_consumers else time_consumers(tq, ctx, rows, r, nw, stream, args.steps)
     weighted = None if args.no_consumers else time_weighted(tq, ctx, rows, r, nw, stream, args.steps)
     autotune = None
@@ -825,6 +846,8 @@ def main():
         "weighted": weighted,
         "autotune": autotune,
     }
+    if graph:
+        rec["graph_replay"] = graph
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(rows, n, nw, r, queries, args.cpu_seconds)
         # one thread, as the paper's single-threaded Java measurements
