@@ -5,8 +5,9 @@ comparison, an off-by-one, a dropped or transposed term, a missing mask, a
 wrong marker field, a missing format check.  It is built with gcc into a
 temporary library, and the pins of test_oracle_pins are run against it in a
 subprocess (oracle_battery.py): at least one pin must fail, crash or time
-out.  The unmodified source, built the same way, must pass them all.  CPU
-only; nothing here touches the library under test.
+out.  The unmodified source, built the same way, must pass them all, also
+when built with UBSan (undefined behaviour aborts).  CPU only; nothing here
+touches the library under test.
 """
 import os
 import subprocess
@@ -59,11 +60,14 @@ MUTANTS = [
 ]
 
 
-def _build(src_text, path):
+UBSAN = ["-g", "-fsanitize=undefined", "-fno-sanitize-recover=all"]
+
+
+def _build(src_text, path, extra=()):
     c = path + ".c"
     with open(c, "w") as fh:
         fh.write(src_text)
-    subprocess.run(["gcc", "-O2", "-std=c11", "-fopenmp", "-shared", "-fPIC", "-o", path, c], check=True)
+    subprocess.run(["gcc", "-O2", "-std=c11", "-fopenmp", "-shared", "-fPIC", *extra, "-o", path, c], check=True)
 
 
 def _battery(lib):
@@ -104,3 +108,19 @@ def test_mutant_is_caught(source, tmp_path, name, old, new, which):
     _build(mutated, lib)
     rc, out = _battery(lib)
     assert rc != 0, "no pin catches the planted mistake '%s'" % name
+
+
+def test_oracle_has_no_undefined_behaviour(source, tmp_path):
+    """The pins pass with the oracle built under UBSan (undefined behaviour
+    aborts the run); the same build of a copy whose tail mask shifts by 64
+    aborts, so the sanitizer is live."""
+    lib = str(tmp_path / "liboracle_ubsan.so")
+    _build(source, lib, UBSAN)
+    rc, out = _battery(lib)
+    assert rc == 0, out
+    bad = _mutate(source, "if (r_bits - first >= 64) return ~(uint64_t)0;",
+                  "if (r_bits - first > 64) return ~(uint64_t)0;", 0)
+    lib = str(tmp_path / "liboracle_ubsan_bad.so")
+    _build(bad, lib, UBSAN)
+    rc, out = _battery(lib)
+    assert rc != 0 and "runtime error" in out, out
