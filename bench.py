@@ -75,13 +75,14 @@ def load_traffic(kernel_key: str):
             rec = json.load(fh).get(kernel_key)
     except (OSError, ValueError):
         return None
-    if not rec or "source" not in rec:
+    if not rec or "sources" not in rec:
         return None
+    # every source the kernel is compiled from, in the listed order
     try:
-        with open(os.path.join(ROOT, rec["source"]), "rb") as fh:
-            h = hashlib.sha256(fh.read()).hexdigest()[:16]
+        blob = b"".join(open(os.path.join(ROOT, s), "rb").read() for s in rec["sources"])
     except OSError:
         return None
+    h = hashlib.sha256(blob).hexdigest()[:16]
     if rec.get("source_sha") != h:
         return None
     return rec.get("bytes_per_launch")

@@ -141,11 +141,17 @@ template <int K, int WPL, bool Guard, typename PtrArr>
 __device__ __forceinline__ void accumulate_pruned(Vec<WPL> (&P)[K], PtrArr ptrs, uint32_t n, uint64_t w,
                                                   uint64_t nwords, uint32_t theta) {
   uint32_t i = 0;
+  // A lane whose positions are all decided (count >= theta, or too low to
+  // reach theta with the inputs left) loads nothing more: adding nothing
+  // keeps every decided position's result, and its memory requests stop.
+  bool alive = true;
   while (i + kBlock <= n) {
-    Vec<WPL> x[kBlock];
+    if (alive) {
+      Vec<WPL> x[kBlock];
 #pragma unroll
-    for (int u = 0; u < kBlock; ++u) x[u] = load_cols<WPL, Guard>(ptrs[i + u], w, nwords);
-    add_block<K, WPL>(P, x);
+      for (int u = 0; u < kBlock; ++u) x[u] = load_cols<WPL, Guard>(ptrs[i + u], w, nwords);
+      add_block<K, WPL>(P, x);
+    }
     i += kBlock;
     if ((i % kPruneEvery) == 0 && i < n) {
       const uint32_t rem = n - i;
@@ -162,10 +168,11 @@ __device__ __forceinline__ void accumulate_pruned(Vec<WPL> (&P)[K], PtrArr ptrs,
         for (int q = 0; q < WPL; ++q) und |= ~hi.w[q];
       }
       if (Guard && w >= nwords) und = 0;
-      if (!__any(und != 0)) return;
+      alive = und != 0;
+      if (!__any(alive)) return;
     }
   }
-  if (i < n) {
+  if (i < n && alive) {
     Vec<WPL> x[kBlock];
 #pragma unroll
     for (int u = 0; u < kBlock; ++u) {

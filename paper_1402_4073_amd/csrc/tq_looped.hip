@@ -25,25 +25,33 @@ __device__ __forceinline__ void looped_accumulate(uint64_t (&B)[T], const uint64
                                                   uint32_t n, uint64_t w, uint64_t nwords, uint64_t valid,
                                                   bool prune) {
   uint32_t i = 0;
+  bool alive = true;   // this lane has positions that have not reached T
   for (; i < n; i += kLoopedBlock) {
-    uint64_t x[kLoopedBlock];
+    // a lane whose positions are all decided loads nothing more (its planes
+    // are saturated); the wave stops once no lane is left
+    if (alive) {
+      uint64_t x[kLoopedBlock];
 #pragma unroll
-    for (int u = 0; u < kLoopedBlock; ++u) {
-      uint64_t v = 0;
-      if (i + u < n && (!Guard || w < nwords)) {
-        v = __builtin_nontemporal_load(ptrs[i + u] + w);
-        if (Comp) v = ~v;
+      for (int u = 0; u < kLoopedBlock; ++u) {
+        uint64_t v = 0;
+        if (i + u < n && (!Guard || w < nwords)) {
+          v = __builtin_nontemporal_load(ptrs[i + u] + w);
+          if (Comp) v = ~v;
+        }
+        x[u] = v;
       }
-      x[u] = v;
-    }
 #pragma unroll
-    for (int u = 0; u < kLoopedBlock; ++u) {
+      for (int u = 0; u < kLoopedBlock; ++u) {
 #pragma unroll
-      for (int t = T - 1; t >= 1; --t) B[t] |= B[t - 1] & x[u];
-      B[0] |= x[u];
+        for (int t = T - 1; t >= 1; --t) B[t] |= B[t - 1] & x[u];
+        B[0] |= x[u];
+      }
     }
-    // positions outside the bitmap count as decided
-    if (prune && !__any((B[T - 1] | ~valid) != ~(uint64_t)0)) return;
+    if (prune) {
+      // positions outside the bitmap count as decided
+      alive = (B[T - 1] | ~valid) != ~(uint64_t)0;
+      if (!__any(alive)) return;
+    }
   }
 }
 
