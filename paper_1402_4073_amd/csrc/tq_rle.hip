@@ -44,7 +44,7 @@ constexpr int kTileThreads = 512;
 // in one pass
 constexpr int kOnePassColumns = kTile / 16;
 constexpr int kEncBlock = 256;
-constexpr int kEncPerThread = 4;
+constexpr int kEncPerThread = 8;
 constexpr int kEncWords = kEncBlock * kEncPerThread;
 
 __device__ __forceinline__ void set_status(int* status, int code) { atomicCAS(status, 0, code); }
@@ -626,33 +626,57 @@ __device__ __forceinline__ uint64_t enc_word(const EncArgs& a, uint64_t w) {
   return a.dense[w] & valid_mask_dev(w, a.nwords, a.tail_mask);
 }
 
-// packed contribution of word w: (is a marker start) << 32 | (is dirty)
-__device__ __forceinline__ uint64_t enc_contrib(const EncArgs& a, uint64_t w, int* kind_out) {
-  const int kc = word_kind(enc_word(a, w));
-  *kind_out = kc;
-  uint64_t start;
-  if (w == 0) {
-    start = 1;
-  } else if (kc == 2) {
-    start = 0;
+// The kEncPerThread consecutive words of a thread from `base` on, bits past r
+// cleared (words past the bitmap read as zero and contribute nothing), and
+// the packed contribution of each: (is a marker start) << 32 | (is dirty).
+// Every load, the word before `base` included, is issued before any is used.
+__device__ __forceinline__ void enc_span(const EncArgs& a, uint64_t base, uint64_t (&x)[kEncPerThread],
+                                         uint64_t (&c)[kEncPerThread]) {
+  const bool whole = base + kEncPerThread <= a.nwords;
+  uint64_t before = 0;   // the word before base (never the last word, so never masked)
+  if (whole) {
+    before = a.dense[base > 0 ? base - 1 : 0];
+#pragma unroll
+    for (int q = 0; q < kEncPerThread; ++q) x[q] = a.dense[base + q];
   } else {
-    const int kp = word_kind(enc_word(a, w - 1));
-    start = (kp == 2 || kp != kc) ? 1 : 0;
+    if (base > 0 && base <= a.nwords) before = a.dense[base - 1];
+#pragma unroll
+    for (int q = 0; q < kEncPerThread; ++q) x[q] = base + q < a.nwords ? a.dense[base + q] : 0;
   }
-  return (start << 32) | (kc == 2 ? 1u : 0u);
+#pragma unroll
+  for (int q = 0; q < kEncPerThread; ++q)
+    if (base + q == a.nwords - 1) x[q] &= a.tail_mask;
+  int kind[kEncPerThread];
+#pragma unroll
+  for (int q = 0; q < kEncPerThread; ++q) kind[q] = word_kind(x[q]);
+  int kp = word_kind(before);
+#pragma unroll
+  for (int q = 0; q < kEncPerThread; ++q) {
+    const int kc = kind[q];
+    const uint64_t start = (base + q == 0) ? 1 : (kc != 2 && (kp == 2 || kp != kc) ? 1 : 0);
+    c[q] = base + q < a.nwords ? (start << 32) | (kc == 2 ? 1u : 0u) : 0;
+    kp = kc;
+  }
 }
 
 __global__ __launch_bounds__(kEncBlock) void enc_reduce_kernel(EncArgs a) {
   __shared__ uint64_t wave_tot[kEncBlock / 64];
-  __shared__ uint64_t total;
   const uint64_t base = (uint64_t)blockIdx.x * kEncWords + (uint64_t)threadIdx.x * kEncPerThread;
+  uint64_t x[kEncPerThread], c[kEncPerThread];
+  enc_span(a, base, x, c);
   uint64_t s = 0;
-  int kind;
 #pragma unroll
-  for (int q = 0; q < kEncPerThread; ++q)
-    if (base + q < a.nwords) s += enc_contrib(a, base + q, &kind);
-  block_exclusive_scan<uint64_t, kEncBlock / 64>(s, wave_tot, &total);
-  if (threadIdx.x == 0) a.block_sums[blockIdx.x] = total;
+  for (int q = 0; q < kEncPerThread; ++q) s += c[q];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((threadIdx.x & 63) == 0) wave_tot[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t t = 0;
+#pragma unroll
+    for (int w = 0; w < kEncBlock / 64; ++w) t += wave_tot[w];
+    a.block_sums[blockIdx.x] = t;
+  }
 }
 
 // exclusive scan of the block sums (one workgroup), totals and output length
@@ -680,14 +704,11 @@ __global__ __launch_bounds__(kEncBlock) void enc_scatter_kernel(EncArgs a) {
   __shared__ uint64_t wave_tot[kEncBlock / 64];
   __shared__ uint64_t total;
   const uint64_t base = (uint64_t)blockIdx.x * kEncWords + (uint64_t)threadIdx.x * kEncPerThread;
-  uint64_t c[kEncPerThread];
-  int kinds[kEncPerThread];
+  uint64_t x[kEncPerThread], c[kEncPerThread];
+  enc_span(a, base, x, c);
   uint64_t s = 0;
 #pragma unroll
-  for (int q = 0; q < kEncPerThread; ++q) {
-    c[q] = base + q < a.nwords ? enc_contrib(a, base + q, &kinds[q]) : 0;
-    s += c[q];
-  }
+  for (int q = 0; q < kEncPerThread; ++q) s += c[q];
   uint64_t pre = block_exclusive_scan<uint64_t, kEncBlock / 64>(s, wave_tot, &total) + a.block_sums[blockIdx.x];
 #pragma unroll
   for (int q = 0; q < kEncPerThread; ++q) {
@@ -700,9 +721,9 @@ __global__ __launch_bounds__(kEncBlock) void enc_scatter_kernel(EncArgs a) {
       a.seg_d0[ms] = (uint32_t)ds;
     }
     if (w % kTile == 0) a.chk_marker[w / kTile] = (uint32_t)(ms + st - 1);
-    if (kinds[q] == 2) {
+    if (c[q] & 1) {
       const uint64_t pos = ms + ds + st;
-      if (pos < a.cap) a.out[pos] = enc_word(a, w);
+      if (pos < a.cap) a.out[pos] = x[q];
     }
     pre += c[q];
   }
@@ -973,7 +994,8 @@ hipError_t launch_rle_encode(const uint64_t* d_dense, uint64_t nwords, uint64_t 
   hipLaunchKernelGGL(enc_reduce_kernel, dim3((uint32_t)nblocks), dim3(kEncBlock), 0, stream, a);
   hipLaunchKernelGGL(enc_scan_kernel, dim3(1), dim3(1024), 0, stream, a, nblocks);
   hipLaunchKernelGGL(enc_scatter_kernel, dim3((uint32_t)nblocks), dim3(kEncBlock), 0, stream, a);
-  hipLaunchKernelGGL(enc_marker_kernel, dim3(grid_cap((nwords + 255) / 256, 65536)), dim3(256), 0, stream, a);
+  // markers are at most nwords; the grid strides over however many there are
+  hipLaunchKernelGGL(enc_marker_kernel, dim3(grid_cap((nwords + 255) / 256, 2048)), dim3(256), 0, stream, a);
   if (d_index)
     hipLaunchKernelGGL(enc_index_kernel, dim3(grid_cap((nchk + 255) / 256, 65536)), dim3(256), 0, stream, a,
                        nchk);

@@ -99,6 +99,29 @@ def test_encoder_matches_oracle(ctx, r):
         assert np.array_equal(idx, expected_index(want, r)), k
 
 
+@pytest.mark.parametrize("nw", [7, 8, 9, 2047, 2048, 2049, 4097])
+def test_encoder_run_boundaries(ctx, nw):
+    """Runs that change exactly where the encoder's per-thread (8-word) and
+    per-block (2048-word) spans change, and one word to either side: whether
+    a word starts a marker depends on the word before it, which then lies in
+    another thread or block.  Bitmaps of nw words and of nw words less five
+    bits (a masked tail word)."""
+    ones = np.uint64(0xFFFFFFFFFFFFFFFF)
+    for r in (nw * 64, nw * 64 - 5):
+        cases = []
+        for period in (8, 2048, 7, 9, 2047):
+            for kinds in ((0, 1), (1, 2), (2, 0), (0, 2, 1)):
+                w = np.arange(nw)
+                k = np.array(kinds)[(w // period) % len(kinds)]
+                x = np.where(k == 0, np.uint64(0), np.where(k == 1, ones, np.uint64(0x0123456789ABCDEF)))
+                cases.append(x.astype(np.uint64))
+        for k, dense in enumerate(cases):
+            got, idx = gpu_encode(ctx, dense, r)
+            want = oracle.rle_encode(dense, r)
+            assert np.array_equal(got, want), (r, k)
+            assert np.array_equal(idx, expected_index(want, r)), (r, k)
+
+
 def test_encoder_capacity(ctx):
     r = 64 * 100
     dense = markov_bitmaps(7, 1, r, 3.0, 5.0)[0]
