@@ -350,6 +350,23 @@ __device__ __forceinline__ void walk_literals(const RleDesc& dsc, Reader& rd, Wa
   }
 }
 
+// Dense inputs of a hybrid query at word col, handed to f in groups of
+// kDenseGroup whose loads are all in flight together (a load per input, each
+// waiting for the one before, would cost a memory round trip per input).
+// Past the last input f is handed zero words, which add nothing to a count.
+constexpr uint32_t kDenseGroup = 8;
+template <typename F>
+__device__ __forceinline__ void for_dense_words(const uint64_t* const* dense, uint32_t n_dense, uint64_t col,
+                                                F&& f) {
+  for (uint32_t i = 0; i < n_dense; i += kDenseGroup) {
+    uint64_t x[kDenseGroup];
+#pragma unroll
+    for (uint32_t u = 0; u < kDenseGroup; ++u) x[u] = i + u < n_dense ? dense[i + u][col] : 0;
+#pragma unroll
+    for (uint32_t u = 0; u < kDenseGroup; ++u) f(x[u]);
+  }
+}
+
 // One workgroup processes a contiguous range of tiles.  The lane that owns
 // input j < kTileThreads carries its stream position (and its reader) from
 // one tile to the next, so a range reads each of its streams once, front to
@@ -372,11 +389,17 @@ __device__ __forceinline__ void walk_literals(const RleDesc& dsc, Reader& rd, Wa
 // Fused = true: consumers of each result word (sink): AND with a filter, and a
 // count; each thread sums the popcounts of its words over the range, and each
 // wave writes one partial count per workgroup (blockIdx.x * 8 + wave).
-template <int K, bool Sym, bool Swar, int Form = kFullPlanes, bool Fused = false>
+//
+// Hybrid = true: n_dense uncompressed inputs are added column by column in
+// step 4 (their loads batched, see for_dense_words); the other builds ignore
+// n_dense and keep no registers for it.
+template <int K, bool Sym, bool Swar, int Form = kFullPlanes, bool Fused = false, bool Hybrid = false>
 __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu((Form != kFullPlanes && K <= 4) ? 8 : 6))) void rle_tile_kernel(
     const RleDesc* __restrict__ descs, uint32_t n_rle, const uint64_t* const* __restrict__ dense,
-    uint32_t n_dense, uint32_t nwords, uint64_t tail_mask, uint32_t theta, RleSym sym, uint32_t tiles_per_group,
+    uint32_t n_dense_arg, uint32_t nwords, uint64_t tail_mask, uint32_t theta, RleSym sym, uint32_t tiles_per_group,
     uint64_t* out, int* __restrict__ status, Sink sink) {
+  static_assert(!(Fused && Hybrid), "fused consumers take compressed inputs only");
+  const uint32_t n_dense = Hybrid ? n_dense_arg : 0;
   extern __shared__ uint64_t lds[];
   constexpr int kCounterWords = Swar ? 16 : K;
   uint64_t* planes = lds;                                         // kCounterWords x kTile
@@ -515,11 +538,11 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu((F
 #pragma unroll
         for (int q = 0; q < 16; ++q) C[q] = planes[q * kTile + c];
         const uint64_t col = (uint64_t)t0 + c;
-        for (uint32_t i = 0; i < n_dense; ++i) {
-          const uint64_t x = dense[i][col];
+        if constexpr (Hybrid)
+          for_dense_words(dense, n_dense, col, [&](uint64_t x) {
 #pragma unroll
-          for (int q = 0; q < 16; ++q) C[q] += (x >> q) & kSwarE;
-        }
+            for (int q = 0; q < 16; ++q) C[q] += (x >> q) & kSwarE;
+          });
         res = 0;
         if constexpr (!Sym) {
           // count >= theta - k per 16-bit field: bit 15 of count + 2^15 - (theta - k)
@@ -533,23 +556,23 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu((F
             res |= ((sym.f[tot >> 6] >> (tot & 63)) & 1) << p;
           }
         }
-      } else if (!Sym && n_dense == 0) {
+      } else if (!Sym && !Hybrid) {
         res = greater_than_lds<K>(planes, c, theta - (uint32_t)k - 1);
       } else {
         uint64_t P[K];
 #pragma unroll
         for (int q = 0; q < K; ++q) P[q] = planes[q * kTile + c];
         const uint64_t col = (uint64_t)t0 + c;
-        for (uint32_t i = 0; i < n_dense; ++i) {
-          uint64_t x = dense[i][col];
+        if constexpr (Hybrid)
+          for_dense_words(dense, n_dense, col, [&](uint64_t x) {
 #pragma unroll
-          for (int q = 0; q < (Sat ? K - 1 : K); ++q) {
-            const uint64_t t = P[q] & x;
-            P[q] ^= x;
-            x = t;
-          }
-          if constexpr (Sat) P[K - 1] |= x;
-        }
+            for (int q = 0; q < (Sat ? K - 1 : K); ++q) {
+              const uint64_t t = P[q] & x;
+              P[q] ^= x;
+              x = t;
+            }
+            if constexpr (Sat) P[K - 1] |= x;
+          });
         if constexpr (Par) {
           // bit 0 of the count: the ones fills' parity and the counted bits'
           res = P[0] ^ ((k & 1) ? ~(uint64_t)0 : 0);
@@ -817,41 +840,41 @@ uint32_t grid_cap(uint64_t want, uint32_t cap) {
 typedef void (*TileFn)(const RleDesc*, uint32_t, const uint64_t* const*, uint32_t, uint32_t, uint64_t,
                        uint32_t, RleSym, uint32_t, uint64_t*, int*, Sink);
 
-template <bool Sym, bool Fused>
+template <bool Sym, bool Fused, bool Hybrid>
 TileFn pick_tile_k(int K) {
   switch (K) {
-    case 4: return rle_tile_kernel<4, Sym, false, kFullPlanes, Fused>;
-    case 5: return rle_tile_kernel<5, Sym, false, kFullPlanes, Fused>;
-    case 6: return rle_tile_kernel<6, Sym, false, kFullPlanes, Fused>;
-    case 7: return rle_tile_kernel<7, Sym, false, kFullPlanes, Fused>;
-    case 8: return rle_tile_kernel<8, Sym, false, kFullPlanes, Fused>;
-    case 9: return rle_tile_kernel<9, Sym, false, kFullPlanes, Fused>;
-    case 10: return rle_tile_kernel<10, Sym, false, kFullPlanes, Fused>;
-    case 11: return rle_tile_kernel<11, Sym, false, kFullPlanes, Fused>;
-    case 12: return rle_tile_kernel<12, Sym, false, kFullPlanes, Fused>;
-    case 13: return rle_tile_kernel<13, Sym, false, kFullPlanes, Fused>;
-    case 16: return rle_tile_kernel<16, Sym, false, kFullPlanes, Fused>;
+    case 4: return rle_tile_kernel<4, Sym, false, kFullPlanes, Fused, Hybrid>;
+    case 5: return rle_tile_kernel<5, Sym, false, kFullPlanes, Fused, Hybrid>;
+    case 6: return rle_tile_kernel<6, Sym, false, kFullPlanes, Fused, Hybrid>;
+    case 7: return rle_tile_kernel<7, Sym, false, kFullPlanes, Fused, Hybrid>;
+    case 8: return rle_tile_kernel<8, Sym, false, kFullPlanes, Fused, Hybrid>;
+    case 9: return rle_tile_kernel<9, Sym, false, kFullPlanes, Fused, Hybrid>;
+    case 10: return rle_tile_kernel<10, Sym, false, kFullPlanes, Fused, Hybrid>;
+    case 11: return rle_tile_kernel<11, Sym, false, kFullPlanes, Fused, Hybrid>;
+    case 12: return rle_tile_kernel<12, Sym, false, kFullPlanes, Fused, Hybrid>;
+    case 13: return rle_tile_kernel<13, Sym, false, kFullPlanes, Fused, Hybrid>;
+    case 16: return rle_tile_kernel<16, Sym, false, kFullPlanes, Fused, Hybrid>;
   }
   return nullptr;
 }
 
 // thresholds with bit_length(theta) exact planes and a sticky one, or
 // symmetric functions with bit_length(tail_from) exact planes and a sticky one
-template <bool Sym, bool Fused>
+template <bool Sym, bool Fused, bool Hybrid>
 TileFn pick_sat_k(int K) {
   switch (K) {
-    case 2: return rle_tile_kernel<2, Sym, false, kSaturating, Fused>;
-    case 3: return rle_tile_kernel<3, Sym, false, kSaturating, Fused>;
-    case 4: return rle_tile_kernel<4, Sym, false, kSaturating, Fused>;
-    case 5: return rle_tile_kernel<5, Sym, false, kSaturating, Fused>;
-    case 6: return rle_tile_kernel<6, Sym, false, kSaturating, Fused>;
-    case 7: return rle_tile_kernel<7, Sym, false, kSaturating, Fused>;
-    case 8: return rle_tile_kernel<8, Sym, false, kSaturating, Fused>;
-    case 9: return rle_tile_kernel<9, Sym, false, kSaturating, Fused>;
-    case 10: return rle_tile_kernel<10, Sym, false, kSaturating, Fused>;
-    case 11: return rle_tile_kernel<11, Sym, false, kSaturating, Fused>;
-    case 12: return rle_tile_kernel<12, Sym, false, kSaturating, Fused>;
-    case 13: return rle_tile_kernel<13, Sym, false, kSaturating, Fused>;
+    case 2: return rle_tile_kernel<2, Sym, false, kSaturating, Fused, Hybrid>;
+    case 3: return rle_tile_kernel<3, Sym, false, kSaturating, Fused, Hybrid>;
+    case 4: return rle_tile_kernel<4, Sym, false, kSaturating, Fused, Hybrid>;
+    case 5: return rle_tile_kernel<5, Sym, false, kSaturating, Fused, Hybrid>;
+    case 6: return rle_tile_kernel<6, Sym, false, kSaturating, Fused, Hybrid>;
+    case 7: return rle_tile_kernel<7, Sym, false, kSaturating, Fused, Hybrid>;
+    case 8: return rle_tile_kernel<8, Sym, false, kSaturating, Fused, Hybrid>;
+    case 9: return rle_tile_kernel<9, Sym, false, kSaturating, Fused, Hybrid>;
+    case 10: return rle_tile_kernel<10, Sym, false, kSaturating, Fused, Hybrid>;
+    case 11: return rle_tile_kernel<11, Sym, false, kSaturating, Fused, Hybrid>;
+    case 12: return rle_tile_kernel<12, Sym, false, kSaturating, Fused, Hybrid>;
+    case 13: return rle_tile_kernel<13, Sym, false, kSaturating, Fused, Hybrid>;
   }
   return nullptr;
 }
@@ -864,16 +887,17 @@ struct TileChoice {
   int key = 0;
 };
 
-template <bool Fused>
+template <bool Fused, bool Hybrid>
 TileChoice choose_tile(int K, uint32_t theta, const RleSym* sym, bool swar) {
   TileChoice c;
   c.K = K;
   if (swar) {
-    c.fn = sym ? rle_tile_kernel<16, true, true, kFullPlanes, Fused> : rle_tile_kernel<16, false, true, kFullPlanes, Fused>;
+    c.fn = sym ? rle_tile_kernel<16, true, true, kFullPlanes, Fused, Hybrid>
+               : rle_tile_kernel<16, false, true, kFullPlanes, Fused, Hybrid>;
     c.key = 34 + (sym ? 1 : 0);
     return c;
   }
-  c.fn = sym ? pick_tile_k<true, Fused>(K) : pick_tile_k<false, Fused>(K);
+  c.fn = sym ? pick_tile_k<true, Fused, Hybrid>(K) : pick_tile_k<false, Fused, Hybrid>(K);
   c.key = K + (sym ? 17 : 0);
   // A threshold compares each column's count with theta - k <= theta, so
   // bit_length(theta) exact planes and a sticky one decide it: less LDS per
@@ -882,7 +906,7 @@ TileChoice choose_tile(int K, uint32_t theta, const RleSym* sym, bool swar) {
     const int ks = bit_length(theta) + 1;
     if (ks < K && ks <= 13) {
       c.K = ks;
-      c.fn = pick_sat_k<false, Fused>(ks);
+      c.fn = pick_sat_k<false, Fused, Hybrid>(ks);
       c.key = 36 + ks;
     }
   }
@@ -892,14 +916,14 @@ TileChoice choose_tile(int K, uint32_t theta, const RleSym* sym, bool swar) {
     const int ks = bit_length(sym->tail_from) + 1;
     if (ks < K && ks <= 13) {
       c.K = ks;
-      c.fn = pick_sat_k<true, Fused>(ks);
+      c.fn = pick_sat_k<true, Fused, Hybrid>(ks);
       c.key = 51 + ks;
     }
   }
   // the parity function (or its complement) needs the count modulo 2 only
   if (sym && sym->epi.kind == EPI_PARITY) {
     c.K = 1;
-    c.fn = rle_tile_kernel<1, true, false, kParityPlane, Fused>;
+    c.fn = rle_tile_kernel<1, true, false, kParityPlane, Fused, Hybrid>;
     c.key = 50;
   }
   return c;
@@ -917,11 +941,16 @@ hipError_t launch_rle_tile(const RleDesc* d_descs, uint32_t n_rle, const uint64_
                            uint64_t* d_out, int* d_status, hipStream_t stream, const Sink& sink,
                            uint64_t* slots_used) {
   const bool fused = sink.filter != nullptr || sink.partial64 != nullptr;
+  const bool hybrid = n_dense > 0;
+  if (fused && hybrid) return hipErrorInvalidValue;   // no such build
   const int K0 = dense_planes_for(n_rle + n_dense);
-  const TileChoice ch = fused ? choose_tile<true>(K0, theta, sym, swar) : choose_tile<false>(K0, theta, sym, swar);
+  const TileChoice ch = fused    ? choose_tile<true, false>(K0, theta, sym, swar)
+                        : hybrid ? choose_tile<false, true>(K0, theta, sym, swar)
+                                 : choose_tile<false, false>(K0, theta, sym, swar);
   TileFn fn = ch.fn;
   const int K = ch.K;
-  const int slot = ch.key + (fused ? 65 : 0);
+  // keys are below 65; fused and hybrid builds get their own ranges
+  const int slot = ch.key + (fused ? 65 : 0) + (hybrid ? 130 : 0);
   if (!fn) return hipErrorInvalidValue;
   const uint64_t tiles = (nwords + kTile - 1) / kTile;
   if (tiles == 0) return hipSuccess;
@@ -929,7 +958,7 @@ hipError_t launch_rle_tile(const RleDesc* d_descs, uint32_t n_rle, const uint64_
   // LDS limit and resident workgroups per CU, set and measured once per device
   constexpr int kMaxDevices = 64;
   static std::mutex mu;
-  static int resident[kMaxDevices][130] = {};
+  static int resident[kMaxDevices][195] = {};
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
