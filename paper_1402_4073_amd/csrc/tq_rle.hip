@@ -382,9 +382,11 @@ __device__ __forceinline__ void for_dense_words(const uint64_t* const* dense, ui
 // K = bit_length(theta) + 1 planes suffice for a threshold, and
 // bit_length(tail_from) + 1 for a symmetric f constant from tail_from on;
 // kParityPlane (the parity function and its complement) keeps one plane, the
-// count modulo 2.  With K <= 4 planes the kernel is built for 8 waves per SIMD, which its
-// small LDS footprint allows, at the cost of a few spilled registers
-// (measured: faster there, slower for larger K).
+// count modulo 2.  With K <= 4 planes (K <= 7 for plain thresholds) the
+// kernel is built for 8 waves per SIMD, which its LDS footprint allows, at
+// the cost of about 13 spilled registers, reloaded once per tile (measured:
+// faster there, where literal words are counted; level or slower for larger
+// K, where the fills decide most columns).
 //
 // Fused = true: consumers of each result word (sink): AND with a filter, and a
 // count; each thread sums the popcounts of its words over the range, and each
@@ -394,7 +396,8 @@ __device__ __forceinline__ void for_dense_words(const uint64_t* const* dense, ui
 // step 4 (their loads batched, see for_dense_words); the other builds ignore
 // n_dense and keep no registers for it.
 template <int K, bool Sym, bool Swar, int Form = kFullPlanes, bool Fused = false, bool Hybrid = false>
-__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu((Form != kFullPlanes && K <= 4) ? 8 : 6))) void rle_tile_kernel(
+__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(
+    ((Form != kFullPlanes && K <= 4) || (!Sym && !Swar && !Fused && !Hybrid && K <= 7)) ? 8 : 6))) void rle_tile_kernel(
     const RleDesc* __restrict__ descs, uint32_t n_rle, const uint64_t* const* __restrict__ dense,
     uint32_t n_dense_arg, uint32_t nwords, uint64_t tail_mask, uint32_t theta, RleSym sym, uint32_t tiles_per_group,
     uint64_t* out, int* __restrict__ status, Sink sink) {
