@@ -142,7 +142,9 @@ struct RleSym {
 };
 
 size_t rle_tile_lds_bytes(int K, bool swar);
-// sym == nullptr: threshold theta; otherwise the symmetric function *sym.
+// sym == nullptr: threshold theta; otherwise the symmetric function *sym
+// (host copy, which picks the kernel), d_sym its copy in device memory (which
+// the kernel reads).
 // swar: SWAR column counters (every tile in one pass) instead of bit planes.
 // sink (filter and/or partial64 set): consumers of each result word (AND
 // filter; popcounts into sink.partial64, one slot per wave of each
@@ -150,9 +152,9 @@ size_t rle_tile_lds_bytes(int K, bool swar);
 // then be null.
 hipError_t launch_rle_tile(const RleDesc* d_descs, uint32_t n_rle, const uint64_t* const* d_dense,
                            uint32_t n_dense, uint64_t nwords, uint64_t tail_mask, uint32_t theta,
-                           const RleSym* sym, bool swar, int num_cus, uint32_t tiles_per_group,
-                           uint64_t* d_out, int* d_status, hipStream_t stream, const Sink& sink = Sink(),
-                           uint64_t* slots_used = nullptr);
+                           const RleSym* sym, const RleSym* d_sym, bool swar, int num_cus,
+                           uint32_t tiles_per_group, uint64_t* d_out, int* d_status, hipStream_t stream,
+                           const Sink& sink = Sink(), uint64_t* slots_used = nullptr);
 uint64_t rle_tile_partials(uint64_t nwords);
 size_t rle_encode_workspace_bytes(uint64_t nwords);
 hipError_t launch_rle_encode(const uint64_t* d_dense, uint64_t nwords, uint64_t tail_mask, uint64_t* d_out,

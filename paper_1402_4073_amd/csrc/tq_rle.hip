@@ -382,11 +382,12 @@ __device__ __forceinline__ void for_dense_words(const uint64_t* const* dense, ui
 // K = bit_length(theta) + 1 planes suffice for a threshold, and
 // bit_length(tail_from) + 1 for a symmetric f constant from tail_from on;
 // kParityPlane (the parity function and its complement) keeps one plane, the
-// count modulo 2.  With K <= 4 planes (K <= 7 for plain thresholds) the
-// kernel is built for 8 waves per SIMD, which its LDS footprint allows, at
-// the cost of about 13 spilled registers, reloaded once per tile (measured:
-// faster there, where literal words are counted; level or slower for larger
-// K, where the fills decide most columns).
+// count modulo 2.  With K <= 4 planes (K <= 7 for plain thresholds, K <= 5
+// for symmetric functions) the kernel is built for 8 waves per SIMD, which
+// its LDS footprint allows, at the cost of 13 to 16 spilled registers,
+// reloaded once per tile (measured: faster there, where literal words are
+// counted; level or slower for larger K, where the fills decide most columns
+// or the spills grow).
 //
 // Fused = true: consumers of each result word (sink): AND with a filter, and a
 // count; each thread sums the popcounts of its words over the range, and each
@@ -397,9 +398,10 @@ __device__ __forceinline__ void for_dense_words(const uint64_t* const* dense, ui
 // n_dense and keep no registers for it.
 template <int K, bool Sym, bool Swar, int Form = kFullPlanes, bool Fused = false, bool Hybrid = false>
 __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(
-    ((Form != kFullPlanes && K <= 4) || (!Sym && !Swar && !Fused && !Hybrid && K <= 7)) ? 8 : 6))) void rle_tile_kernel(
+    ((Form != kFullPlanes && K <= 4) || (!Swar && !Fused && !Hybrid && K <= (Sym ? 5 : 7))) ? 8 : 6))) void rle_tile_kernel(
     const RleDesc* __restrict__ descs, uint32_t n_rle, const uint64_t* const* __restrict__ dense,
-    uint32_t n_dense_arg, uint32_t nwords, uint64_t tail_mask, uint32_t theta, RleSym sym, uint32_t tiles_per_group,
+    uint32_t n_dense_arg, uint32_t nwords, uint64_t tail_mask, uint32_t theta, const RleSym* __restrict__ sym,
+    uint32_t tiles_per_group,
     uint64_t* out, int* __restrict__ status, Sink sink) {
   static_assert(!(Fused && Hybrid), "fused consumers take compressed inputs only");
   const uint32_t n_dense = Hybrid ? n_dense_arg : 0;
@@ -493,7 +495,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(
         int k, d;
         unpack_kd(ex + v, k, d);
         if constexpr (Sym) {
-          und = (uint32_t)(k + d) + n_dense > sym.run_end[k];
+          und = (uint32_t)(k + d) + n_dense > sym->run_end[k];
         } else {
           const int tp = (int)theta - k;
           und = tp >= 1 && tp <= d + (int)n_dense;
@@ -532,7 +534,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(
         // decided by the fills: f(k), resp. k >= theta
         bool one;
         if constexpr (Sym)
-          one = (sym.f[k >> 6] >> (k & 63)) & 1;
+          one = (sym->f[k >> 6] >> (k & 63)) & 1;
         else
           one = k >= (int)theta;
         res = one ? ~(uint64_t)0 : 0;
@@ -556,7 +558,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
           for (int p = 0; p < 64; ++p) {
             const uint32_t tot = (uint32_t)k + (uint32_t)((C[p & 15] >> (16 * (p >> 4))) & 0xFFFF);
-            res |= ((sym.f[tot >> 6] >> (tot & 63)) & 1) << p;
+            res |= ((sym->f[tot >> 6] >> (tot & 63)) & 1) << p;
           }
         }
       } else if (!Sym && !Hybrid) {
@@ -579,7 +581,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(
         if constexpr (Par) {
           // bit 0 of the count: the ones fills' parity and the counted bits'
           res = P[0] ^ ((k & 1) ? ~(uint64_t)0 : 0);
-          if (sym.epi.invert) res = ~res;
+          if (sym->epi.invert) res = ~res;
         } else if constexpr (Sym && Sat) {
           // An undecided column has k < tail_from, so with the sticky plane
           // clear the count k + (exact planes) is below 2^K and exact; a set
@@ -591,15 +593,15 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(
           csa::Vec<1> V[K];
 #pragma unroll
           for (int q = 0; q < K; ++q) V[q].w[0] = P[q];
-          res = csa::epilogue<K, 1>(V, sym.epi, n_rle + n_dense, sym.epi.table).w[0];
-          res = (res & ~sticky) | (sym.tail_value ? sticky : 0);
+          res = csa::epilogue<K, 1>(V, sym->epi, n_rle + n_dense, sym->epi.table).w[0];
+          res = (res & ~sticky) | (sym->tail_value ? sticky : 0);
         } else if constexpr (Sym) {
           // the full count of the column: its ones fills plus the counted bits
           add_constant<K>(P, (uint32_t)k);
           csa::Vec<1> V[K];
 #pragma unroll
           for (int q = 0; q < K; ++q) V[q].w[0] = P[q];
-          res = csa::epilogue<K, 1>(V, sym.epi, n_rle + n_dense, sym.epi.table).w[0];
+          res = csa::epilogue<K, 1>(V, sym->epi, n_rle + n_dense, sym->epi.table).w[0];
         } else {
           res = greater_than_lane<K>(P, theta - (uint32_t)k - 1);
         }
@@ -841,7 +843,7 @@ uint32_t grid_cap(uint64_t want, uint32_t cap) {
 }
 
 typedef void (*TileFn)(const RleDesc*, uint32_t, const uint64_t* const*, uint32_t, uint32_t, uint64_t,
-                       uint32_t, RleSym, uint32_t, uint64_t*, int*, Sink);
+                       uint32_t, const RleSym*, uint32_t, uint64_t*, int*, Sink);
 
 template <bool Sym, bool Fused, bool Hybrid>
 TileFn pick_tile_k(int K) {
@@ -940,9 +942,10 @@ size_t rle_tile_lds_bytes(int K, bool swar) {
 
 hipError_t launch_rle_tile(const RleDesc* d_descs, uint32_t n_rle, const uint64_t* const* d_dense,
                            uint32_t n_dense, uint64_t nwords, uint64_t tail_mask, uint32_t theta,
-                           const RleSym* sym, bool swar, int num_cus, uint32_t tiles_per_group,
-                           uint64_t* d_out, int* d_status, hipStream_t stream, const Sink& sink,
-                           uint64_t* slots_used) {
+                           const RleSym* sym, const RleSym* d_sym, bool swar, int num_cus,
+                           uint32_t tiles_per_group, uint64_t* d_out, int* d_status, hipStream_t stream,
+                           const Sink& sink, uint64_t* slots_used) {
+  if (sym && !d_sym) return hipErrorInvalidValue;
   const bool fused = sink.filter != nullptr || sink.partial64 != nullptr;
   const bool hybrid = n_dense > 0;
   if (fused && hybrid) return hipErrorInvalidValue;   // no such build
@@ -986,7 +989,7 @@ hipError_t launch_rle_tile(const RleDesc* d_descs, uint32_t n_rle, const uint64_
   const uint64_t ranges = (tiles + per_group - 1) / per_group;
   const uint64_t grid = (ranges + kXcds - 1) / kXcds * kXcds;
   hipLaunchKernelGGL(fn, dim3((uint32_t)grid), dim3(kTileThreads), lds, stream, d_descs, n_rle, d_dense,
-                     n_dense, (uint32_t)nwords, tail_mask, theta, sym ? *sym : RleSym{}, (uint32_t)per_group,
+                     n_dense, (uint32_t)nwords, tail_mask, theta, d_sym, (uint32_t)per_group,
                      d_out, d_status, sink);
   if (slots_used) *slots_used = grid * (kTileThreads / 64);
   return hipGetLastError();

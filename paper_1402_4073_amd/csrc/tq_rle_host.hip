@@ -96,7 +96,8 @@ struct RleFn {
 // Device tables of a symmetric function for the tile kernel (cached blobs).
 struct SymTables {
   RleSym sym{};
-  Blob* blobs[3] = {nullptr, nullptr, nullptr};
+  const RleSym* d_sym = nullptr;   // sym itself in device memory, for the kernel
+  Blob* blobs[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 
 tq_status sym_tables(tq_ctx* ctx, uint32_t n, const uint64_t* truth, const SymPlan& plan, hipStream_t stream,
@@ -130,6 +131,15 @@ tq_status sym_tables(tq_ctx* ctx, uint32_t n, const uint64_t* truth, const SymPl
     if (!d_t) return staging_error(ctx, TQ_EDEVICE);
     t->sym.epi.table = static_cast<const uint32_t*>(d_t);
   }
+  // The kernel reads the plan from memory: passed by value it would take
+  // some 30 scalar registers for the whole launch.  Every field is set and
+  // the struct has no padding, so equal plans stage equal bytes.
+  static_assert(sizeof(RleSym) % 8 == 0, "staged as whole words");
+  uint64_t words[sizeof(RleSym) / 8];
+  memcpy(words, &t->sym, sizeof(RleSym));
+  const void* d_s = blob_get(ctx, words, sizeof(RleSym) / 8, stream, &t->blobs[3]);
+  if (!d_s) return staging_error(ctx, TQ_EDEVICE);
+  t->d_sym = static_cast<const RleSym*>(d_s);
   return TQ_OK;
 }
 
@@ -243,7 +253,8 @@ tq_status run_rle_tiles(tq_ctx* ctx, const tq_rle* inputs, uint32_t n_rle, const
   auto launch = [&](const RleShape& sh) {
     return launch_rle_tile(reinterpret_cast<const RleDesc*>(d_desc), n_rle,
                            reinterpret_cast<const uint64_t* const*>(d_dense), n_dense, nw, tmask, qf.theta,
-                           qf.truth ? &tabs.sym : nullptr, sh.swar, ctx->num_cus, sh.tiles, d_dense_out,
+                           qf.truth ? &tabs.sym : nullptr, qf.truth ? tabs.d_sym : nullptr, sh.swar,
+                           ctx->num_cus, sh.tiles, d_dense_out,
                            ctx->d_status, stream, sink, slots_used);
   };
   st = record_hip(ctx, launch(rle_shape(ctx, n, nw, qf, plan, launch, stream)));
