@@ -466,7 +466,13 @@ tq_status tq_bitmap_stats(tq_ctx* ctx, const uint64_t* d_dense, uint64_t r_bits,
 tq_status tq_query_features(const tq_bitmap* inputs, uint32_t n, uint64_t r_bits, uint32_t theta, float* out);
 
 /* Threshold query run by the given variant (dense output, semantics of
- * tq_threshold).  TQ_EINVAL if an input lacks the form the variant reads. */
+ * tq_threshold).  TQ_EINVAL if an input lacks the form the variant reads.
+ * With pruning on (TQ_OPTION_PRUNE), TQ_VARIANT_CSA reads the inputs in order
+ * of their registered cardinality: densest first when theta is below half
+ * the expected count (sum of ones / r_bits), so that positions reach theta
+ * sooner, else sparsest first, so that they are written off sooner (section
+ * 1, lower bound and skipping).  The result does not depend on the order or
+ * on the registered values. */
 tq_status tq_threshold_variant(tq_ctx* ctx, const tq_bitmap* inputs, uint32_t n, uint64_t r_bits,
                                uint32_t theta, uint32_t variant, uint64_t* d_out, hipStream_t stream);
 

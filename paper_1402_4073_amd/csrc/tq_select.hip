@@ -161,9 +161,28 @@ tq_status tq_threshold_variant(tq_ctx* ctx, const tq_bitmap* inputs, uint32_t n,
   std::vector<const uint64_t*> dense;
   std::vector<tq_rle> rle;
   switch (variant) {
-    case TQ_VARIANT_CSA:
-      for (uint32_t j = 0; j < n; ++j) dense.push_back(inputs[j].dense);
+    case TQ_VARIANT_CSA: {
+      // Inputs in order of registered cardinality (the lower-bound skipping
+      // of section 1, with pruning on): a lane stops reading once each of its
+      // positions has reached theta, which dense inputs read first bring
+      // about sooner, or can no longer reach it with the inputs left, which
+      // sparse inputs read first bring about sooner (the count stays low
+      // while the inputs left run out).  Dense first when theta is below half
+      // the expected count, else sparse first; equal cardinalities keep the
+      // caller's order.  The result does not depend on the order.
+      std::vector<uint32_t> order(n);
+      for (uint32_t j = 0; j < n; ++j) order[j] = j;
+      if (ctx->prune && r_bits > 0) {
+        double total = 0;
+        for (uint32_t j = 0; j < n; ++j) total += (double)inputs[j].ones;
+        const bool dense_first = 2.0 * (double)theta < total / (double)r_bits;
+        std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+          return dense_first ? inputs[a].ones > inputs[b].ones : inputs[a].ones < inputs[b].ones;
+        });
+      }
+      for (uint32_t j = 0; j < n; ++j) dense.push_back(inputs[order[j]].dense);
       return tq_threshold(ctx, dense.data(), n, r_bits, theta, d_out, stream);
+    }
     case TQ_VARIANT_COUNTER: {
       for (uint32_t j = 0; j < n; ++j) dense.push_back(inputs[j].dense);
       if (n > TQ_MAX_INPUTS || !d_out || ((uintptr_t)d_out & 7)) return TQ_EINVAL;

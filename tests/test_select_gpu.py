@@ -64,6 +64,30 @@ def test_variants_match_oracle(ctx, n, ones, zeros):
             assert np.array_equal(to_host(out), want), (theta, tq.VARIANT_NAMES[v])
 
 
+def test_csa_reads_inputs_by_cardinality(ctx):
+    """The CSA variant reads its inputs in order of registered cardinality
+    (densest first below half the expected count, sparsest first above),
+    with pruning on and off; the result is the oracle's whether the
+    registered cardinalities are true, reversed or all equal."""
+    n, r = 48, 64 * 2000 + 5
+    bs = tqgen.bernoulli_loguniform(31, n, r, 1e-3, 0.5)
+    dense = [bs.words(j) for j in range(n)]
+    bms, keep = registered(ctx, dense, r, with_rle=False)
+    true_ones = [b["ones"] for b in bms]
+    mean = sum(true_ones) / r
+    thetas = sorted({1, 2, 3, max(1, int(mean / 4)), int(mean), 2 * int(mean) + 1, n - 2, n - 1, n})
+    for label, ones in (("true", true_ones), ("reversed", true_ones[::-1]), ("equal", [7] * n)):
+        arr = (tq.bitmap_array([dict(b, ones=o) for b, o in zip(bms, ones)]), n)
+        for prune in (1, 0):
+            tq.tq_set_option(ctx, tq.TQ_OPTION_PRUNE, prune)
+            for theta in thetas:
+                out = empty_words((r + 63) // 64)
+                tq.tq_threshold_variant(ctx, arr, r, theta, tq.TQ_VARIANT_CSA, out)
+                assert tq.tq_ctx_check(ctx) == 0
+                assert np.array_equal(to_host(out), oracle.threshold(dense, r, theta)), (label, prune, theta)
+    tq.tq_set_option(ctx, tq.TQ_OPTION_PRUNE, 1)
+
+
 def test_variant_needs_its_form(ctx):
     r = 64 * 100
     dense = [tqgen.markov_fixed(1, 1, r, 5.0, 50.0).words(0)]
