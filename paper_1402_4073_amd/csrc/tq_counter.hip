@@ -78,29 +78,61 @@ __global__ __launch_bounds__(256) void counter_kernel(const uint64_t* const* __r
 }
 
 // ones and runs of one bitmap: runs = 1 + number of positions p in [1, r)
-// where bit p differs from bit p-1
-__global__ void stats_kernel(const uint64_t* __restrict__ d, uint64_t nwords, uint64_t tail_mask,
-                             uint64_t r_bits, unsigned long long* __restrict__ ones,
-                             unsigned long long* __restrict__ changes) {
+// where bit p differs from bit p-1.  Each workgroup adds its two sums with
+// one atomic each: atomics on one address are served one at a time, so the
+// grid is kept to at most kStatsMaxBlocks workgroups, and a thread loads its
+// kStatsWordsPerThread words of a chunk (and the word before each) before
+// using any.
+constexpr int kStatsBlock = 256;
+constexpr uint64_t kStatsWordsPerThread = 8;
+constexpr uint64_t kStatsMaxBlocks = 1024;
+__global__ __launch_bounds__(kStatsBlock) void stats_kernel(const uint64_t* __restrict__ d, uint64_t nwords,
+                                                            uint64_t tail_mask, uint64_t r_bits,
+                                                            unsigned long long* __restrict__ ones,
+                                                            unsigned long long* __restrict__ changes) {
+  __shared__ unsigned long long s_sum[2][kStatsBlock / 64];
   unsigned long long so = 0, sc = 0;
-  for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nwords;
-       w += (uint64_t)gridDim.x * blockDim.x) {
-    const uint64_t m = (w == nwords - 1) ? tail_mask : ~(uint64_t)0;
-    const uint64_t x = d[w] & m;
-    so += __popcll(x);
-    // bit p vs bit p-1 inside the word, and the first bit vs the previous word's last
-    const uint64_t prev_last = w ? (d[w - 1] >> 63) : (x & 1);
-    const uint64_t shifted = (x << 1) | prev_last;
-    sc += __popcll((x ^ shifted) & m);
+  const uint64_t chunk = (uint64_t)kStatsBlock * kStatsWordsPerThread;
+  for (uint64_t base = (uint64_t)blockIdx.x * chunk; base < nwords; base += (uint64_t)gridDim.x * chunk) {
+    uint64_t x[kStatsWordsPerThread], before[kStatsWordsPerThread];
+#pragma unroll
+    for (uint64_t k = 0; k < kStatsWordsPerThread; ++k) {
+      const uint64_t w = base + threadIdx.x + k * kStatsBlock;
+      x[k] = w < nwords ? d[w] : 0;
+      before[k] = (w < nwords && w > 0) ? d[w - 1] : 0;   // never the tail word
+    }
+#pragma unroll
+    for (uint64_t k = 0; k < kStatsWordsPerThread; ++k) {
+      const uint64_t w = base + threadIdx.x + k * kStatsBlock;
+      if (w >= nwords) continue;
+      const uint64_t m = (w == nwords - 1) ? tail_mask : ~(uint64_t)0;
+      const uint64_t xv = x[k] & m;
+      so += __popcll(xv);
+      // bit p vs bit p-1 inside the word, and the first bit vs the previous word's last
+      const uint64_t prev_last = w ? (before[k] >> 63) : (xv & 1);
+      const uint64_t shifted = (xv << 1) | prev_last;
+      sc += __popcll((xv ^ shifted) & m);
+    }
   }
-  // wave reduction then one atomic per wave
+  // wave reduction, then the workgroup's sums, then one atomic per sum
   for (int off = 32; off > 0; off >>= 1) {
     so += __shfl_down(so, off, 64);
     sc += __shfl_down(sc, off, 64);
   }
   if ((threadIdx.x & 63) == 0) {
-    atomicAdd(ones, so);
-    atomicAdd(changes, sc);
+    s_sum[0][threadIdx.x >> 6] = so;
+    s_sum[1][threadIdx.x >> 6] = sc;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long to = 0, tc = 0;
+#pragma unroll
+    for (int w = 0; w < kStatsBlock / 64; ++w) {
+      to += s_sum[0][w];
+      tc += s_sum[1][w];
+    }
+    atomicAdd(ones, to);
+    atomicAdd(changes, tc);
   }
 }
 
@@ -140,9 +172,10 @@ hipError_t launch_stats(const uint64_t* d_dense, uint64_t r_bits, uint64_t* d_on
   unsigned long long* c = reinterpret_cast<unsigned long long*>(d_runs);
   hipLaunchKernelGGL(zero2_kernel, dim3(1), dim3(1), 0, stream, o, c);
   if (nw) {
-    uint64_t blocks = (nw + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(stats_kernel, dim3((uint32_t)blocks), dim3(256), 0, stream, d_dense, nw,
+    const uint64_t per_block = kStatsBlock * kStatsWordsPerThread;
+    uint64_t blocks = (nw + per_block - 1) / per_block;
+    if (blocks > kStatsMaxBlocks) blocks = kStatsMaxBlocks;
+    hipLaunchKernelGGL(stats_kernel, dim3((uint32_t)blocks), dim3(kStatsBlock), 0, stream, d_dense, nw,
                        tail_mask_for(r_bits), r_bits, o, c);
   }
   hipLaunchKernelGGL(stats_finish_kernel, dim3(1), dim3(1), 0, stream, c, r_bits);

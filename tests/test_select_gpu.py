@@ -38,7 +38,19 @@ def registered(ctx, dense_list, r, with_dense=True, with_rle=True):
 
 
 def test_bitmap_stats(ctx):
-    for r in (1, 63, 64 * 100 + 7, 1 << 16):
+    """Cardinality and run count equal the oracle's: tiny and ragged bitmaps,
+    several 2048-word chunks with a partial last one, and more chunks than
+    workgroups (the grid strides)."""
+    big = 64 * (2048 * 1024 + 2048 * 2 + 9) + 33
+    for r in (big,):
+        bs = tqgen.bernoulli_loguniform(r % 1000, 2, r, 1e-3, 0.5)
+        dense = [bs.words(j) for j in range(2)]
+        bms, keep = registered(ctx, dense, r, with_rle=False)
+        for j, b in enumerate(bms):
+            bits = np.unpackbits(dense[j].view(np.uint8), bitorder="little")[:r]
+            assert b["ones"] == int(bits.sum())
+            assert b["runs"] == oracle.run_count(dense[j], r)
+    for r in (1, 63, 64 * 100 + 7, 1 << 16, 64 * 2048 * 3 + 64 * 5 + 17):
         ms = tqgen.markov_fixed(r, 3, r, 5.0, 40.0)
         dense = [ms.words(j) for j in range(3)]
         bms, keep = registered(ctx, dense, r)
