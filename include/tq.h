@@ -81,11 +81,11 @@ tq_status tq_destroy(tq_ctx* ctx);
 const char* tq_status_string(int status);
 
 /* Context options. */
-#define TQ_OPTION_PRUNE 1  /* value 1 (default): threshold queries stop reading inputs once every
-                              position of a 64-word column group is decided, i.e. its count already
-                              reaches theta or cannot reach it with the remaining inputs (the skipping
-                              argument of section 1, "Lower Bound").  Results are identical either
-                              way; 0 reads every input word. */
+#define TQ_OPTION_PRUNE 1  /* value 1 (default): threshold queries, plain and weighted, stop reading
+                              inputs for a word once each of its positions is decided, i.e. its
+                              (weighted) count already reaches theta or cannot reach it with the
+                              remaining inputs (the skipping argument of section 1, "Lower Bound").
+                              Results are identical either way; 0 reads every input word. */
 #define TQ_OPTION_RLE_TILES 2  /* tiles of TQ_RLE_INDEX_STRIDE words that one workgroup of a query over
                                   RLE inputs walks in a row, each input read front to back across
                                   them; 0 (default) picks one range per resident workgroup.  Any value
@@ -175,7 +175,9 @@ tq_status tq_symmetric(tq_ctx* ctx, const uint64_t* const* ptrs, uint32_t n, uin
  * Weighted threshold query (section 2.3: inputs may carry positive integer
  * weights, there realised by replicating input j weights[j] times):
  *   d_out bit p = [ sum_j weights[j] * bit p of ptrs[j] >= theta ]  for p < r_bits.
- * Each input is read once whatever its weight.  h_weights: HOST array of n
+ * Each input is read at most once whatever its weight (heaviest first; with
+ * TQ_OPTION_PRUNE a word stops being read once each of its positions is
+ * decided).  h_weights: HOST array of n
  * uint32 weights (0 allowed: the input is ignored); their sum must not exceed
  * 2^32 - 1 (else TQ_EINVAL).  theta == 0 gives all ones on [0, r_bits), theta
  * above the sum gives zeros.  Other arguments and errors as for tq_threshold.

@@ -534,20 +534,25 @@ tq_status tq_threshold_weighted(tq_ctx* ctx, const uint64_t* const* ptrs, uint32
   if (nw == 0) return TQ_OK;
   if (theta == 0 || theta > total)
     return record_hip(ctx, launch_fill(d_out, nw, theta == 0 ? ~(uint64_t)0 : 0, tmask, stream));
-  // group the inputs of equal weight (weight 0 contributes nothing)
+  // group the inputs of equal weight (weight 0 contributes nothing), heaviest
+  // first; with pruning, classes of at most kPruneClass inputs, after each of
+  // which the kernel checks whether a lane's positions are all decided
+  constexpr uint32_t kPruneClass = 64;
   std::vector<uint32_t> order;
   order.reserve(n);
   for (uint32_t j = 0; j < n; ++j)
     if (h_weights[j]) order.push_back(j);
   std::stable_sort(order.begin(), order.end(),
-                   [&](uint32_t a, uint32_t b) { return h_weights[a] < h_weights[b]; });
+                   [&](uint32_t a, uint32_t b) { return h_weights[a] > h_weights[b]; });
   std::vector<uint64_t> sorted(order.size());
   std::vector<WeightClass> classes;
   uint32_t max_class = 0;
   for (size_t i = 0; i < order.size(); ++i) {
     sorted[i] = (uint64_t)(uintptr_t)ptrs[order[i]];
     const uint32_t wt = h_weights[order[i]];
-    if (classes.empty() || classes.back().weight != wt) classes.push_back(WeightClass{wt, (uint32_t)i, (uint32_t)i, 0});
+    if (classes.empty() || classes.back().weight != wt ||
+        (ctx->prune && classes.back().end - classes.back().begin >= kPruneClass))
+      classes.push_back(WeightClass{wt, (uint32_t)i, (uint32_t)i, 0});
     classes.back().end = (uint32_t)i + 1;
     const uint32_t size = classes.back().end - classes.back().begin;
     if (size > max_class) max_class = size;
@@ -561,7 +566,8 @@ tq_status tq_threshold_weighted(tq_ctx* ctx, const uint64_t* const* ptrs, uint32
   if (!d_cls) return staging_error(ctx, TQ_EDEVICE);
   st = record_hip(ctx, launch_weighted(reinterpret_cast<const uint64_t* const*>(d_ptrs),
                                        reinterpret_cast<const WeightClass*>(d_cls), (uint32_t)classes.size(),
-                                       max_class, nw, tmask, (uint32_t)theta, (uint32_t)total, d_out, stream));
+                                       max_class, nw, tmask, (uint32_t)theta, (uint32_t)total, ctx->prune != 0,
+                                       d_out, stream));
   blob_used(ctx, pb, stream);
   blob_used(ctx, cb, stream);
   return st;

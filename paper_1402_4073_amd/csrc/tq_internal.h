@@ -98,9 +98,11 @@ hipError_t launch_looped(const uint64_t* const* d_ptrs, uint32_t n, uint64_t nwo
 struct WeightClass {
   uint32_t weight, begin, end, pad;
 };
+// prune: after each class a lane whose positions are all decided (weighted
+// sum already >= theta, or below theta even with every class left) stops.
 hipError_t launch_weighted(const uint64_t* const* d_ptrs, const WeightClass* d_classes, uint32_t nclasses,
                            uint32_t max_class, uint64_t nwords, uint64_t tail_mask, uint32_t theta,
-                           uint32_t total_weight, uint64_t* d_out, hipStream_t stream);
+                           uint32_t total_weight, bool prune, uint64_t* d_out, hipStream_t stream);
 
 // Constant result with consumers: out = value AND filter (tail cleared),
 // partial popcounts per 256-word block (fill_groups(nwords) slots).

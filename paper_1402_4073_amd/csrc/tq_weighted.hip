@@ -11,6 +11,12 @@
 // costs nothing; the additions run once per class and column, against one
 // full adder per input for the counting.  The comparison with theta is the
 // same scalar walk over the bits of theta - 1 as in the unweighted kernels.
+//
+// Pruning (the skipping argument of section 1 with weights): the classes come
+// heaviest first, and after each class a lane whose positions all have a
+// total of at least theta, or a total below theta even with the weight of
+// every class left, stops loading; the wave stops once no lane loads.  The
+// total then still gives the right answer at every position.
 #include "tq_csa.hpp"
 
 namespace tq {
@@ -23,8 +29,8 @@ template <int KC, int KT>
 __global__ __launch_bounds__(64) void weighted_kernel(const uint64_t* const* __restrict__ ptrs,
                                                       const WeightClass* __restrict__ classes, uint32_t nclasses,
                                                       uint64_t nwords, uint64_t tail_mask, uint32_t theta,
-                                                      uint32_t total_weight, uint64_t* __restrict__ out,
-                                                      uint64_t block0) {
+                                                      uint32_t total_weight, bool prune,
+                                                      uint64_t* __restrict__ out, uint64_t block0) {
   const int lane = threadIdx.x;
   const uint64_t base = (block0 + blockIdx.x) * 64;
   const uint64_t w = base + lane;
@@ -33,15 +39,20 @@ __global__ __launch_bounds__(64) void weighted_kernel(const uint64_t* const* __r
 #pragma unroll
   for (int t = 0; t < KT; ++t) T[t].w[0] = 0;
 
+  const uint64_t valid = w < nwords ? (w == nwords - 1 ? tail_mask : ~(uint64_t)0) : 0;
+  uint32_t left = total_weight;   // weight of the classes not read yet
+  bool alive = true;
   for (uint32_t c = 0; c < nclasses; ++c) {
     const WeightClass cl = classes[c];
     Vec<1> C[KC];
 #pragma unroll
     for (int q = 0; q < KC; ++q) C[q].w[0] = 0;
-    if (full)
-      accumulate<KC, 1, false>(C, ptrs, cl.begin, cl.end, w, nwords);
-    else
-      accumulate<KC, 1, true>(C, ptrs, cl.begin, cl.end, w, nwords);
+    if (alive) {
+      if (full)
+        accumulate<KC, 1, false>(C, ptrs, cl.begin, cl.end, w, nwords);
+      else
+        accumulate<KC, 1, true>(C, ptrs, cl.begin, cl.end, w, nwords);
+    }
     // T += weight * C, one shifted addition per set bit of the weight
 #pragma unroll
     for (int b = 0; b < KT; ++b) {
@@ -56,6 +67,13 @@ __global__ __launch_bounds__(64) void weighted_kernel(const uint64_t* const* __r
         }
       }
     }
+    if (prune) {
+      left -= cl.weight * (cl.end - cl.begin);
+      const uint64_t yes = at_least<KT, 1>(T, theta, total_weight).w[0];
+      const uint64_t no = left < theta ? ~at_least<KT, 1>(T, theta - left, total_weight).w[0] : 0;
+      alive = ((yes | no) & valid) != valid;
+      if (!__any(alive)) break;
+    }
   }
   if (w >= nwords) return;
   uint64_t r = at_least<KT, 1>(T, theta, total_weight).w[0];
@@ -64,7 +82,7 @@ __global__ __launch_bounds__(64) void weighted_kernel(const uint64_t* const* __r
 }
 
 typedef void (*WeightedFn)(const uint64_t* const*, const WeightClass*, uint32_t, uint64_t, uint64_t, uint32_t,
-                           uint32_t, uint64_t*, uint64_t);
+                           uint32_t, bool, uint64_t*, uint64_t);
 
 template <int KC>
 WeightedFn pick_kt(int kt) {
@@ -101,7 +119,7 @@ void weighted_planes(uint32_t max_class, uint64_t total_weight, int* kc, int* kt
 
 hipError_t launch_weighted(const uint64_t* const* d_ptrs, const WeightClass* d_classes, uint32_t nclasses,
                            uint32_t max_class, uint64_t nwords, uint64_t tail_mask, uint32_t theta,
-                           uint32_t total_weight, uint64_t* d_out, hipStream_t stream) {
+                           uint32_t total_weight, bool prune, uint64_t* d_out, hipStream_t stream) {
   int kc, kt;
   weighted_planes(max_class, total_weight, &kc, &kt);
   WeightedFn fn = pick_weighted(kc, kt);
@@ -111,7 +129,7 @@ hipError_t launch_weighted(const uint64_t* const* d_ptrs, const WeightClass* d_c
   for (uint64_t b0 = 0; b0 < blocks; b0 += per_launch) {
     const uint64_t nb = blocks - b0 < per_launch ? blocks - b0 : per_launch;
     hipLaunchKernelGGL(fn, dim3((uint32_t)nb), dim3(64), 0, stream, d_ptrs, d_classes, nclasses, nwords,
-                       tail_mask, theta, total_weight, d_out, b0);
+                       tail_mask, theta, total_weight, prune, d_out, b0);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -3,8 +3,10 @@
 Every output word is compared with the oracle's weighted threshold (the
 definition: the sum of the weights of the inputs that have the bit), over
 weight classes of every counter width, zero and duplicate weights, totals up
-to 2^32 - 1, ragged tails and the theta edges; small weights are also checked
-against the unweighted kernel on replicated inputs (section 2.3).
+to 2^32 - 1, ragged tails and the theta edges, with pruning on (classes of
+at most 64 inputs, heaviest first, lanes stopping once decided) and off;
+small weights are also checked against the unweighted kernel on replicated
+inputs (section 2.3).
 """
 import numpy as np
 import pytest
@@ -24,6 +26,13 @@ def ctx():
     tq.tq_destroy(c)
 
 
+@pytest.fixture(params=[1, 0], ids=["prune", "noprune"])
+def prune(ctx, request):
+    tq.tq_set_option(ctx, tq.TQ_OPTION_PRUNE, request.param)
+    yield request.param
+    tq.tq_set_option(ctx, tq.TQ_OPTION_PRUNE, 1)
+
+
 def rand_words(rng, n, nw, p):
     bits = rng.random((n, nw * 64)) < p
     return np.packbits(bits.astype(np.uint8), axis=1, bitorder="little").view("<u8").astype(np.uint64)
@@ -40,7 +49,7 @@ CASES = [
 
 @pytest.mark.parametrize("n,r", [(1, 64 * 100 + 1), (7, 64 * 900 + 13), (40, 64 * 1024), (300, 64 * 150 + 63)])
 @pytest.mark.parametrize("case", [c[0] for c in CASES])
-def test_weighted_matches_oracle(ctx, n, r, case):
+def test_weighted_matches_oracle(ctx, prune, n, r, case):
     rng = np.random.default_rng(n * 7 + len(case))
     weights = [int(x) for x in dict(CASES)[case](rng, n)]
     nw = (r + 63) // 64
@@ -57,7 +66,7 @@ def test_weighted_matches_oracle(ctx, n, r, case):
             (case, theta)
 
 
-def test_weighted_equals_replication(ctx):
+def test_weighted_equals_replication(ctx, prune):
     rng = np.random.default_rng(5)
     n, r = 12, 64 * 2000 + 7
     nw = (r + 63) // 64
@@ -75,7 +84,7 @@ def test_weighted_equals_replication(ctx):
         assert np.array_equal(to_host(a), to_host(b)), theta
 
 
-def test_weighted_extreme_totals(ctx):
+def test_weighted_extreme_totals(ctx, prune):
     """Totals near 2^32 - 1 (the widest total counter) and classes of more
     than 8191 equal weights (the widest class counter)."""
     rng = np.random.default_rng(9)
