@@ -4,14 +4,15 @@
 // For T <= 3, bit plane B[t] of a lane holds "at least t + 1 of the inputs so
 // far have this bit": adding an input word x is B[t] |= B[t-1] & x from the
 // top plane down, then B[0] |= x (2T - 1 operations, no carries).  A position
-// is decided once B[T-1] is set, and because the planes only grow, a wave
-// whose positions are all decided can stop reading; the test costs one
-// ballot per 8 inputs, against one per 32 in the carry-save kernel.
+// is decided once B[T-1] is set, and because the planes only grow, a lane
+// whose positions are all decided stops reading and the wave ends once no
+// lane reads; the test runs every 8 inputs (every 16 in the carry-save
+// kernel).
 //
 // A threshold theta close to N is the complement of a small one over the
 // complemented inputs: NOT T_theta(B) = T_{N - theta + 1}(NOT B) (the
 // corrected form of the identity), so theta >= N - 2 runs with T = N - theta
-// + 1 <= 3 on the zeros of the inputs and inverts the result.  There the wave
+// + 1 <= 3 on the zeros of the inputs and inverts the result.  There a lane
 // stops once every position has seen T zeros, typically after a few inputs.
 #include "tq_internal.h"
 
