@@ -397,14 +397,14 @@ void batch_destroy(tq_ctx* ctx) {
   BatchState* bs = static_cast<BatchState*>(ctx->batch);
   if (!bs) return;
   for (auto& s : bs->slots) {
-    if (s.done_ev) hipEventSynchronize(s.done_ev);
-    if (s.exec) hipGraphExecDestroy(s.exec);
-    if (s.graph) hipGraphDestroy(s.graph);
-    if (s.done_ev) hipEventDestroy(s.done_ev);
-    if (s.d_buf) hipFree(s.d_buf);
-    if (s.h_buf) hipHostFree(s.h_buf);
-    if (s.d_qdone) hipFree(s.d_qdone);
-    if (s.h_rec) hipHostFree(s.h_rec);
+    if (s.done_ev) (void)hipEventSynchronize(s.done_ev);
+    if (s.exec) (void)hipGraphExecDestroy(s.exec);
+    if (s.graph) (void)hipGraphDestroy(s.graph);
+    if (s.done_ev) (void)hipEventDestroy(s.done_ev);
+    if (s.d_buf) (void)hipFree(s.d_buf);
+    if (s.h_buf) (void)hipHostFree(s.h_buf);
+    if (s.d_qdone) (void)hipFree(s.d_qdone);
+    if (s.h_rec) (void)hipHostFree(s.h_rec);
   }
   delete bs;
   ctx->batch = nullptr;

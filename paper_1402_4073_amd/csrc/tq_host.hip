@@ -39,13 +39,13 @@ hipError_t blob_wait_idle(Blob& b) {
 }
 
 void blob_release(Blob& b) {
-  blob_wait_idle(b);
-  for (auto& u : b.uses) hipEventDestroy(u.second);
+  (void)blob_wait_idle(b);
+  for (auto& u : b.uses) (void)hipEventDestroy(u.second);
   b.uses.clear();
-  if (b.copied) hipEventDestroy(b.copied);
+  if (b.copied) (void)hipEventDestroy(b.copied);
   b.copied = nullptr;
-  if (b.d) hipFree(b.d);
-  if (b.h_pinned) hipHostFree(b.h_pinned);
+  if (b.d) (void)hipFree(b.d);
+  if (b.h_pinned) (void)hipHostFree(b.h_pinned);
   b.d = nullptr;
   b.h_pinned = nullptr;
   b.cap_words = 0;
@@ -98,8 +98,8 @@ const void* blob_get(tq_ctx* ctx, const uint64_t* words, size_t count, hipStream
   if (e != hipSuccess) { record_hip(ctx, e); return nullptr; }
   victim->valid = false;
   if (victim->cap_words < count) {
-    if (victim->d) hipFree(victim->d);
-    if (victim->h_pinned) hipHostFree(victim->h_pinned);
+    if (victim->d) (void)hipFree(victim->d);
+    if (victim->h_pinned) (void)hipHostFree(victim->h_pinned);
     victim->d = nullptr;
     victim->h_pinned = nullptr;
     size_t cap = std::max<size_t>(count, 512);
@@ -289,7 +289,7 @@ tq_status tq_create(tq_ctx** out, int device) {
     return TQ_ENOMEM;
   }
   if (hipMemset(c->d_status, 0, 256) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
-    hipFree(c->d_status);
+    (void)hipFree(c->d_status);
     delete c;
     return TQ_EDEVICE;
   }
@@ -298,17 +298,19 @@ tq_status tq_create(tq_ctx** out, int device) {
   return TQ_OK;
 }
 
+// Teardown is best effort: every resource is released whatever the device
+// reports on the way.
 tq_status tq_destroy(tq_ctx* ctx) {
   if (!ctx) return TQ_OK;
-  hipSetDevice(ctx->device);
-  hipDeviceSynchronize();
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
   batch_destroy(ctx);
   selector_destroy(ctx);
   tuner_destroy(ctx);
   for (auto& b : ctx->blobs) blob_release(b);
-  if (ctx->ws) hipFree(ctx->ws);
-  for (void* p : ctx->ws_retired) hipFree(p);
-  if (ctx->d_status) hipFree(ctx->d_status);
+  if (ctx->ws) (void)hipFree(ctx->ws);
+  for (void* p : ctx->ws_retired) (void)hipFree(p);
+  if (ctx->d_status) (void)hipFree(ctx->d_status);
   delete ctx;
   return TQ_OK;
 }

@@ -295,23 +295,33 @@ tq_status tq_threshold_auto(tq_ctx* ctx, const tq_bitmap* inputs, uint32_t n, ui
       }
     }
     // exhaustive fallback: time every available variant once on this query
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return TQ_EDEVICE;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto release = [&]() {
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+    };
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+      release();
+      return TQ_EDEVICE;
+    }
     float best_ms = 0.f;
     int fastest = -1;
     for (int v = 0; v < kOut; ++v) {
       if (!variant_available(inputs, n, v)) continue;
-      hipEventRecord(e0, stream);
-      tq_status st = tq_threshold_variant(ctx, inputs, n, r_bits, theta, (uint32_t)v, d_out, stream);
-      hipEventRecord(e1, stream);
-      if (st != TQ_OK) { hipEventDestroy(e0); hipEventDestroy(e1); return st; }
-      hipEventSynchronize(e1);
+      hipError_t e = hipEventRecord(e0, stream);
+      tq_status st = e == hipSuccess ? tq_threshold_variant(ctx, inputs, n, r_bits, theta, (uint32_t)v, d_out, stream)
+                                     : record_hip(ctx, e);
+      if (st == TQ_OK) st = record_hip(ctx, hipEventRecord(e1, stream));
+      if (st == TQ_OK) st = record_hip(ctx, hipEventSynchronize(e1));
       float ms = 0.f;
-      hipEventElapsedTime(&ms, e0, e1);
+      if (st == TQ_OK) st = record_hip(ctx, hipEventElapsedTime(&ms, e0, e1));
+      if (st != TQ_OK) {
+        release();
+        return st;
+      }
       if (fastest < 0 || ms < best_ms) { best_ms = ms; fastest = v; }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    release();
     if (cache && fastest >= 0) {
       if (s->decided.size() >= kMaxDecisions) s->decided.clear();
       s->decided[key] = (uint8_t)fastest;
