@@ -539,7 +539,9 @@ tq_status tq_threshold_weighted(tq_ctx* ctx, const uint64_t* const* ptrs, uint32
   // group the inputs of equal weight (weight 0 contributes nothing), heaviest
   // first; with pruning, classes of at most kPruneClass inputs, after each of
   // which the kernel checks whether a lane's positions are all decided
-  constexpr uint32_t kPruneClass = 64;
+  // (measured on 256 inputs of weights 1..4: 16 against 64 is 10-40 % faster
+  // where theta lets it prune, 1 % slower where it cannot)
+  constexpr uint32_t kPruneClass = 16;
   std::vector<uint32_t> order;
   order.reserve(n);
   for (uint32_t j = 0; j < n; ++j)

@@ -4,7 +4,7 @@ Every output word is compared with the oracle's weighted threshold (the
 definition: the sum of the weights of the inputs that have the bit), over
 weight classes of every counter width, zero and duplicate weights, totals up
 to 2^32 - 1, ragged tails and the theta edges, with pruning on (classes of
-at most 64 inputs, heaviest first, lanes stopping once decided) and off;
+at most 16 inputs, heaviest first, lanes stopping once decided) and off;
 small weights are also checked against the unweighted kernel on replicated
 inputs (section 2.3).
 """
