@@ -46,6 +46,7 @@ constexpr int kOnePassColumns = kTile / 16;
 constexpr int kEncBlock = 256;
 constexpr int kEncPerThread = 8;
 constexpr int kEncWords = kEncBlock * kEncPerThread;
+static_assert(kEncWords % kTile == 0 && kEncWords / kTile <= kEncBlock, "whole checkpoint strides per encoder block");
 
 __device__ __forceinline__ void set_status(int* status, int code) { atomicCAS(status, 0, code); }
 
@@ -731,13 +732,23 @@ __global__ __launch_bounds__(1024) void enc_scan_kernel(EncArgs a, uint64_t nblo
 __global__ __launch_bounds__(kEncBlock) void enc_scatter_kernel(EncArgs a) {
   __shared__ uint64_t wave_tot[kEncBlock / 64];
   __shared__ uint64_t total;
+  // A block without marker starts and dirty words (its sum, the difference of
+  // two exclusive prefixes, is zero) lies inside the marker that covers its
+  // first word: only its checkpoints are written, and its words are not read.
+  const uint64_t pre_block = a.block_sums[blockIdx.x];
+  const uint64_t next_block = blockIdx.x + 1 < gridDim.x ? a.block_sums[blockIdx.x + 1] : a.totals[0];
+  if (next_block == pre_block) {
+    const uint64_t w = (uint64_t)blockIdx.x * kEncWords + (uint64_t)threadIdx.x * kTile;
+    if (threadIdx.x < kEncWords / kTile && w < a.nwords) a.chk_marker[w / kTile] = (uint32_t)((pre_block >> 32) - 1);
+    return;
+  }
   const uint64_t base = (uint64_t)blockIdx.x * kEncWords + (uint64_t)threadIdx.x * kEncPerThread;
   uint64_t x[kEncPerThread], c[kEncPerThread];
   enc_span(a, base, x, c);
   uint64_t s = 0;
 #pragma unroll
   for (int q = 0; q < kEncPerThread; ++q) s += c[q];
-  uint64_t pre = block_exclusive_scan<uint64_t, kEncBlock / 64>(s, wave_tot, &total) + a.block_sums[blockIdx.x];
+  uint64_t pre = block_exclusive_scan<uint64_t, kEncBlock / 64>(s, wave_tot, &total) + pre_block;
 #pragma unroll
   for (int q = 0; q < kEncPerThread; ++q) {
     const uint64_t w = base + q;
