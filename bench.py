@@ -141,7 +141,6 @@ def bench_rle(args):
     import numpy as np
     import torch
     import tqgen
-    import oracle
     from paper_1402_4073_amd import binding as tq
 
     ms = tqgen.rle_set(3)
@@ -193,7 +192,7 @@ def bench_rle(args):
                 ev_tile.append((a, b))
         torch.cuda.synchronize()
     # symmetric functions over the same compressed inputs (canonical RLE output)
-    sym = {"parity": oracle.truth_parity(n), "2<=count<=10": oracle.truth_interval(n, 2, 10)}
+    sym = {"parity": tq.truth_parity(n), "2<=count<=10": tq.truth_interval(n, 2, 10)}
     sym_ms = {}
     with torch.cuda.stream(stream):
         for name, t in sym.items():
@@ -254,6 +253,7 @@ def bench_rle(args):
     }
     if not args.no_cpu_baseline:
         # the oracle on a prefix of every bitmap: threshold then canonical encoding
+        import oracle
         threads = oracle.max_threads()
         cols = np.arange(sample_cols, dtype=np.uint64)
         rs = sample_cols * 64
@@ -737,7 +737,6 @@ def main():
     import numpy as np
     import torch
     import tqgen
-    import oracle
     from paper_1402_4073_amd import binding as tq
 
     dev = torch.device("cuda:0")
@@ -758,7 +757,7 @@ def main():
     rows = [pool[j] for j in range(n)]
     out = torch.empty(nw, dtype=torch.int64, device=dev)
     queries = [("threshold", t) for t in thetas]
-    queries += [("symmetric", oracle.truth_interval(n, lo, hi)), ("symmetric", oracle.truth_parity(n))]
+    queries += [("symmetric", tq.truth_interval(n, lo, hi)), ("symmetric", tq.truth_parity(n))]
 
     ctx = tq.tq_create(0)
     stream = torch.cuda.Stream(device=dev)

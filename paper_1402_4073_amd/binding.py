@@ -166,6 +166,16 @@ def truth_words(truth) -> list:
     return words
 
 
+def truth_interval(n: int, lo: int, hi: int) -> list:
+    """Truth table f[0..n] of the interval query lo <= count <= hi (section 2.2)."""
+    return [1 if lo <= c <= hi else 0 for c in range(n + 1)]
+
+
+def truth_parity(n: int) -> list:
+    """Truth table f[0..n] of parity, 1 iff the count is odd (section 2.2)."""
+    return [c & 1 for c in range(n + 1)]
+
+
 # ------------------------------------------------------------------ context
 def tq_create(device: int = 0) -> int:
     h = _P()

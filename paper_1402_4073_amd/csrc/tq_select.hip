@@ -255,6 +255,12 @@ tq_status tq_selector_predict(tq_ctx* ctx, const float* features, float* predict
 tq_status tq_threshold_auto(tq_ctx* ctx, const tq_bitmap* inputs, uint32_t n, uint64_t r_bits, uint32_t theta,
                             uint64_t* d_out, uint32_t flags, uint32_t* chosen, hipStream_t stream) {
   if (!ctx || !inputs || n == 0) return TQ_EINVAL;
+  // a query no variant can read (an input with neither form) is refused
+  // whatever the flags, before any prediction or timing
+  uint32_t avail = 0;
+  for (int v = 0; v < kOut; ++v)
+    if (variant_available(inputs, n, v)) avail |= 1u << v;
+  if (avail == 0) return TQ_EINVAL;
   Selector* s = static_cast<Selector*>(ctx->selector);
   float f[kIn], y[kOut];
   int best = -1, second = -1;
@@ -278,9 +284,6 @@ tq_status tq_threshold_auto(tq_ctx* ctx, const tq_bitmap* inputs, uint32_t n, ui
   }
   // the fallback times the variants and synchronises: not under stream capture
   if ((flags & TQ_AUTO_FALLBACK) && uncertain && !stream_capturing(stream)) {
-    uint32_t avail = 0;
-    for (int v = 0; v < kOut; ++v)
-      if (variant_available(inputs, n, v)) avail |= 1u << v;
     if (!s && have_f) {
       s = new (std::nothrow) Selector();   // holds the remembered decisions only
       ctx->selector = s;

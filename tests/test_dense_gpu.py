@@ -1,8 +1,8 @@
 """Dense threshold / symmetric queries on the GPU against the CPU oracle.
 
 Element-by-element comparison of whole outputs at sizes the oracle finishes
-in seconds (several tiles, ragged tails), sampled-column comparison at the
-full large configuration, and the error paths of the ABI.
+in seconds (several tiles, ragged tails) and at the full large
+configuration, and the error paths of the ABI.
 """
 import ctypes
 
@@ -200,48 +200,57 @@ def large(ctx):
     torch.cuda.empty_cache()
 
 
-def test_large_config_sampled(ctx, large):
-    """N=256, r=2^26: outputs checked on sampled columns against the oracle,
-    plus properties that hold at any size."""
+def test_large_config_full(ctx, large):
+    """N=256, r=2^26 (2 GiB): the benchmark's step exactly as timed (inputs
+    registered with their cardinality and run count, thresholds 2, 16, 128,
+    255 through the carry-save variant with registered input order, pruning
+    and the saturating counters on; the interval 2 <= count <= 10 and parity
+    through tq_symmetric), then the roofline pass (pruning and saturating
+    counters off); every output word of every query equals the oracle's.
+    theta = 1 is also checked against torch's OR of all inputs and parity
+    against torch's XOR."""
     bs, pool = large
-    rows = [pool[j] for j in range(bs.n)]
-    rng = np.random.default_rng(77)
-    cols = np.unique(np.concatenate([[0, 1, bs.nwords - 1],
-                                     rng.integers(0, bs.nwords, 200)])).astype(np.int64)
-    words = np.stack([np.concatenate([bs.words(j, int(c), int(c) + 1) for c in cols]) for j in range(bs.n)])
-    outs = {}
-    for theta in (1, 2, 16, 128, 255):
-        out = torch.empty(bs.nwords, dtype=torch.int64, device="cuda")
-        tq.tq_threshold(ctx, rows, bs.r_bits, theta, out)
-        assert tq.tq_ctx_check(ctx) == 0
-        got = to_host(out)
-        assert np.array_equal(got[cols], oracle.threshold_cols(words, cols, bs.r_bits, theta)), theta
-        outs[theta] = out
-    # theta = 1 is the OR of all inputs (torch's own bitwise_or, whole bitmaps)
-    acc = torch.zeros(bs.nwords, dtype=torch.int64, device="cuda")
-    for j in range(bs.n):
+    n, nw, r = bs.n, bs.nwords, bs.r_bits
+    rows = [pool[j] for j in range(n)]
+    host_all = pool.cpu().numpy().view(np.uint64)
+    host = [host_all[j] for j in range(n)]
+    stats = torch.zeros((n, 2), dtype=torch.int64, device="cuda")
+    for j in range(n):
+        tq.tq_bitmap_stats(ctx, rows[j], r, stats[j, 0:1], stats[j, 1:2])
+    st = stats.cpu().numpy()
+    registered = (tq.bitmap_array([dict(dense=rows[j], rle=None, ones=int(st[j, 0]), runs=int(st[j, 1]))
+                                   for j in range(n)]), n)
+    queries = [("threshold", t) for t in tqgen.LARGE["thetas"]]
+    lo, hi = tqgen.LARGE["interval"]
+    queries += [("symmetric", oracle.truth_interval(n, lo, hi)), ("symmetric", oracle.truth_parity(n))]
+    wants = [oracle.threshold(host, r, a) if k == "threshold" else oracle.symmetric(host, r, a)
+             for k, a in queries]
+    out = torch.empty(nw, dtype=torch.int64, device="cuda")
+    for prune in (1, 0):
+        tq.tq_set_option(ctx, tq.TQ_OPTION_PRUNE, prune)
+        tq.tq_set_option(ctx, tq.TQ_OPTION_LOOPED, prune)
+        for (kind, arg), want in zip(queries, wants):
+            out.fill_(0x5A5A5A5A)
+            if kind == "threshold":
+                tq.tq_threshold_variant(ctx, registered, r, arg, tq.TQ_VARIANT_CSA, out)
+            else:
+                tq.tq_symmetric(ctx, rows, r, arg, out)
+            assert tq.tq_ctx_check(ctx) == 0
+            assert np.array_equal(to_host(out), want), (kind, prune)
+    tq.tq_set_option(ctx, tq.TQ_OPTION_PRUNE, 1)
+    tq.tq_set_option(ctx, tq.TQ_OPTION_LOOPED, 1)
+    # theta = 1 is the OR of all inputs, parity their XOR (torch's own ops)
+    acc = torch.zeros(nw, dtype=torch.int64, device="cuda")
+    x = torch.zeros(nw, dtype=torch.int64, device="cuda")
+    for j in range(n):
         acc |= pool[j]
-    assert torch.equal(acc, outs[1])
-    # T_{t+1} is a subset of T_t
-    for a, b in ((1, 2), (2, 16), (16, 128), (128, 255)):
-        assert not torch.any(outs[b] & ~outs[a]).item()
-    for name, f in (("interval", oracle.truth_interval(bs.n, 2, 10)), ("parity", oracle.truth_parity(bs.n))):
-        out = torch.empty(bs.nwords, dtype=torch.int64, device="cuda")
-        tq.tq_symmetric(ctx, rows, bs.r_bits, f, out)
-        assert tq.tq_ctx_check(ctx) == 0
-        got = to_host(out)
-        assert np.array_equal(got[cols], oracle.symmetric_cols(words, cols, bs.r_bits, f)), name
-        if name == "parity":
-            x = torch.zeros(bs.nwords, dtype=torch.int64, device="cuda")
-            for j in range(bs.n):
-                x ^= pool[j]
-            assert torch.equal(x, out)
-        else:
-            want = outs[2] & ~torch.zeros_like(outs[2])
-            # interval [2,10] = T_2 and not T_11
-            out11 = torch.empty(bs.nwords, dtype=torch.int64, device="cuda")
-            tq.tq_threshold(ctx, rows, bs.r_bits, 11, out11)
-            assert torch.equal(out, want & ~out11)
+        x ^= pool[j]
+    tq.tq_threshold(ctx, rows, r, 1, out)
+    assert tq.tq_ctx_check(ctx) == 0
+    assert torch.equal(acc, out)
+    tq.tq_symmetric(ctx, rows, r, oracle.truth_parity(n), out)
+    assert tq.tq_ctx_check(ctx) == 0
+    assert torch.equal(x, out)
 
 
 # ----------------------------------------------------------------- pruning

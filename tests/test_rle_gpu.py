@@ -294,8 +294,12 @@ def test_hybrid(ctx, n_rle, n_dense):
 # ------------------------------------------------------- full configuration
 def test_rle_config_full_size(ctx):
     """N=512 Markov bitmaps of r=2^28 bits (ones-runs mean 64, zeros-runs mean
-    4096), encoded on the GPU; thresholds 2, 64, 256 checked on sampled words
-    against the oracle and in full against the uncompressed kernel."""
+    4096), encoded on the GPU; thresholds 2, 64, 256, parity and
+    2 <= count <= 10 with canonical RLE output.  Every output stream decodes
+    (oracle decoder) to a bitmap equal, word for word, to the oracle's result
+    on the generator's words (compared in word ranges of 2^18 columns), is
+    the oracle's canonical encoding of it, and equals the uncompressed
+    kernel's output on the same inputs."""
     ms = tqgen.rle_set(3)
     n, nw, r = ms.n, ms.nwords, ms.r_bits
     dense = torch.empty((n, nw), dtype=torch.int64, device="cuda")
@@ -305,41 +309,48 @@ def test_rle_config_full_size(ctx):
     rows = [dense[j] for j in range(n)]
     pool, offs, lens, index_pool = tq.encode_pool(ctx, rows, r)
     inputs = [(pool[offs[j]:], lens[j], index_pool[j]) for j in range(n)]
-    rng = np.random.default_rng(5)
-    cols = np.unique(np.concatenate([[0, nw - 1], rng.integers(0, nw, 48)])).astype(np.int64)
-    words = np.stack([np.concatenate([ms.words(j, int(c), int(c) + 1) for c in cols]) for j in range(n)])
-    # the GPU-encoded inputs decode back to the generator's words at the sampled columns
-    for j in (0, n - 1):
+    # the GPU-encoded inputs decode back to the generator's words
+    for j in (0, 1, n - 1):
         dec = torch.empty(nw, dtype=torch.int64, device="cuda")
         tq.tq_rle_decode(ctx, inputs[j], r, dec)
         assert tq.tq_ctx_check(ctx) == 0
-        assert np.array_equal(to_host(dec)[cols], words[j])
+        assert torch.equal(dec, dense[j])
+        s_host = to_host(pool[offs[j]:offs[j] + lens[j]])
+        assert np.array_equal(oracle.rle_decode(s_host, r), to_host(dense[j]))
     cap = tq.tq_rle_max_words(r)
     out = torch.empty(cap, dtype=torch.int64, device="cuda")
     ln = torch.zeros(1, dtype=torch.int64, device="cuda")
     ref = torch.empty(nw, dtype=torch.int64, device="cuda")
-    for theta in (2, 64, 256):
-        tq.tq_threshold_rle(ctx, inputs, r, theta, out, cap, ln)
-        assert tq.tq_ctx_check(ctx) == 0
-        L = int(ln.item())
-        stream = to_host(out)[:L]
-        got = oracle.rle_decode(stream, r)                       # valid, exact coverage
-        assert np.array_equal(oracle.rle_encode(got, r), stream)  # canonical
-        assert np.array_equal(got[cols], oracle.threshold_cols(words, cols, r, theta)), theta
-        tq.tq_threshold(ctx, rows, r, theta, ref)                # uncompressed path, same inputs
-        assert tq.tq_ctx_check(ctx) == 0
-        assert np.array_equal(got, to_host(ref)), theta
-    # symmetric functions over the same compressed inputs: parity, 2 <= count <= 10
-    for t in (oracle.truth_parity(n), oracle.truth_interval(n, 2, 10)):
-        tq.tq_symmetric_rle(ctx, inputs, r, t, out, cap, ln)
+    queries = [("threshold", t) for t in (2, 64, 256)]
+    queries += [("symmetric", oracle.truth_parity(n)), ("symmetric", oracle.truth_interval(n, 2, 10))]
+    results = []
+    for kind, arg in queries:
+        if kind == "threshold":
+            tq.tq_threshold_rle(ctx, inputs, r, arg, out, cap, ln)
+        else:
+            tq.tq_symmetric_rle(ctx, inputs, r, arg, out, cap, ln)
         assert tq.tq_ctx_check(ctx) == 0
         stream = to_host(out)[:int(ln.item())]
-        got = oracle.rle_decode(stream, r)
-        assert np.array_equal(oracle.rle_encode(got, r), stream)
-        assert np.array_equal(got[cols], oracle.symmetric_cols(words, cols, r, t))
-        tq.tq_symmetric(ctx, rows, r, t, ref)
+        got = oracle.rle_decode(stream, r)                       # valid, exact coverage
+        assert np.array_equal(oracle.rle_encode(got, r), stream), kind  # canonical
+        if kind == "threshold":
+            tq.tq_threshold(ctx, rows, r, arg, ref)              # uncompressed path, same inputs
+        else:
+            tq.tq_symmetric(ctx, rows, r, arg, ref)
         assert tq.tq_ctx_check(ctx) == 0
-        assert np.array_equal(got, to_host(ref))
+        assert np.array_equal(got, to_host(ref)), kind
+        results.append(got)
+    span = 1 << 18
+    for c0 in range(0, nw, span):
+        c1 = min(nw, c0 + span)
+        words = dense[:, c0:c1].contiguous().cpu().numpy().view(np.uint64)
+        cols = np.arange(c0, c1, dtype=np.uint64)
+        for (kind, arg), got in zip(queries, results):
+            if kind == "threshold":
+                want = oracle.threshold_cols(words, cols, r, arg)
+            else:
+                want = oracle.symmetric_cols(words, cols, r, arg)
+            assert np.array_equal(got[c0:c1], want), (kind, c0)
 
 
 @pytest.mark.parametrize("n,tiles", [(70, 0), (150, 0), (70, 3), (150, 2)])

@@ -111,6 +111,25 @@ def test_variant_needs_its_form(ctx):
     assert np.array_equal(to_host(out), oracle.threshold(dense, r, 1))
 
 
+def test_auto_refuses_input_without_a_form(ctx):
+    """An input with neither a dense nor a compressed form leaves no variant
+    to run: TQ_EINVAL with and without the timing fallback, and nothing is
+    written."""
+    r = 64 * 100
+    dense = [tqgen.markov_fixed(2, 1, r, 5.0, 50.0).words(0)] * 2
+    bms, keep = registered(ctx, dense, r)
+    bms[1] = dict(dense=None, rle=None, ones=bms[1]["ones"], runs=bms[1]["runs"])
+    p = mlp_ref.init_params(3).astype(np.float32)
+    tq.tq_selector_set(ctx, p, np.zeros(8), np.ones(8), np.full(8, -1e9), np.full(8, 1e9), 1e9)
+    out = empty_words(100)
+    for flags in (0, tq.TQ_AUTO_FALLBACK, tq.TQ_AUTO_FALLBACK | tq.TQ_AUTO_RETIME):
+        with pytest.raises(tq.TQError) as ei:
+            tq.tq_threshold_auto(ctx, bms, r, 1, out, flags)
+        assert ei.value.status == tq.TQ_EINVAL, flags
+    assert tq.tq_ctx_check(ctx) == 0
+    assert np.all(to_host(out) == np.uint64(0x5A5A5A5A5A5A5A5A))
+
+
 def test_mlp_gradient_matches_fp64_reference(ctx):
     rng = np.random.default_rng(4)
     B = 77
