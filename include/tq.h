@@ -208,6 +208,31 @@ tq_status tq_symmetric_fused(tq_ctx* ctx, const uint64_t* const* ptrs, uint32_t 
                              const uint64_t* h_truth, const uint64_t* d_filter, uint64_t* d_out,
                              uint64_t* d_count, hipStream_t stream);
 
+/*
+ * For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc, code that must not allocate while a graph
+ * is being captured): the query
+ * of tq_threshold_fused, with the same arguments, results and errors, that
+ * makes no device or pinned allocation.  Its device scratch (the copy of the
+ * pointer array, then one uint32 partial count per 64 output words when
+ * d_count is given) is a fixed array of TQ_NOALLOC_SCRATCH_BYTES per device,
+ * held until the process ends:
+ *   roundup(8 n, 256) + 4 ceil(ceil(r_bits/64) / 64)  <=  TQ_NOALLOC_SCRATCH_BYTES
+ * when d_count is given (theta in [1, n]); 4 ceil(ceil(r_bits/64) / 256)
+ * bytes when theta is 0 or above n; else TQ_EINVAL and nothing is queued.
+ * Without d_count only the pointer array is held, which always fits.  The
+ * host pointer array is copied with hipMemcpyAsync on `stream`, which stages
+ * pageable memory before it returns (under stream capture the copy becomes a
+ * graph node that reads the host array at every replay).  The
+ * launch shape is the default one (no autotuning).  Every call on a device
+ * shares that device's array: calls that overlap in time on one device (two
+ * streams, two contexts, two threads) race; calls on one stream are ordered.
+ */
+#define TQ_NOALLOC_SCRATCH_BYTES (4u << 20)
+tq_status tq_threshold_fused_noalloc(tq_ctx* ctx, const uint64_t* const* ptrs, uint32_t n, uint64_t r_bits,
+                                     uint32_t theta, const uint64_t* d_filter, uint64_t* d_out,
+                                     uint64_t* d_count, hipStream_t stream);
+
 /* ------------------------------------------------------------------------
  * Run-length-encoded bitmaps (section 2.1, word-aligned RLE with markers that
  * carry both a fill-run length and a dirty-word count, as in EWAH).

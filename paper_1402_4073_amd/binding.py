@@ -57,6 +57,7 @@ def _load():
         "tq_threshold": (_INT, [_P, _P, _U32, _U64, _U32, _P, _P]),
         "tq_symmetric": (_INT, [_P, _P, _U32, _U64, _P, _P, _P]),
         "tq_threshold_fused": (_INT, [_P, _P, _U32, _U64, _U32, _P, _P, _P, _P]),
+        "tq_threshold_fused_noalloc": (_INT, [_P, _P, _U32, _U64, _U32, _P, _P, _P, _P]),
         "tq_threshold_weighted": (_INT, [_P, _P, _U32, _P, _U64, _U64, _P, _P]),
         "tq_symmetric_fused": (_INT, [_P, _P, _U32, _U64, _P, _P, _P, _P, _P]),
         "tq_rle_max_words": (_U64, [_U64]),
@@ -254,6 +255,22 @@ def tq_threshold_fused(ctx: int, inputs, r_bits: int, theta: int, filt=None, out
     ptrs = ptr_array(inputs)
     _check(_lib.tq_threshold_fused(ctx, ptrs, len(inputs), r_bits, theta, _optr(filt), _optr(out), _optr(count),
                                    _stream(stream)), "tq_threshold_fused")
+
+
+def tq_threshold_fused_noalloc(ctx: int, inputs, r_bits: int, theta: int, filt=None, out=None, count=None,
+                               stream=None) -> None:
+    """tq_threshold_fused through the entry point that allocates nothing."""
+    ptrs = ptr_array(inputs)
+    _check(_lib.tq_threshold_fused_noalloc(ctx, ptrs, len(inputs), r_bits, theta, _optr(filt), _optr(out),
+                                           _optr(count), _stream(stream)), "tq_threshold_fused_noalloc")
+
+
+def raw_threshold_fused_noalloc(ctx: int, inputs, r_bits: int, theta: int, filt_ptr, out_ptr, count_ptr,
+                                stream=None) -> int:
+    """Status code of tq_threshold_fused_noalloc with raw device addresses (0 = NULL)."""
+    ptrs = ptr_array(inputs)
+    return _lib.tq_threshold_fused_noalloc(ctx, ptrs, len(inputs), r_bits, theta, filt_ptr, out_ptr, count_ptr,
+                                           _stream(stream))
 
 
 def tq_symmetric_fused(ctx: int, inputs, r_bits: int, truth, filt=None, out=None, count=None,

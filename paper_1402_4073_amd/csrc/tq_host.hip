@@ -281,6 +281,12 @@ tq_status tq_create(tq_ctx** out, int device) {
   tq_ctx* c = new (std::nothrow) tq_ctx();
   if (!c) return TQ_ENOMEM;
   c->device = device;
+  // scratch array of the allocation-free entry point, located once per device
+  const tq_status ns = noalloc_init(device);
+  if (ns != TQ_OK) {
+    delete c;
+    return ns;
+  }
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
     c->num_cus = prop.multiProcessorCount;
@@ -361,11 +367,9 @@ tq_status tq_ctx_check(tq_ctx* ctx, hipStream_t stream) {
 
 }  // extern "C"
 
-namespace {
-
 // Validate the pointer array and the output; returns whether every buffer is 16-byte aligned.
-tq_status check_dense_args(const uint64_t* const* ptrs, uint32_t n, uint64_t r_bits, const uint64_t* d_out,
-                           bool* aligned16, bool out_optional = false) {
+tq_status tq::check_dense_args(const uint64_t* const* ptrs, uint32_t n, uint64_t r_bits, const uint64_t* d_out,
+                               bool* aligned16, bool out_optional) {
   if (!ptrs || n == 0 || n > TQ_MAX_INPUTS) return TQ_EINVAL;
   const uint64_t nw = words_for_bits(r_bits);
   if (r_bits > 0 && !d_out && !out_optional) return TQ_EINVAL;
@@ -381,6 +385,8 @@ tq_status check_dense_args(const uint64_t* const* ptrs, uint32_t n, uint64_t r_b
   *aligned16 = (any & 15) == 0;
   return TQ_OK;
 }
+
+namespace {
 
 // Arguments of the fused consumers: the filter is nullable and may be the
 // output itself but must not overlap it otherwise; the count is nullable;

@@ -114,6 +114,18 @@ hipError_t launch_fill_sink(uint64_t* d_out, uint64_t nwords, uint64_t value, ui
 hipError_t launch_count_reduce(const uint32_t* d_partial, uint64_t m, uint64_t* d_count, hipStream_t stream);
 hipError_t launch_count_reduce(const uint64_t* d_partial, uint64_t m, uint64_t* d_count, hipStream_t stream);
 
+// Arguments of the dense calls: n in [1, TQ_MAX_INPUTS], non-null 8-byte
+// aligned inputs, an 8-byte aligned output (nullable if out_optional) that
+// overlaps no input.  *aligned16: every buffer is 16-byte aligned.
+tq_status check_dense_args(const uint64_t* const* ptrs, uint32_t n, uint64_t r_bits, const uint64_t* d_out,
+                           bool* aligned16, bool out_optional = false);
+
+// Device address of the fixed scratch array of the allocation-free entry
+// point on `device` (set by noalloc_init, which tq_create calls with the
+// device current); nullptr before.
+tq_status noalloc_init(int device);
+void* noalloc_scratch(int device);
+
 // Arguments of the fused-consumer calls: at least one of d_out / d_count,
 // 8-byte alignment, a filter equal to d_out or disjoint from it, d_count
 // outside d_out.
