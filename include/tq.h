@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define TQ_API_VERSION 1
+#define TQ_API_VERSION 2
 
 /* Largest N accepted by the dense calls (the in-register counter has at most
  * 16 bit planes). */
@@ -64,7 +64,9 @@ typedef enum tq_status {
   TQ_ECAPACITY = -4,  /* output capacity too small; the required length is reported */
   TQ_EDEVICE = -5,    /* a HIP runtime call failed */
   TQ_EBUSY = -6,      /* admission refused: the batch ring or workspace is full, retry later */
-  TQ_ENOTSUP = -7     /* the request is valid but not supported by this library */
+  TQ_ENOTSUP = -7,    /* the request is valid but not supported by this library */
+  TQ_ECANCELED = -8,  /* batched query not completed: its batch was cancelled (tq_batch_cancel) */
+  TQ_ETIMEDOUT = -9   /* batched query not completed: its batch passed its deadline */
 } tq_status;
 
 typedef struct tq_ctx tq_ctx;
@@ -108,6 +110,15 @@ const char* tq_status_string(int status);
                                  the context for later queries of the class (skipped while the
                                  stream is being captured into a graph).  0 (default): fixed
                                  shape rules.  Results are identical either way. */
+
+#define TQ_OPTION_BATCH_BYTES 6  /* admission limit of batches (default 2^30): the device bytes that the
+                                    batches of the context not yet released may hold together (packed
+                                    descriptors, pointer arrays and tables, per-query records and
+                                    counters, and the workspace of compressed inputs and compressed
+                                    outputs); value >= 1 */
+#define TQ_OPTION_BATCH_DEADLINE_US 7  /* deadline of later batches in microseconds after the batch
+                                         starts on the device (0, the default: none); see
+                                         tq_batch_submit.  Value in [0, 2^40] */
 
 /* Set a context option; TQ_EINVAL for an unknown option. */
 tq_status tq_set_option(tq_ctx* ctx, int option, int64_t value);
@@ -361,50 +372,106 @@ tq_status tq_symmetric_rle_fused(tq_ctx* ctx, const tq_rle* inputs, uint32_t n, 
  * ---------------------------------------------------------------------- */
 typedef enum tq_query_kind { TQ_QUERY_THRESHOLD = 0, TQ_QUERY_SYMMETRIC = 1 } tq_query_kind;
 
+/* tq_query.variant: let the installed selector choose (see tq_threshold_auto). */
+#define TQ_VARIANT_AUTO 0xFFFFFFFFu
+
+struct tq_bitmap;
+
 typedef struct tq_query {
   uint32_t kind;                /* tq_query_kind */
-  uint32_t n;                   /* number of inputs, [1, TQ_MAX_INPUTS] */
-  const uint64_t* const* ptrs;  /* HOST array of n device pointers (copied at submission) */
+  uint32_t n;                   /* number of inputs, [1, TQ_MAX_INPUTS]; [1, TQ_RLE_MAX_INPUTS] when
+                                   any input is read in compressed form */
+  const uint64_t* const* ptrs;  /* HOST array of n dense device inputs, or NULL when `inputs` is given */
   uint64_t r_bits;
   uint32_t theta;               /* TQ_QUERY_THRESHOLD */
-  uint32_t pad;
+  uint32_t variant;             /* tq_variant, or TQ_VARIANT_AUTO (only with `inputs`); with `ptrs`
+                                   TQ_VARIANT_CSA (0) or TQ_VARIANT_COUNTER */
   const uint64_t* h_truth;      /* TQ_QUERY_SYMMETRIC: host truth table as for tq_symmetric (copied) */
-  uint64_t* d_out;              /* ceil(r_bits/64) device words */
+  uint64_t* d_out;              /* dense result (ceil(r_bits/64) words) when out_cap == 0, else the
+                                   canonical compressed result (at most out_cap words) */
   uint64_t user_tag;            /* returned in the query's record */
+  const struct tq_bitmap* inputs;  /* HOST array of n registered inputs (either or both forms, with
+                                      metadata), or NULL when `ptrs` is given (copied) */
+  uint64_t out_cap;             /* 0: dense result; > 0: compressed result of capacity out_cap words */
+  uint64_t* d_out_len;          /* out_cap > 0: device uint64 receiving the compressed length */
 } tq_query;
 
 typedef struct tq_query_record {
   uint64_t user_tag;
-  int32_t status;               /* TQ_OK once done */
+  int32_t status;               /* TQ_OK once done; see tq_batch_records */
   uint32_t done;                /* 1 once the query's output is complete and visible */
-  uint64_t t_start_ns;          /* device clock when the first work item of the query started */
-  uint64_t t_end_ns;            /* device clock when its last work item finished */
+  uint64_t t_start_ns;          /* device clock when the first work of the query started */
+  uint64_t t_end_ns;            /* device clock when its last work finished */
+  uint32_t variant;             /* tq_variant that ran (the selector's choice for TQ_VARIANT_AUTO) */
+  uint32_t pad;
 } tq_query_record;
 
 typedef struct tq_batch tq_batch;
 
 /* Flags of tq_batch_submit. */
 #define TQ_BATCH_NO_GRAPH 1u    /* launch directly instead of replaying the slot's graph (batches of
-                                   fewer than 64 queries are always launched directly) */
+                                   fewer than 64 queries are always launched directly).  A graph
+                                   replay and a direct launch cost the host different times, which
+                                   shows in the latency of small batches: the caller picks. */
 
 /* Largest batch: queries and total pointer entries (sum of n). */
 #define TQ_BATCH_MAX_QUERIES 8192u
 #define TQ_BATCH_MAX_POINTERS 2097152u
 #define TQ_BATCH_MAX_TABLE_BYTES 1048576u
+/* Batches not yet released that a context holds at once. */
+#define TQ_BATCH_MAX_INFLIGHT 16u
 
 /*
  * Submit `count` queries as one batch on `stream`.  Each query has the
- * semantics of tq_threshold or tq_symmetric (sections 2.2-2.3); results are
- * bit-identical to those calls.  Queries with n > 1 are split into work items
- * of similar byte counts that a persistent kernel serves from one queue.
- * Admission: a context holds a fixed number of batch slots; when none is free
+ * semantics of tq_threshold or tq_symmetric (the threshold and symmetric
+ * functions of sections 2.2-2.3); results are bit-identical to those calls.
+ *
+ * Inputs: either `ptrs` (dense inputs) or `inputs` (registered bitmaps as
+ * for tq_threshold_variant, each with its dense and/or compressed form and
+ * its cardinality and run count).  The variant reads them as in
+ * tq_threshold_variant: TQ_VARIANT_CSA (with TQ_OPTION_LOOPED, thresholds
+ * within 3 of either end by saturating counters; with `inputs` and pruning,
+ * inputs read by registered cardinality), TQ_VARIANT_COUNTER (thresholds
+ * only), TQ_VARIANT_RLE, TQ_VARIANT_HYBRID (compressed and hybrid reads:
+ * thresholds only), or TQ_VARIANT_AUTO: the installed selector's prediction
+ * among the variants the inputs allow (features outside its training range
+ * are clamped into it; nothing is timed), the carry-save counter without a
+ * selector.  A symmetric query with TQ_VARIANT_AUTO runs the carry-save
+ * counter (TQ_ENOTSUP if an input has no dense form).  An input lacking the
+ * form its variant reads is TQ_EINVAL.
+ *
+ * Execution: dense-input queries (carry-save, Looped and counter variants)
+ * are split into work items of similar byte counts that one persistent
+ * kernel serves from one queue; queries over compressed inputs, and the
+ * encoding of compressed results, run after it on the stream as their own
+ * launches (tile kernel, encoder), with indexes the inputs lack built by one
+ * launch per query.  A compressed result (out_cap > 0) behaves as in
+ * tq_threshold_rle: its length goes to *d_out_len, and a capacity below it is
+ * the query's TQ_ECAPACITY (in its record) with the required length still
+ * written.
+ *
+ * Admission: the device bytes the batch holds (packed descriptors and copies
+ * of the pointer arrays and truth tables, per-query records and counters,
+ * and the workspace of compressed inputs and results) are counted against
+ * TQ_OPTION_BATCH_BYTES together with the batches of the context not yet
+ * released; when they do not fit, or TQ_BATCH_MAX_INFLIGHT batches are held,
  * the call returns TQ_EBUSY and queues nothing (retry after releasing a
- * batch).  count in [1, TQ_BATCH_MAX_QUERIES]; sum of n at most
- * TQ_BATCH_MAX_POINTERS.  A symmetric function with more than 8 runs of ones
- * and of zeros in f is evaluated through a lookup table of 2^K bits (K the
- * counter width, bit_length(n)); the tables of one batch may take at most
- * TQ_BATCH_MAX_TABLE_BYTES (each rounded up to 8 bytes), else TQ_EINVAL.  All
- * pointer arrays and truth tables are copied; *out receives the batch.
+ * batch).  A batch that alone exceeds the limit is TQ_EINVAL.
+ *
+ * Deadline and cancellation: the persistent kernel takes no new work item
+ * once the batch is cancelled (tq_batch_cancel) or, with
+ * TQ_OPTION_BATCH_DEADLINE_US set, once that many microseconds have passed
+ * since the batch's kernel started; work items already taken finish.
+ * Queries left incomplete are reported TQ_ECANCELED / TQ_ETIMEDOUT and
+ * their outputs are undefined.  Queries over compressed inputs, which run
+ * after the persistent kernel, are not stopped.
+ *
+ * count in [1, TQ_BATCH_MAX_QUERIES]; sum of n at most TQ_BATCH_MAX_POINTERS.
+ * A symmetric function with more than 8 runs of ones and of zeros in f is
+ * evaluated through a lookup table of 2^K bits (K the counter width,
+ * bit_length(n)); the tables of one batch may take at most
+ * TQ_BATCH_MAX_TABLE_BYTES (each rounded up to 8 bytes), else TQ_EINVAL.
+ * All host arrays are copied; *out receives the batch.
  */
 tq_status tq_batch_submit(tq_ctx* ctx, const tq_query* queries, uint32_t count, uint32_t flags,
                           hipStream_t stream, tq_batch** out);
@@ -413,10 +480,20 @@ tq_status tq_batch_submit(tq_ctx* ctx, const tq_query* queries, uint32_t count, 
  * completion flags are written by the device into pinned host memory). */
 tq_status tq_batch_poll(tq_batch* batch, uint32_t* ndone);
 
-/* Block until the whole batch has completed. */
+/* Block until the batch's work has finished.  Returns TQ_OK if every query
+ * completed with TQ_OK, else the status of the first query (in submission
+ * order) that did not. */
 tq_status tq_batch_wait(tq_batch* batch);
 
-/* Copy the batch's per-query records (count entries, submission order). */
+/* Stop the batch from taking new work items (see tq_batch_submit); does not
+ * wait.  Queries already complete keep their results. */
+tq_status tq_batch_cancel(tq_batch* batch);
+
+/* Copy the batch's per-query records (count entries, submission order).
+ * status: TQ_OK (done = 1 once complete); TQ_ECAPACITY or TQ_EFORMAT for a
+ * compressed result too large or a malformed compressed input (done = 1,
+ * the record is final); TQ_ECANCELED / TQ_ETIMEDOUT once the batch has
+ * finished without completing the query (done = 0). */
 tq_status tq_batch_records(tq_batch* batch, tq_query_record* out);
 
 /* Wait for the batch, free its slot and the handle. */

@@ -28,6 +28,8 @@ TQ_ECAPACITY = -4
 TQ_EDEVICE = -5
 TQ_EBUSY = -6
 TQ_ENOTSUP = -7
+TQ_ECANCELED = -8
+TQ_ETIMEDOUT = -9
 TQ_MAX_INPUTS = 65535
 
 _P = ctypes.c_void_p
@@ -78,6 +80,7 @@ def _load():
         "tq_batch_wait": (_INT, [_P]),
         "tq_batch_records": (_INT, [_P, _P]),
         "tq_batch_release": (_INT, [_P]),
+        "tq_batch_cancel": (_INT, [_P]),
         "tq_batch_tune": (_INT, [_P, _P, _U32, _P, ctypes.POINTER(_U32), ctypes.POINTER(_U32)]),
         "tq_batch_set_schedule": (_INT, [_P, _U32, _U32]),
         "tq_tune_export": (_INT, [_P, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
@@ -193,6 +196,8 @@ TQ_OPTION_RLE_TILES = 2
 TQ_OPTION_AUTOTUNE = 3
 TQ_OPTION_RLE_COUNTERS = 4
 TQ_OPTION_LOOPED = 5
+TQ_OPTION_BATCH_BYTES = 6
+TQ_OPTION_BATCH_DEADLINE_US = 7
 
 
 def tq_set_option(ctx: int, option: int, value: int) -> None:
@@ -442,43 +447,71 @@ TQ_BATCH_NO_GRAPH = 1
 TQ_BATCH_MAX_QUERIES = 8192
 TQ_BATCH_MAX_POINTERS = 2097152
 TQ_BATCH_MAX_TABLE_BYTES = 1048576
+TQ_BATCH_MAX_INFLIGHT = 16
+TQ_VARIANT_AUTO = 0xFFFFFFFF
 
 
 class TqQuery(ctypes.Structure):
     _fields_ = [("kind", _U32), ("n", _U32), ("ptrs", _U64), ("r_bits", _U64), ("theta", _U32),
-                ("pad", _U32), ("h_truth", _U64), ("d_out", _U64), ("user_tag", _U64)]
+                ("variant", _U32), ("h_truth", _U64), ("d_out", _U64), ("user_tag", _U64), ("inputs", _U64),
+                ("out_cap", _U64), ("d_out_len", _U64)]
 
 
 class TqQueryRecord(ctypes.Structure):
     _fields_ = [("user_tag", _U64), ("status", ctypes.c_int32), ("done", _U32),
-                ("t_start_ns", _U64), ("t_end_ns", _U64)]
+                ("t_start_ns", _U64), ("t_end_ns", _U64), ("variant", _U32), ("pad", _U32)]
+
+
+def _fill_query(q, keep, r_bits, out, theta=None, truth=None, tag=0, inputs=None, bitmaps=None,
+                variant=0, out_cap=0, out_len=None):
+    """Fill a TqQuery; host arrays it points to are appended to keep.
+    inputs: dense device inputs (tensors/addresses); bitmaps: registered
+    inputs (dicts as for bitmap_array, or a prebuilt TqBitmap array)."""
+    if (inputs is None) == (bitmaps is None):
+        raise ValueError("give exactly one of inputs and bitmaps")
+    if inputs is not None:
+        ptrs = ptr_array(inputs)
+        keep.append(ptrs)
+        q.n = len(inputs)
+        q.ptrs = ctypes.addressof(ptrs)
+    else:
+        arr = bitmaps if isinstance(bitmaps, ctypes.Array) else bitmap_array(bitmaps)
+        keep.append(arr)
+        q.n = len(bitmaps)
+        q.inputs = ctypes.addressof(arr)
+    q.r_bits = int(r_bits)
+    q.d_out = _ptr(out)
+    q.user_tag = int(tag)
+    q.variant = int(variant)
+    q.out_cap = int(out_cap)
+    q.d_out_len = 0 if out_len is None else _ptr(out_len)
+    if truth is not None:
+        tw = _u64_host(truth_words(truth))
+        keep.append(tw)
+        q.kind = TQ_QUERY_SYMMETRIC
+        q.h_truth = ctypes.addressof(tw)
+    else:
+        q.kind = TQ_QUERY_THRESHOLD
+        q.theta = int(theta)
 
 
 class PreparedQuery:
-    """A query with its host pointer array and tq_query record already built
+    """A query with its host arrays and tq_query record already built
     (marshalled once, reusable across submissions)."""
-    __slots__ = ("ptrs", "n", "r_bits", "theta", "out", "tag", "truth", "rec")
+    __slots__ = ("ptrs", "n", "r_bits", "theta", "out", "tag", "keep", "rec")
 
-    def __init__(self, inputs, r_bits, out, theta=None, truth=None, tag=0):
-        self.ptrs = ptr_array(inputs)
-        self.n = len(inputs)
+    def __init__(self, inputs, r_bits, out, theta=None, truth=None, tag=0, bitmaps=None, variant=0, out_cap=0,
+                 out_len=None):
+        self.keep = []
+        q = TqQuery()
+        _fill_query(q, self.keep, r_bits, out, theta, truth, tag, inputs=inputs, bitmaps=bitmaps, variant=variant,
+                    out_cap=out_cap, out_len=out_len)
+        self.ptrs = self.keep[0] if inputs is not None else None
+        self.n = q.n
         self.r_bits = int(r_bits)
         self.out = _ptr(out)
         self.theta = theta
-        self.truth = _u64_host(truth_words(truth)) if truth is not None else None
         self.tag = int(tag)
-        q = TqQuery()
-        q.n = self.n
-        q.ptrs = ctypes.addressof(self.ptrs)
-        q.r_bits = self.r_bits
-        q.d_out = self.out
-        q.user_tag = self.tag
-        if self.truth is not None:
-            q.kind = TQ_QUERY_SYMMETRIC
-            q.h_truth = ctypes.addressof(self.truth)
-        else:
-            q.kind = TQ_QUERY_THRESHOLD
-            q.theta = theta
         self.rec = q
 
 
@@ -503,26 +536,16 @@ class BatchQueries:
         return self
 
     def __init__(self, specs):
-        """specs: list of dicts with keys inputs, r_bits, out, and theta or truth, optional tag."""
+        """specs: list of dicts with keys r_bits, out, theta or truth, and
+        either inputs (dense device inputs) or bitmaps (registered inputs);
+        optional tag, variant (default TQ_VARIANT_CSA), out_cap and out_len
+        (compressed result)."""
         self.keep = []
         self.arr = (TqQuery * max(1, len(specs)))()
         for i, sp in enumerate(specs):
-            q = self.arr[i]
-            ptrs = ptr_array(sp["inputs"])
-            self.keep.append(ptrs)
-            q.n = len(sp["inputs"])
-            q.ptrs = ctypes.addressof(ptrs)
-            q.r_bits = int(sp["r_bits"])
-            q.d_out = _ptr(sp["out"])
-            q.user_tag = int(sp.get("tag", i))
-            if "truth" in sp:
-                tw = _u64_host(truth_words(sp["truth"]))
-                self.keep.append(tw)
-                q.kind = TQ_QUERY_SYMMETRIC
-                q.h_truth = ctypes.addressof(tw)
-            else:
-                q.kind = TQ_QUERY_THRESHOLD
-                q.theta = int(sp["theta"])
+            _fill_query(self.arr[i], self.keep, sp["r_bits"], sp["out"], sp.get("theta"), sp.get("truth"),
+                        sp.get("tag", i), inputs=sp.get("inputs"), bitmaps=sp.get("bitmaps"),
+                        variant=sp.get("variant", 0), out_cap=sp.get("out_cap", 0), out_len=sp.get("out_len"))
         self.count = len(specs)
 
 
@@ -583,8 +606,17 @@ def tq_batch_wait(batch: int) -> None:
     _check(_lib.tq_batch_wait(batch), "tq_batch_wait")
 
 
+def raw_batch_wait(batch: int) -> int:
+    """Status of tq_batch_wait (the first query that did not complete with TQ_OK)."""
+    return _lib.tq_batch_wait(batch)
+
+
+def tq_batch_cancel(batch: int) -> None:
+    _check(_lib.tq_batch_cancel(batch), "tq_batch_cancel")
+
+
 RECORD_DTYPE = [("user_tag", "<u8"), ("status", "<i4"), ("done", "<u4"), ("t_start_ns", "<u8"),
-                ("t_end_ns", "<u8")]
+                ("t_end_ns", "<u8"), ("variant", "<u4"), ("pad", "<u4")]
 
 
 def tq_batch_records(batch: int, count: int):

@@ -10,40 +10,13 @@
 // threshold (or any truth table) is then applied per position.  Compared with
 // the carry-save counter this spends W times more ALU work per input word,
 // which is the trade the selector weighs.
-#include "tq_internal.h"
+#include "tq_variants.hpp"
 
 namespace tq {
 namespace {
 
-template <int W>
-struct Packed {
-  static constexpr uint64_t E = W == 8 ? 0x0101010101010101ull : 0x0001000100010001ull;
-  static constexpr int F = 64 / W;   // counters per register
-};
-
-template <int W, bool Guard>
-__device__ __forceinline__ void count_inputs(uint64_t (&C)[W], const uint64_t* const* __restrict__ ptrs,
-                                             uint32_t n, uint64_t w, uint64_t nwords) {
-  constexpr uint64_t E = Packed<W>::E;
-  uint32_t i = 0;
-  for (; i + 8 <= n; i += 8) {
-    uint64_t x[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const uint64_t* p = ptrs[i + u];
-      x[u] = (!Guard || w < nwords) ? __builtin_nontemporal_load(p + w) : 0;
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-#pragma unroll
-      for (int k = 0; k < W; ++k) C[k] += (x[u] >> k) & E;
-  }
-  for (; i < n; ++i) {
-    const uint64_t x = (!Guard || w < nwords) ? ptrs[i][w] : 0;
-#pragma unroll
-    for (int k = 0; k < W; ++k) C[k] += (x >> k) & E;
-  }
-}
+using var::count_inputs;
+using var::counter_word;
 
 // W-bit counters per lane; the epilogue compares each counter with theta or
 // looks f up in a table of n + 1 bits (one of the two is used).
@@ -52,8 +25,6 @@ __global__ __launch_bounds__(256) void counter_kernel(const uint64_t* const* __r
                                                      uint64_t nwords, uint64_t tail_mask, uint32_t theta,
                                                      const uint32_t* __restrict__ table, uint64_t* __restrict__ out,
                                                      uint64_t block0) {
-  constexpr int F = Packed<W>::F;
-  constexpr uint64_t M = (W == 8) ? 0xFFull : 0xFFFFull;
   const uint64_t w = (block0 + blockIdx.x) * blockDim.x + threadIdx.x;
   const uint64_t wave_base = w & ~(uint64_t)63;
   uint64_t C[W];
@@ -64,16 +35,7 @@ __global__ __launch_bounds__(256) void counter_kernel(const uint64_t* const* __r
   else
     count_inputs<W, true>(C, ptrs, n, w, nwords);
   if (w >= nwords) return;
-  uint64_t o = 0;
-#pragma unroll
-  for (int k = 0; k < W; ++k) {
-#pragma unroll
-    for (int f = 0; f < F; ++f) {
-      const uint32_t c = (uint32_t)((C[k] >> (W * f)) & M);
-      const uint32_t bit = table ? ((table[c >> 5] >> (c & 31)) & 1u) : (c >= theta ? 1u : 0u);
-      o |= (uint64_t)bit << (k + W * f);
-    }
-  }
+  const uint64_t o = counter_word<W>(C, theta, table);
   out[w] = (w == nwords - 1) ? (o & tail_mask) : o;
 }
 

@@ -267,6 +267,8 @@ const char* tq_status_string(int s) {
     case TQ_ECAPACITY: return "TQ_ECAPACITY: output capacity too small";
     case TQ_EDEVICE: return "TQ_EDEVICE: HIP runtime error";
     case TQ_EBUSY: return "TQ_EBUSY: admission refused, retry";
+    case TQ_ECANCELED: return "TQ_ECANCELED: batch cancelled before the query completed";
+    case TQ_ETIMEDOUT: return "TQ_ETIMEDOUT: batch deadline passed before the query completed";
     case TQ_ENOTSUP: return "TQ_ENOTSUP: not supported";
   }
   return "unknown tq status";
@@ -336,6 +338,14 @@ tq_status tq_set_option(tq_ctx* ctx, int option, int64_t value) {
       return TQ_OK;
     case TQ_OPTION_LOOPED:
       ctx->looped = value ? 1 : 0;
+      return TQ_OK;
+    case TQ_OPTION_BATCH_BYTES:
+      if (value < 1) return TQ_EINVAL;
+      ctx->batch_bytes = (uint64_t)value;
+      return TQ_OK;
+    case TQ_OPTION_BATCH_DEADLINE_US:
+      if (value < 0 || value > (1ll << 40)) return TQ_EINVAL;
+      ctx->batch_deadline_us = (uint64_t)value;
       return TQ_OK;
     case TQ_OPTION_RLE_COUNTERS:
       if (value < 0 || value > 2) return TQ_EINVAL;

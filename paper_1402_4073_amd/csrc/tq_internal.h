@@ -176,6 +176,21 @@ hipError_t launch_rle_encode(const uint64_t* d_dense, uint64_t nwords, uint64_t 
                              int* d_status, hipStream_t stream);
 hipError_t launch_build_index(const uint64_t* d_words, uint64_t len, uint64_t nwords, uint64_t* d_index,
                               int* d_status, hipStream_t stream);
+// Validate n compressed inputs over bitmaps of nwords words (nwords below
+// 2^31, streams non-empty, aligned and not longer than kRleMaxWords); counts
+// those without an index.
+tq_status check_rle_inputs(const tq_rle* inputs, uint32_t n, uint64_t nwords, uint32_t* missing_index);
+// Device descriptors (3 words each: stream, length, index) of n_rle
+// compressed inputs into desc; an input without an index is given the next
+// slot of idx_area (rle_index_bytes each) and its position in *missing.
+// TQ_EINVAL if an index is missing and idx_area is null.
+tq_status rle_describe(const tq_rle* inputs, uint32_t n_rle, uint64_t nwords, uint64_t* idx_area, uint64_t* desc,
+                       std::vector<uint32_t>* missing);
+size_t rle_index_bytes(uint64_t nwords);
+// Indexes of the streams d_descs[d_list[0..count)], one wave per stream in
+// one launch; each is written where its descriptor's index points.
+hipError_t launch_build_indexes(const RleDesc* d_descs, const uint32_t* d_list, uint32_t count, uint64_t nwords,
+                                int* d_status, hipStream_t stream);
 hipError_t launch_set_u64(uint64_t* d_dst, uint64_t value, hipStream_t stream);
 
 // --------------------------------------------------------------- autotuner
@@ -240,6 +255,8 @@ struct tq_ctx {
   int rle_counters = 0;        // TQ_OPTION_RLE_COUNTERS (0: automatic, 1: bit planes, 2: SWAR)
   int autotune = 0;            // TQ_OPTION_AUTOTUNE
   int looped = 1;              // TQ_OPTION_LOOPED
+  uint64_t batch_bytes = 1ull << 30;   // TQ_OPTION_BATCH_BYTES: device bytes of batches in flight
+  uint64_t batch_deadline_us = 0;      // TQ_OPTION_BATCH_DEADLINE_US (0: none)
   void* tuner = nullptr;       // tuned launch shapes by shape class
 };
 
@@ -266,6 +283,17 @@ inline int bit_length(uint64_t x) {
 tq_status record_hip(tq_ctx* ctx, hipError_t e);
 
 void batch_destroy(tq_ctx* ctx);
+
+// Variants (bit v for tq_variant v) that can read every input of a query.
+uint32_t variants_available(const tq_bitmap* in, uint32_t n);
+// The variant the installed selector predicts fastest among `avail`
+// (features outside the training range clamped into it); without a selector
+// the carry-save counter if available, else the hybrid, else the first.
+int select_variant(tq_ctx* ctx, const tq_bitmap* in, uint32_t n, uint64_t r_bits, uint32_t theta, uint32_t avail);
+// Dense input pointers of a carry-save threshold in the order it reads them
+// (by registered cardinality when pruning).
+void csa_input_order(const tq_bitmap* in, uint32_t n, uint64_t r_bits, uint32_t theta, bool prune,
+                     std::vector<const uint64_t*>* dense);
 void selector_destroy(tq_ctx* ctx);
 
 // Device workspace of at least `bytes` (grown with a device synchronisation).

@@ -14,47 +14,12 @@
 // corrected form of the identity), so theta >= N - 2 runs with T = N - theta
 // + 1 <= 3 on the zeros of the inputs and inverts the result.  There a lane
 // stops once every position has seen T zeros, typically after a few inputs.
-#include "tq_internal.h"
+#include "tq_variants.hpp"
 
 namespace tq {
 namespace {
 
-constexpr int kLoopedBlock = 8;   // inputs loaded together, then one decided-test
-
-template <int T, bool Comp, bool Guard>
-__device__ __forceinline__ void looped_accumulate(uint64_t (&B)[T], const uint64_t* const* __restrict__ ptrs,
-                                                  uint32_t n, uint64_t w, uint64_t nwords, uint64_t valid,
-                                                  bool prune) {
-  uint32_t i = 0;
-  bool alive = true;   // this lane has positions that have not reached T
-  for (; i < n; i += kLoopedBlock) {
-    // a lane whose positions are all decided loads nothing more (its planes
-    // are saturated); the wave stops once no lane is left
-    if (alive) {
-      uint64_t x[kLoopedBlock];
-#pragma unroll
-      for (int u = 0; u < kLoopedBlock; ++u) {
-        uint64_t v = 0;
-        if (i + u < n && (!Guard || w < nwords)) {
-          v = __builtin_nontemporal_load(ptrs[i + u] + w);
-          if (Comp) v = ~v;
-        }
-        x[u] = v;
-      }
-#pragma unroll
-      for (int u = 0; u < kLoopedBlock; ++u) {
-#pragma unroll
-        for (int t = T - 1; t >= 1; --t) B[t] |= B[t - 1] & x[u];
-        B[0] |= x[u];
-      }
-    }
-    if (prune) {
-      // positions outside the bitmap count as decided
-      alive = (B[T - 1] | ~valid) != ~(uint64_t)0;
-      if (!__any(alive)) return;
-    }
-  }
-}
+using var::looped_accumulate;
 
 template <int T, bool Comp>
 __global__ __launch_bounds__(64) void looped_kernel(const uint64_t* const* __restrict__ ptrs, uint32_t n,

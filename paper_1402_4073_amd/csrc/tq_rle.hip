@@ -804,10 +804,11 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, int lane) {
   return (uint64_t)lo | ((uint64_t)hi << 32);
 }
 
-__global__ __launch_bounds__(64) void build_index_kernel(const uint64_t* __restrict__ s, uint64_t len,
-                                                         uint64_t nwords, uint64_t* __restrict__ index,
-                                                         int* __restrict__ status) {
-  const int lane = threadIdx.x;
+// One wave walks the marker chain of one stream (the walk is sequential:
+// each marker says where the next one is).
+__device__ __forceinline__ void build_index_wave(const uint64_t* __restrict__ s, uint64_t len, uint64_t nwords,
+                                                 uint64_t* __restrict__ index, int* __restrict__ status) {
+  const int lane = threadIdx.x & 63;
   const uint64_t nchk = (nwords + kTile - 1) / kTile;
   uint64_t base = ~(uint64_t)0;
   uint64_t chunk[4] = {0, 0, 0, 0};
@@ -846,6 +847,21 @@ __global__ __launch_bounds__(64) void build_index_kernel(const uint64_t* __restr
   if (bad || w != nwords || pos != len) {
     if (lane == 0) set_status(status, TQ_EFORMAT);
   }
+}
+
+__global__ __launch_bounds__(64) void build_index_kernel(const uint64_t* __restrict__ s, uint64_t len,
+                                                         uint64_t nwords, uint64_t* __restrict__ index,
+                                                         int* __restrict__ status) {
+  build_index_wave(s, len, nwords, index, status);
+}
+
+// The indexes of several streams of one query at once: workgroup b walks the
+// stream of descriptor list[b] and writes the index that descriptor names.
+__global__ __launch_bounds__(64) void build_indexes_kernel(const RleDesc* __restrict__ descs,
+                                                           const uint32_t* __restrict__ list, uint64_t nwords,
+                                                           int* __restrict__ status) {
+  const RleDesc d = descs[list[blockIdx.x]];
+  build_index_wave(d.words, d.len, nwords, const_cast<uint64_t*>(d.index), status);
 }
 
 uint32_t grid_cap(uint64_t want, uint32_t cap) {
@@ -1052,6 +1068,13 @@ hipError_t launch_build_index(const uint64_t* d_words, uint64_t len, uint64_t nw
                               int* d_status, hipStream_t stream) {
   hipLaunchKernelGGL(build_index_kernel, dim3(1), dim3(64), 0, stream, d_words, len, nwords, d_index,
                      d_status);
+  return hipGetLastError();
+}
+
+hipError_t launch_build_indexes(const RleDesc* d_descs, const uint32_t* d_list, uint32_t count, uint64_t nwords,
+                                int* d_status, hipStream_t stream) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(build_indexes_kernel, dim3(count), dim3(64), 0, stream, d_descs, d_list, nwords, d_status);
   return hipGetLastError();
 }
 

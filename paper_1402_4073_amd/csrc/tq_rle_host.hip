@@ -61,8 +61,6 @@ tq_status staging_error(tq_ctx* ctx, tq_status dflt) {
   return st != TQ_OK ? st : dflt;
 }
 
-namespace {
-
 // Validate compressed inputs; counts those without an index.
 tq_status check_rle_inputs(const tq_rle* inputs, uint32_t n, uint64_t nwords, uint32_t* missing_index) {
   *missing_index = 0;
@@ -77,6 +75,28 @@ tq_status check_rle_inputs(const tq_rle* inputs, uint32_t n, uint64_t nwords, ui
   }
   return TQ_OK;
 }
+
+tq_status rle_describe(const tq_rle* inputs, uint32_t n_rle, uint64_t nwords, uint64_t* idx_area, uint64_t* desc,
+                       std::vector<uint32_t>* missing) {
+  const uint64_t nchk = index_entries(nwords);
+  missing->clear();
+  for (uint32_t j = 0; j < n_rle; ++j) {
+    const uint64_t* index = inputs[j].index;
+    if (!index) {
+      if (!idx_area) return TQ_EINVAL;
+      index = idx_area + (size_t)missing->size() * nchk * 2;
+      missing->push_back(j);
+    }
+    desc[3 * j] = (uint64_t)(uintptr_t)inputs[j].words;
+    desc[3 * j + 1] = inputs[j].n_words;
+    desc[3 * j + 2] = (uint64_t)(uintptr_t)index;
+  }
+  return TQ_OK;
+}
+
+size_t rle_index_bytes(uint64_t nwords) { return (size_t)index_entries(nwords) * 16; }
+
+namespace {
 
 // Bytes of workspace needed for the indexes the caller did not supply.
 tq_status missing_index_bytes(const tq_rle* inputs, uint32_t n_rle, uint64_t nw, size_t* bytes) {
@@ -224,26 +244,28 @@ tq_status run_rle_tiles(tq_ctx* ctx, const tq_rle* inputs, uint32_t n_rle, const
     if (st != TQ_OK) return st;
   }
   std::vector<uint64_t> desc(3 * (size_t)(n_rle ? n_rle : 1), 0);
-  const uint64_t nchk = index_entries(nw);
-  uint32_t built = 0;
-  tq_status st = TQ_OK;
-  for (uint32_t j = 0; j < n_rle; ++j) {
-    const uint64_t* index = inputs[j].index;
-    if (!index) {
-      if (!idx_area) return TQ_EINVAL;
-      uint64_t* dst = idx_area + (size_t)built * nchk * 2;
-      st = record_hip(ctx, launch_build_index(inputs[j].words, inputs[j].n_words, nw, dst, ctx->d_status, stream));
-      if (st != TQ_OK) return st;
-      index = dst;
-      ++built;
-    }
-    desc[3 * j] = (uint64_t)(uintptr_t)inputs[j].words;
-    desc[3 * j + 1] = inputs[j].n_words;
-    desc[3 * j + 2] = (uint64_t)(uintptr_t)index;
-  }
+  // inputs without an index get one in idx_area, all built by one launch
+  std::vector<uint32_t> missing;
+  if (rle_describe(inputs, n_rle, nw, idx_area, desc.data(), &missing) != TQ_OK) return TQ_EINVAL;
   Blob* bd = nullptr;
   const void* d_desc = blob_get(ctx, desc.data(), desc.size(), stream, &bd);
   if (!d_desc) return staging_error(ctx, TQ_EDEVICE);
+  tq_status st = TQ_OK;
+  if (!missing.empty()) {
+    std::vector<uint64_t> list64((missing.size() + 1) / 2, 0);
+    memcpy(list64.data(), missing.data(), missing.size() * 4);
+    Blob* bl = nullptr;
+    const void* d_list = blob_get(ctx, list64.data(), list64.size(), stream, &bl);
+    if (!d_list) return staging_error(ctx, TQ_EDEVICE);
+    st = record_hip(ctx, launch_build_indexes(static_cast<const RleDesc*>(d_desc),
+                                              static_cast<const uint32_t*>(d_list), (uint32_t)missing.size(), nw,
+                                              ctx->d_status, stream));
+    blob_used(ctx, bl, stream);
+    if (st != TQ_OK) {
+      blob_used(ctx, bd, stream);
+      return st;
+    }
+  }
   Blob* bp = nullptr;
   const void* d_dense = nullptr;
   if (n_dense) {

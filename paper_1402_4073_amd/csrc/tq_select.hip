@@ -107,6 +107,55 @@ uint64_t decision_key(const Selector& s, const float* f, uint32_t avail) {
 
 }  // namespace
 
+uint32_t variants_available(const tq_bitmap* in, uint32_t n) {
+  uint32_t avail = 0;
+  for (int v = 0; v < kOut; ++v)
+    if (variant_available(in, n, v)) avail |= 1u << v;
+  return avail;
+}
+
+int select_variant(tq_ctx* ctx, const tq_bitmap* in, uint32_t n, uint64_t r_bits, uint32_t theta, uint32_t avail) {
+  const Selector* s = static_cast<const Selector*>(ctx->selector);
+  float f[kIn], y[kOut];
+  if (s && s->ready && r_bits > 0 && tq_query_features(in, n, r_bits, theta, f) == TQ_OK) {
+    // no variant can be timed here: features outside the training range are
+    // taken at the nearest edge of it
+    for (int i = 0; i < kIn; ++i) f[i] = std::min(std::max(f[i], s->lo[i]), s->hi[i]);
+    host_forward(*s, f, y);
+    int best = -1;
+    for (int v = 0; v < kOut; ++v)
+      if (((avail >> v) & 1u) && (best < 0 || y[v] < y[best])) best = v;
+    if (best >= 0) return best;
+  }
+  if (avail & (1u << TQ_VARIANT_CSA)) return TQ_VARIANT_CSA;
+  if (avail & (1u << TQ_VARIANT_HYBRID)) return TQ_VARIANT_HYBRID;
+  return avail ? __builtin_ctz(avail) : -1;
+}
+
+void csa_input_order(const tq_bitmap* in, uint32_t n, uint64_t r_bits, uint32_t theta, bool prune,
+                     std::vector<const uint64_t*>* dense) {
+  // Inputs in order of registered cardinality (the lower-bound skipping of
+  // section 1, with pruning on): a lane stops reading once each of its
+  // positions has reached theta, which dense inputs read first bring about
+  // sooner, or can no longer reach it with the inputs left, which sparse
+  // inputs read first bring about sooner (the count stays low while the
+  // inputs left run out).  Dense first when theta is below half the expected
+  // count, else sparse first; equal cardinalities keep the caller's order.
+  // The result does not depend on the order.
+  std::vector<uint32_t> order(n);
+  for (uint32_t j = 0; j < n; ++j) order[j] = j;
+  if (prune && r_bits > 0) {
+    double total = 0;
+    for (uint32_t j = 0; j < n; ++j) total += (double)in[j].ones;
+    const bool dense_first = 2.0 * (double)theta < total / (double)r_bits;
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+      return dense_first ? in[a].ones > in[b].ones : in[a].ones < in[b].ones;
+    });
+  }
+  dense->clear();
+  for (uint32_t j = 0; j < n; ++j) dense->push_back(in[order[j]].dense);
+}
+
 void selector_destroy(tq_ctx* ctx) {
   delete static_cast<Selector*>(ctx->selector);
   ctx->selector = nullptr;
@@ -161,28 +210,9 @@ tq_status tq_threshold_variant(tq_ctx* ctx, const tq_bitmap* inputs, uint32_t n,
   std::vector<const uint64_t*> dense;
   std::vector<tq_rle> rle;
   switch (variant) {
-    case TQ_VARIANT_CSA: {
-      // Inputs in order of registered cardinality (the lower-bound skipping
-      // of section 1, with pruning on): a lane stops reading once each of its
-      // positions has reached theta, which dense inputs read first bring
-      // about sooner, or can no longer reach it with the inputs left, which
-      // sparse inputs read first bring about sooner (the count stays low
-      // while the inputs left run out).  Dense first when theta is below half
-      // the expected count, else sparse first; equal cardinalities keep the
-      // caller's order.  The result does not depend on the order.
-      std::vector<uint32_t> order(n);
-      for (uint32_t j = 0; j < n; ++j) order[j] = j;
-      if (ctx->prune && r_bits > 0) {
-        double total = 0;
-        for (uint32_t j = 0; j < n; ++j) total += (double)inputs[j].ones;
-        const bool dense_first = 2.0 * (double)theta < total / (double)r_bits;
-        std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
-          return dense_first ? inputs[a].ones > inputs[b].ones : inputs[a].ones < inputs[b].ones;
-        });
-      }
-      for (uint32_t j = 0; j < n; ++j) dense.push_back(inputs[order[j]].dense);
+    case TQ_VARIANT_CSA:
+      csa_input_order(inputs, n, r_bits, theta, ctx->prune != 0, &dense);
       return tq_threshold(ctx, dense.data(), n, r_bits, theta, d_out, stream);
-    }
     case TQ_VARIANT_COUNTER: {
       for (uint32_t j = 0; j < n; ++j) dense.push_back(inputs[j].dense);
       if (n > TQ_MAX_INPUTS || !d_out || ((uintptr_t)d_out & 7)) return TQ_EINVAL;
@@ -257,9 +287,7 @@ tq_status tq_threshold_auto(tq_ctx* ctx, const tq_bitmap* inputs, uint32_t n, ui
   if (!ctx || !inputs || n == 0) return TQ_EINVAL;
   // a query no variant can read (an input with neither form) is refused
   // whatever the flags, before any prediction or timing
-  uint32_t avail = 0;
-  for (int v = 0; v < kOut; ++v)
-    if (variant_available(inputs, n, v)) avail |= 1u << v;
+  const uint32_t avail = variants_available(inputs, n);
   if (avail == 0) return TQ_EINVAL;
   Selector* s = static_cast<Selector*>(ctx->selector);
   float f[kIn], y[kOut];

@@ -113,16 +113,16 @@ def test_batch_admission_and_errors(ctx, pool):
     base, dpool, nw = pool
     rng = np.random.default_rng(5)
     handles = []
-    for _ in range(4):
+    for _ in range(tq.TQ_BATCH_MAX_INFLIGHT):
         specs, _ = make_specs(rng, base, dpool, nw, 5, with_symmetric=False)
         bq = tq.BatchQueries(specs)
         handles.append((tq.tq_batch_submit(ctx, bq), bq))
     specs, want = make_specs(rng, base, dpool, nw, 5, with_symmetric=False)
     bq = tq.BatchQueries(specs)
     st, h = tq.raw_batch_submit(ctx, bq)
-    assert st == tq.TQ_EBUSY and not h             # every slot is in flight
+    assert st == tq.TQ_EBUSY and not h             # the context holds as many batches as it may
     tq.tq_batch_release(handles[0][0])
-    b = tq.tq_batch_submit(ctx, bq)                # a slot is free again
+    b = tq.tq_batch_submit(ctx, bq)                # room again
     tq.tq_batch_release(b)
     for h, _ in handles[1:]:
         tq.tq_batch_release(h)
