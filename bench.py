@@ -41,6 +41,12 @@ def parse():
                     help="batches in flight at once in the serving client (1..4)")
     ap.add_argument("--serving-shared-stream", action="store_true",
                     help="submit every batch on one stream instead of one stream per slot")
+    ap.add_argument("--serving-selector", default="batch", choices=["batch", "train", "single"],
+                    help="weights of the serving selector: batch = shipped weights trained on batch-path costs "
+                         "(trained here if none are shipped), train = train them here, single = the "
+                         "single-query weights")
+    ap.add_argument("--serving-train-queries", type=int, default=600)
+    ap.add_argument("--serving-eval-queries", type=int, default=200)
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -276,6 +282,77 @@ def bench_rle(args):
     return rec
 
 
+def batch_variant_costs(tq, ctx, table, r, outs, q, avail_rle, stream, copies=16, reps=3):
+    """Cost in seconds per query of each variant when the batch path serves it:
+    a batch of `copies` copies of the query (distinct outputs) with the
+    variant forced, timed with HIP events on the stream around submission
+    and completion (median of `reps` after a warm-up), divided by `copies`;
+    inf where the variant cannot read the inputs."""
+    import numpy as np
+    import torch
+    bm = tq.bitmap_rows(table, q.members)
+    cost = np.full(4, np.inf)
+    for v in range(4):
+        if v == tq.TQ_VARIANT_RLE and not avail_rle:
+            continue
+        bq = tq.BatchQueries.from_prepared(
+            [tq.PreparedQuery(None, r, outs[k], theta=q.theta, bitmaps=bm, variant=v) for k in range(copies)])
+        ts = []
+        for rep in range(reps + 1):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            h = tq.tq_batch_submit(ctx, bq, 0, stream)
+            b.record(stream)
+            b.synchronize()
+            tq.tq_batch_release(h)
+            if rep:
+                ts.append(a.elapsed_time(b))
+        cost[v] = float(np.median(ts)) / 1e3 / copies
+    return cost
+
+
+def train_batch_selector(args, tq, ctx, table, keep_rle, r, outs, pool_n, stream):
+    """The selector trained on what the batch path costs: features of seeded
+    serving-workload queries (other seeds than the timed ones), their
+    per-variant batch costs as targets (log seconds, unavailable variants
+    masked), full-batch Adam with the library's kernels; evaluated on
+    held-out queries timed the same way."""
+    import numpy as np
+    import tqgen
+    from paper_1402_4073_amd import selector as sel
+    ntr, nev = args.serving_train_queries, args.serving_eval_queries
+    qs = tqgen.serving_queries(55, count=ntr + nev, pool=pool_n, rate_qps=1.0)
+    X = np.zeros((len(qs), 8), dtype=np.float32)
+    T = np.zeros((len(qs), 4))
+    t0 = time.perf_counter()
+    for i, q in enumerate(qs):
+        bm = tq.bitmap_rows(table, q.members)
+        X[i] = tq.tq_query_features((bm, len(q.members)), r, q.theta)
+        T[i] = batch_variant_costs(tq, ctx, table, r, outs, q, bool(keep_rle[list(q.members)].all()), stream)
+        if i % 200 == 0:
+            print("batch selector data: %d/%d queries, %.0f s" % (i, len(qs), time.perf_counter() - t0),
+                  file=sys.stderr, flush=True)
+    M = np.isfinite(T).astype(np.float32)
+    logT = np.where(np.isfinite(T), np.log(np.where(np.isfinite(T), T, 1.0)), 0.0).astype(np.float32)
+    mean, std = sel.normalisation(X[:ntr])
+    params, hist = sel.train(ctx, (X[:ntr] - mean) / std, logT[:ntr], M[:ntr], epochs=3000, lr=2e-3)
+    lo, hi = X[:ntr].min(axis=0), X[:ntr].max(axis=0)
+    pred = sel.predict(ctx, params, (X - mean) / std)
+    pred = np.where(M > 0, pred, np.inf)
+    te = slice(ntr, len(qs))
+    chosen = pred[te].argmin(axis=1)
+    Tt = np.where(np.isfinite(T[te]), T[te], np.inf)
+    w = {"params": params.tolist(), "mean": mean.tolist(), "std": std.tolist(), "lo": lo.tolist(),
+         "hi": hi.tolist(), "margin": 0.0, "queries": len(qs), "train": ntr,
+         "context": "batch path (cost per query in a batch of 16 copies)"}
+    ev = {"held_out_queries": nev, "regret": sel.regret(Tt, chosen),
+          "always_csa_regret": sel.regret(Tt, np.zeros(len(chosen), dtype=int)),
+          "best_counts": np.bincount(Tt.argmin(axis=1), minlength=4).tolist(),
+          "pick_counts": np.bincount(chosen, minlength=4).tolist(),
+          "timing_seconds": round(time.perf_counter() - t0, 1)}
+    return w, ev
+
+
 def bench_serving(args):
     """Serving workload: a pool of 8192 uncompressed bitmaps of r=2^23 bits
     (8 GiB, density log-uniform [1e-4, 0.3]); 20000 queries, each over N
@@ -313,11 +390,60 @@ def bench_serving(args):
     else:
         slot_streams = [torch.cuda.Stream(device=dev) for _ in range(slots)]
 
-    # host pointer arrays are marshalled once, outside every timed region
-    specs = [tq.PreparedQuery([rows[m] for m in q.members], r, outs[i % n_out], theta=q.theta, tag=i)
-             for i, q in enumerate(qs)]
+    # Registration, before any timing: cardinality and run count of every
+    # pool bitmap, and its canonical stream with checkpoint index where that
+    # is smaller than the dense words (the hybrid reads each input in its
+    # smaller form; the dense words stay registered for every bitmap).
+    reg_t0 = time.perf_counter()
+    ones_d = torch.zeros(bs.n, dtype=torch.int64, device=dev)
+    runs_d = torch.zeros(bs.n, dtype=torch.int64, device=dev)
+    with torch.cuda.stream(stream):
+        for j in range(bs.n):
+            tq.tq_bitmap_stats(ctx, rows[j], r, ones_d[j:j + 1], runs_d[j:j + 1], stream)
+        streams, offs, lens, index_pool = tq.encode_pool(ctx, rows, r, stream)
+    torch.cuda.synchronize()
+    lens_a = np.array(lens, dtype=np.uint64)
+    keep_rle = lens_a < nw
+    base_s = streams.data_ptr()
+    rle_addr = np.where(keep_rle, base_s + 8 * np.array(offs, dtype=np.uint64), 0).astype(np.uint64)
+    idx_addr = np.where(keep_rle, index_pool.data_ptr() + np.arange(bs.n, dtype=np.uint64) * index_pool.shape[1] * 8,
+                        0).astype(np.uint64)
+    table = tq.bitmap_table(np.array([rw.data_ptr() for rw in rows], dtype=np.uint64), rle_addr,
+                            np.where(keep_rle, lens_a, 0), idx_addr, ones_d.cpu().numpy().astype(np.uint64),
+                            runs_d.cpu().numpy().astype(np.uint64))
+    reg_s = time.perf_counter() - reg_t0
+    from paper_1402_4073_amd import selector as sel
+    batch_weights = os.path.join(ROOT, "paper_1402_4073_amd", "data", "selector_batch_mi355x.json")
+    sel_info = {"weights": args.serving_selector}
+    if args.serving_selector == "single":
+        sel.load_default(ctx)
+    elif args.serving_selector == "batch" and os.path.exists(batch_weights):
+        sel.load_default(ctx, batch_weights)
+        sel_info["weights"] = "batch (shipped)"
+    else:
+        w, ev = train_batch_selector(args, tq, ctx, table, keep_rle, r, outs, bs.n, stream)
+        sel_info["weights"] = "batch (trained in this run)"
+        sel_info["evaluation"] = ev
+        if args.selector_out:
+            os.makedirs(args.selector_out, exist_ok=True)
+            with open(os.path.join(args.selector_out, "selector_batch.json"), "w") as fh:
+                json.dump(w, fh)
+        tq.tq_selector_set(ctx, np.array(w["params"], dtype=np.float32), np.array(w["mean"], dtype=np.float32),
+                           np.array(w["std"], dtype=np.float32), np.array(w["lo"], dtype=np.float32),
+                           np.array(w["hi"], dtype=np.float32), 0.0)
 
-    def run_batched(arrivals, flags):
+    # host arrays are marshalled once, outside every timed region: plain
+    # pointer arrays for the carry-save-only batches, registered inputs with
+    # the selector's choice for the others
+    specs_csa = [tq.PreparedQuery([rows[m] for m in q.members], r, outs[i % n_out], theta=q.theta, tag=i)
+                 for i, q in enumerate(qs)]
+    specs_sel = [tq.PreparedQuery(None, r, outs[i % n_out], theta=q.theta, tag=i,
+                                  bitmaps=tq.bitmap_rows(table, q.members), variant=tq.TQ_VARIANT_AUTO)
+                 for i, q in enumerate(qs)]
+    specs = specs_csa
+    chosen = np.zeros(tq.TQ_SEL_VARIANTS, dtype=np.int64)
+
+    def run_batched(arrivals, flags, count_variants=False):
         """Serve queries arriving at `arrivals` (seconds); returns (elapsed, latencies)."""
         inflight = collections.deque()
         done_at = np.zeros(nq)
@@ -351,6 +477,9 @@ def bench_serving(args):
                     completed += d - seen
                     ent[3] = d
                 if ent[3] == b - a:
+                    if count_variants:
+                        recs = tq.tq_batch_records(h, b - a)
+                        chosen[:] += np.bincount(recs["variant"], minlength=tq.TQ_SEL_VARIANTS)[:tq.TQ_SEL_VARIANTS]
                     tq.tq_batch_release(h)
                     inflight.remove(ent)
         elapsed = time.perf_counter() - t0
@@ -384,23 +513,28 @@ def bench_serving(args):
         return float(np.percentile(np.array(v), p))
 
     zero = [0.0] * nq
-    # warm up both paths (graph instantiation, staging caches)
+    # warm up every path (graph instantiation, staging caches)
     warm = min(nq, 2000)
-    saved = specs
-    specs = saved[:warm]
     nq_full = nq
     nq = warm
-    run_batched([0.0] * warm, 0)
-    run_batched([0.0] * warm, tq.TQ_BATCH_NO_GRAPH)
+    for sp in (specs_csa, specs_sel):
+        specs = sp[:warm]
+        run_batched([0.0] * warm, 0)
+        run_batched([0.0] * warm, tq.TQ_BATCH_NO_GRAPH)
+    specs = specs_csa[:warm]
     run_single([0.0] * warm)
-    specs = saved
     nq = nq_full
     torch.cuda.synchronize()
 
     res = {}
+    specs = specs_csa
     el_g, _ = run_batched(zero, 0)
     el_d, _ = run_batched(zero, tq.TQ_BATCH_NO_GRAPH)
     el_s, _ = run_single(zero)
+    specs = specs_sel
+    el_sg, _ = run_batched(zero, 0, count_variants=True)
+    el_sd, _ = run_batched(zero, tq.TQ_BATCH_NO_GRAPH)
+    specs = specs_csa
     sat_qps = nq / el_g
     # word-column schedule chosen by the autotuner on one full batch, then the
     # saturation run again (the latency runs below keep the default schedule)
@@ -409,23 +543,36 @@ def bench_serving(args):
     el_t, _ = run_batched(zero, 0)
     tq.tq_batch_set_schedule(ctx, 4, 16)
     res["saturation"] = {
+        "batched_selector_graph": {"qps": round(nq / el_sg, 1), "GBps": round(total_bytes / el_sg / 1e9, 1)},
+        "batched_selector_direct": {"qps": round(nq / el_sd, 1), "GBps": round(total_bytes / el_sd / 1e9, 1)},
         "batched_graph": {"qps": round(nq / el_g, 1), "GBps": round(total_bytes / el_g / 1e9, 1)},
         "batched_direct": {"qps": round(nq / el_d, 1), "GBps": round(total_bytes / el_d / 1e9, 1)},
         "per_query_launch": {"qps": round(nq / el_s, 1), "GBps": round(total_bytes / el_s / 1e9, 1)},
         "batched_graph_tuned_schedule": {"qps": round(nq / el_t, 1), "GBps": round(total_bytes / el_t / 1e9, 1),
                                          "items_per_wave": tuned[0], "min_item_work": tuned[1]},
         "default_schedule": {"items_per_wave": 4, "min_item_work": 16},
+        "note": "batched_* without 'selector': every query runs the carry-save variant (pointer arrays); "
+                "batched_selector_*: registered inputs, variant chosen per query by the shipped selector",
     }
+    res["selector_choices"] = {tq.VARIANT_NAMES[v]: int(chosen[v]) for v in range(tq.TQ_SEL_VARIANTS)}
+    res["selector"] = sel_info
+    res["registration"] = {"seconds": round(reg_s, 2), "compressed_forms": int(keep_rle.sum()),
+                           "compressed_words": int(lens_a[keep_rle].sum())}
     res["latency_ms"] = {}
     base_arr = [q.arrival_s for q in qs]      # Poisson with rate 1 query/s
     for frac in (0.5, 0.8, 0.95):
+        # the same offered rates for every path: fractions of the carry-save batched saturation
         rate = frac * sat_qps
         arr = [a / rate for a in base_arr]
+        specs = specs_sel
+        _, lsel = run_batched(arr, 0)
+        specs = specs_csa
         _, lb = run_batched(arr, 0)
         _, ld = run_batched(arr, tq.TQ_BATCH_NO_GRAPH)
         _, ls = run_single(arr)
         res["latency_ms"]["%.2f" % frac] = {
             "offered_qps": round(rate, 1),
+            "batched_selector": {"p50": round(pct(lsel, 50) * 1e3, 3), "p99": round(pct(lsel, 99) * 1e3, 3)},
             "batched": {"p50": round(pct(lb, 50) * 1e3, 3), "p99": round(pct(lb, 99) * 1e3, 3)},
             "batched_direct": {"p50": round(pct(ld, 50) * 1e3, 3), "p99": round(pct(ld, 99) * 1e3, 3)},
             "per_query_launch": {"p50": round(pct(ls, 50) * 1e3, 3), "p99": round(pct(ls, 99) * 1e3, 3)},
@@ -436,14 +583,15 @@ def bench_serving(args):
     tq.tq_destroy(ctx)
     rec = {
         "metric": "batched serving throughput (queries/s) and p50/p99 latency",
-        "value": res["saturation"]["batched_graph"]["qps"],
+        "value": res["saturation"]["batched_selector_graph"]["qps"],
         "unit": "queries/s",
         "n_gpus": 1, "steps": 1, "warmup": 1,
-        "ms_per_step": round(el_g * 1e3, 3),
+        "ms_per_step": round(el_sg * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u64 bitwise", "data": "synthetic (seeded Bernoulli pool resident in HBM)",
         "config": {"workload": "serving: pool 8192 x r=2^23 bits (8 GiB), %d queries, N log-uniform [2,1024], "
-                               "theta uniform [1,N], Poisson arrivals" % nq,
+                               "theta uniform [1,N], Poisson arrivals; variant per query from the shipped "
+                               "selector over registered inputs" % nq,
                    "logical_input_bytes": total_bytes, "max_batch": max_batch, "slots": slots,
                    "shared_stream": bool(args.serving_shared_stream)},
         "serving": res,

@@ -663,6 +663,29 @@ def bitmap_array(bitmaps):
     return arr
 
 
+BITMAP_DTYPE = [("dense", "<u8"), ("rle_words", "<u8"), ("rle_n_words", "<u8"), ("rle_index", "<u8"),
+                ("ones", "<u8"), ("runs", "<u8")]
+
+
+def bitmap_table(dense_addrs, rle_addrs, rle_lens, index_addrs, ones, runs):
+    """numpy table of registered bitmaps laid out as tq_bitmap (address 0 =
+    absent form); rows are picked for a query with bitmap_rows."""
+    import numpy as np
+    t = np.zeros(len(ones), dtype=np.dtype(BITMAP_DTYPE))
+    t["dense"], t["rle_words"], t["rle_n_words"] = dense_addrs, rle_addrs, rle_lens
+    t["rle_index"], t["ones"], t["runs"] = index_addrs, ones, runs
+    return t
+
+
+def bitmap_rows(table, members):
+    """ctypes tq_bitmap array of the given rows of a bitmap_table."""
+    import numpy as np
+    sub = np.ascontiguousarray(table[np.asarray(members)])
+    arr = (TqBitmap * max(1, len(sub)))()
+    ctypes.memmove(ctypes.addressof(arr), sub.ctypes.data, sub.nbytes)
+    return arr
+
+
 def tq_bitmap_stats(ctx: int, dense, r_bits: int, ones_out, runs_out, stream=None) -> None:
     _check(_lib.tq_bitmap_stats(ctx, _ptr(dense), r_bits, _ptr(ones_out), _ptr(runs_out), _stream(stream)),
            "tq_bitmap_stats")

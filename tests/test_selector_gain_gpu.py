@@ -1,0 +1,102 @@
+"""What the trained selector gains over dispatch without it, measured.
+
+The shipped weights were trained on the first 2000 queries of the seeded
+selector workload (r = 2^22 bits, N log-uniform in [2, 4096], density
+log-uniform in [1e-5, 0.5], mean ones-run log-uniform in [1, 4096], theta/N
+uniform in (0, 1]).  This test takes 48 of the queries held out from that
+training, registers each query's bitmaps in both forms, times every variant
+(median of 5 after a warm-up, HIP events on the library's stream) and asks
+the library's own dispatch (tq_threshold_auto, no timing fallback) which
+variant it runs.  Over the set, the selector's summed time must be within
+10 % of the exhaustive best's (the regret target, workload normalisation of
+the paper's section 5.9) and below the summed time of always running the
+carry-save counter, the dispatch without a network.  Every variant's output
+equals the carry-save result word for word, and that result equals the
+oracle on a column sample.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import tqgen
+from paper_1402_4073_amd import binding as tq
+from paper_1402_4073_amd import selector
+
+pytestmark = pytest.mark.gpu
+
+HELD_OUT = range(2000, 2048)
+SAMPLE_COLS = 256
+
+
+def median_ms(fn, reps=5):
+    fn()
+    evs = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        evs.append((a, b))
+    torch.cuda.synchronize()
+    return float(np.median([a.elapsed_time(b) for a, b in evs]))
+
+
+def test_selector_beats_default_dispatch_within_regret():
+    ctx = tq.tq_create(0)
+    try:
+        selector.load_default(ctx)
+        r = tqgen.SELECTOR["r_bits"]
+        nw = (r + 63) // 64
+        iw = tq.tq_rle_index_words(r)
+        qs = tqgen.selector_queries(4, count=HELD_OUT.stop)
+        T = np.zeros((len(HELD_OUT), 4))
+        chosen = np.zeros(len(HELD_OUT), dtype=int)
+        dev = torch.device("cuda:0")
+        for k, qi in enumerate(HELD_OUT):
+            q = qs[qi]
+            print("selector held-out query %d: N=%d theta=%d density=%.2g run=%.1f"
+                  % (qi, q.n, q.theta, q.density, q.mean_run), flush=True)
+            ms = tqgen.markov_density_runlength(q.seed, q.n, r, q.density, q.mean_run)
+            dense = torch.empty((q.n, nw), dtype=torch.int64, device=dev)
+            tqgen.fill_gpu(ms, dense.view(-1))
+            slots = torch.empty((q.n, nw + 2), dtype=torch.int64, device=dev)
+            idx = torch.empty((q.n, iw), dtype=torch.int64, device=dev)
+            lens = torch.zeros(q.n, dtype=torch.int64, device=dev)
+            stats = torch.zeros((q.n, 2), dtype=torch.int64, device=dev)
+            for j in range(q.n):
+                tq.tq_bitmap_stats(ctx, dense[j], r, stats[j, 0:1], stats[j, 1:2])
+                tq.tq_rle_encode(ctx, dense[j], r, slots[j], nw + 2, lens[j:j + 1], idx[j])
+            assert tq.tq_ctx_check(ctx) == 0
+            st, ln = stats.cpu().numpy(), lens.cpu().numpy()
+            arr = (tq.bitmap_array([dict(dense=dense[j], rle=(slots[j], int(ln[j]), idx[j]), ones=int(st[j, 0]),
+                                         runs=int(st[j, 1])) for j in range(q.n)]), q.n)
+            outs = [torch.empty(nw, dtype=torch.int64, device=dev) for _ in range(4)]
+            for v in range(4):
+                T[k, v] = median_ms(lambda: tq.tq_threshold_variant(ctx, arr, r, q.theta, v, outs[v]))
+            sel_out = torch.empty(nw, dtype=torch.int64, device=dev)
+            chosen[k] = tq.tq_threshold_auto(ctx, arr, r, q.theta, sel_out, 0)
+            assert chosen[k] < 4
+            assert tq.tq_ctx_check(ctx) == 0
+            for v in range(1, 4):
+                assert torch.equal(outs[v], outs[0]), (qi, v)
+            assert torch.equal(sel_out, outs[0]), qi
+            # the carry-save result against the oracle on a column range
+            w0 = (q.seed % (nw - SAMPLE_COLS))
+            host = np.stack([ms.words(j, w0, w0 + SAMPLE_COLS) for j in range(q.n)])
+            want = oracle.threshold_cols(host, np.arange(SAMPLE_COLS, dtype=np.uint64), SAMPLE_COLS * 64, q.theta)
+            got = outs[0][w0:w0 + SAMPLE_COLS].cpu().numpy().view(np.uint64)
+            assert np.array_equal(got, want), qi
+            del dense, slots, idx, outs, sel_out
+        torch.cuda.empty_cache()
+        t_best = T.min(axis=1).sum()
+        t_sel = T[np.arange(len(chosen)), chosen].sum()
+        t_csa = T[:, tq.TQ_VARIANT_CSA].sum()
+        regret = t_sel / t_best - 1.0
+        print("selector on %d held-out queries: regret %.4f, %.3fx over always-csa; picks %s, best %s"
+              % (len(chosen), regret, t_csa / t_sel, np.bincount(chosen, minlength=4).tolist(),
+                 np.bincount(T.argmin(axis=1), minlength=4).tolist()), flush=True)
+        assert regret <= 0.10
+        assert t_sel < t_csa
+    finally:
+        tq.tq_destroy(ctx)
