@@ -71,9 +71,10 @@ def copy_calibration():
                                            "bytes_written_per_launch": 1 << 30, "launches": 3}}))
 
 
-def load_traffic(kernel_key: str):
-    """HBM bytes per launch measured by rocprofv3 counters (profiles/traffic.json),
-    or None if not measured for the current source of that kernel."""
+def load_traffic(kernel_key: str, field: str = "bytes_per_launch"):
+    """HBM bytes measured by rocprofv3 counters (profiles/traffic.json): the
+    record's `field`, or None if not measured for the current sources of
+    that kernel."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
@@ -91,7 +92,7 @@ def load_traffic(kernel_key: str):
     h = hashlib.sha256(blob).hexdigest()[:16]
     if rec.get("source_sha") != h:
         return None
-    return rec.get("bytes_per_launch")
+    return rec.get(field)
 
 
 def cpu_baseline(pool_rows, n, nwords, r_bits, queries, target_s, threads=None):
@@ -1004,6 +1005,19 @@ def main():
         "weighted": weighted,
         "autotune": autotune,
     }
+    # HBM bytes the timed (pruned) step moves, per query from rocprofv3
+    # counters on the same sources and data, over the measured step time
+    step_bytes = load_traffic("dense_step/large-pruned", "bytes_per_query") \
+        if args.workload == "large" and args.prune else None
+    if step_bytes:
+        step_s = elapsed / args.steps
+        ach = sum(step_bytes) / step_s / 1e9
+        rec["pruned_step"] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": round(ach / HBM_PEAK_GBS, 4), "traffic_bytes_per_step": sum(step_bytes),
+                              "traffic_bytes_per_query": step_bytes,
+                              "note": "bytes the six queries of the timed step move (FETCH_SIZE + WRITE_SIZE "
+                                      "per dispatch, scaled by a plain copy) over ms_per_step; the logical "
+                                      "`value` counts every input word of every query"}
     if graph:
         rec["graph_replay"] = graph
     if not args.no_cpu_baseline:
