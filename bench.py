@@ -54,6 +54,8 @@ def parse():
                     help="skip the fused-consumer and weighted timings (profiling runs of the roofline kernel)")
     ap.add_argument("--prune", type=int, default=1,
                     help="threshold pruning in the timed pass (the roofline pass never prunes)")
+    ap.add_argument("--no-summaries", action="store_true",
+                    help="default workload only: skip the compact RLE, serving and selector summaries")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
@@ -725,6 +727,94 @@ def bench_selector(args):
     }
 
 
+def selector_summary(args, held_out=range(2000, 2048)):
+    """The shipped selector on queries of the selector workload held out from
+    its training: every variant timed, the
+    library's own dispatch (tq_threshold_auto, no timing fallback) asked for
+    its choice; regret against the exhaustive best and gain over always
+    running the carry-save variant (timings: median of 5 after a warm-up)."""
+    import numpy as np
+    import torch
+    import tqgen
+    from paper_1402_4073_amd import binding as tq
+    from paper_1402_4073_amd import selector as sel
+    ctx = tq.tq_create(0)
+    sel.load_default(ctx)
+    r = tqgen.SELECTOR["r_bits"]
+    nw = (r + 63) // 64
+    iw = tq.tq_rle_index_words(r)
+    qs = tqgen.selector_queries(4, count=held_out.stop)
+    dev = torch.device("cuda:0")
+    T = np.zeros((len(held_out), 4))
+    chosen = np.zeros(len(held_out), dtype=int)
+    t0 = time.perf_counter()
+    for k, qi in enumerate(held_out):
+        q = qs[qi]
+        ms = tqgen.markov_density_runlength(q.seed, q.n, r, q.density, q.mean_run)
+        dense = torch.empty((q.n, nw), dtype=torch.int64, device=dev)
+        tqgen.fill_gpu(ms, dense.view(-1))
+        slots = torch.empty((q.n, nw + 2), dtype=torch.int64, device=dev)
+        idx = torch.empty((q.n, iw), dtype=torch.int64, device=dev)
+        lens = torch.zeros(q.n, dtype=torch.int64, device=dev)
+        stats = torch.zeros((q.n, 2), dtype=torch.int64, device=dev)
+        for j in range(q.n):
+            tq.tq_bitmap_stats(ctx, dense[j], r, stats[j, 0:1], stats[j, 1:2])
+            tq.tq_rle_encode(ctx, dense[j], r, slots[j], nw + 2, lens[j:j + 1], idx[j])
+        st, ln = stats.cpu().numpy(), lens.cpu().numpy()
+        arr = (tq.bitmap_array([dict(dense=dense[j], rle=(slots[j], int(ln[j]), idx[j]), ones=int(st[j, 0]),
+                                     runs=int(st[j, 1])) for j in range(q.n)]), q.n)
+        out = torch.empty(nw, dtype=torch.int64, device=dev)
+        for v in range(4):
+            tq.tq_threshold_variant(ctx, arr, r, q.theta, v, out)
+            evs = []
+            for _ in range(5):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                tq.tq_threshold_variant(ctx, arr, r, q.theta, v, out)
+                b.record()
+                evs.append((a, b))
+            torch.cuda.synchronize()
+            T[k, v] = float(np.median([a.elapsed_time(b) for a, b in evs])) / 1e3
+        chosen[k] = tq.tq_threshold_auto(ctx, arr, r, q.theta, out, 0)
+        del dense, slots, idx
+    if tq.tq_ctx_check(ctx) != 0:
+        raise RuntimeError("device error in the selector summary")
+    tq.tq_destroy(ctx)
+    torch.cuda.empty_cache()
+    reg = sel.regret(T, chosen)
+    return {"queries": len(held_out), "held_out_of": "selector workload (r=2^22, seeded), queries %d-%d"
+            % (held_out.start, held_out.stop - 1),
+            "regret": round(reg["workload"], 4), "per_query_regret": round(reg["per_query_mean"], 4),
+            "gain_over_always_csa": round(float(T[:, 0].sum() / T[np.arange(len(chosen)), chosen].sum()), 3),
+            "picks": np.bincount(chosen, minlength=4).tolist(), "best": np.bincount(T.argmin(axis=1), minlength=4).tolist(),
+            "seconds": round(time.perf_counter() - t0, 1)}
+
+
+def summaries(args):
+    """Compact figures of the RLE, serving and selector workloads for the
+    default run (each also has a full run of its own: --workload ...)."""
+    import copy
+    import torch
+    out = {}
+    a = copy.copy(args)
+    a.steps, a.warmup, a.no_cpu_baseline = 3, 1, True
+    r = bench_rle(a)
+    out["rle"] = {"metric": r["metric"], "value": r["value"], "unit": r["unit"],
+                  "per_query_ms": r["per_query_ms"], "tile_kernel_ms": r["tile_kernel_ms"],
+                  "compressed_input_GBps": r["compressed_input_GBps"],
+                  "roofline": {k: r["roofline"][k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")}}
+    torch.cuda.empty_cache()
+    a = copy.copy(args)
+    a.serving_selector = "batch"
+    sv = bench_serving(a)["serving"]
+    out["serving"] = {"unit": "queries/s", "saturation": {k: v["qps"] for k, v in sv["saturation"].items()
+                                                          if isinstance(v, dict) and "qps" in v},
+                      "latency_ms_at_0.8": sv["latency_ms"]["0.80"], "selector_choices": sv["selector_choices"]}
+    torch.cuda.empty_cache()
+    out["selector"] = selector_summary(args)
+    return out
+
+
 def time_graph_step(torch, one_step, stream, steps):
     """The step's queries captured once into a HIP graph (every array they
     stage was staged by the eager passes on the same stream) and replayed:
@@ -829,6 +919,9 @@ def time_autotune(tq, tqgen, r_large, rows_large, stream, steps):
         ptrs = tq.ptr_array(rows)
         ctx = tq.tq_create(0)
         ent = {"theta": theta}
+        # the launch shapes of the single counter kernel (inputs not split
+        # over workgroups: time_split covers that)
+        tq.tq_set_option(ctx, tq.TQ_OPTION_SPLIT, 0)
         tq.tq_set_option(ctx, tq.TQ_OPTION_AUTOTUNE, 1)
         with torch.cuda.stream(stream):
             tq.raw_threshold(ctx, ptrs, len(rows), r, theta, out.data_ptr(), stream)   # tunes the class
@@ -859,6 +952,46 @@ def time_autotune(tq, tqgen, r_large, rows_large, stream, steps):
         tq.tq_destroy(ctx)
         res[name] = ent
     res["shape_fields"] = "words per lane, waves splitting the inputs, column groups per workgroup, 0"
+    return res
+
+
+def time_split(tq, tqgen, dev, stream, steps):
+    """Short bitmaps with many inputs: the inputs split over workgroups (two
+    kernels, partial counts added by the second) against one counter kernel
+    with at most eight waves per column group, same queries."""
+    import torch
+    res = {}
+    for name, n, r, theta in (("N=5000 r=200 words", 5000, 200 * 64, 1500), ("N=4096 r=2^18", 4096, 1 << 18, 200)):
+        bs = tqgen.bernoulli_loguniform(12, n, r, 1e-4, 0.5)
+        pool = torch.empty((n, bs.nwords), dtype=torch.int64, device=dev)
+        tqgen.fill_gpu(bs, pool.view(-1))
+        rows = [pool[j] for j in range(n)]
+        out = torch.empty(bs.nwords, dtype=torch.int64, device=dev)
+        ptrs = tq.ptr_array(rows)
+        ctx = tq.tq_create(0)
+        reps = max(steps, 200)
+        acc = {"split_us": 0.0, "single_kernel_us": 0.0}
+        with torch.cuda.stream(stream):
+            for _ in range(3):
+                for label, on in (("split_us", 1), ("single_kernel_us", 0)):
+                    tq.tq_set_option(ctx, tq.TQ_OPTION_SPLIT, on)
+                    tq.raw_threshold(ctx, ptrs, n, r, theta, out.data_ptr(), stream)
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    for _ in range(reps):
+                        tq.raw_threshold(ctx, ptrs, n, r, theta, out.data_ptr(), stream)
+                    e1.record(stream)
+                    torch.cuda.synchronize()
+                    acc[label] += e0.elapsed_time(e1) * 1e3 / reps / 3
+        if tq.tq_ctx_check(ctx, stream) != 0:
+            raise RuntimeError("device error in the split timings")
+        tq.tq_destroy(ctx)
+        in_bytes = n * bs.nwords * 8
+        res[name] = {"theta": theta, "input_bytes": in_bytes, **{k: round(v, 2) for k, v in acc.items()},
+                     "split_GBps": round(in_bytes / acc["split_us"] / 1e3, 1),
+                     "single_kernel_GBps": round(in_bytes / acc["single_kernel_us"] / 1e3, 1)}
+        del pool, rows
     return res
 
 
@@ -964,8 +1097,10 @@ def main():
     consumers = None if args.no_consumers else time_consumers(tq, ctx, rows, r, nw, stream, args.steps)
     weighted = None if args.no_consumers else time_weighted(tq, ctx, rows, r, nw, stream, args.steps)
     autotune = None
+    split = None
     if args.workload == "large" and not args.no_consumers:
         autotune = time_autotune(tq, tqgen, r, rows, stream, args.steps)
+        split = time_split(tq, tqgen, dev, stream, args.steps)
     mean_kernel_s = sum(kernel_ms) / len(kernel_ms) / 1e3
     in_bytes_query = n * nw * 8
     out_bytes_query = nw * 8
@@ -1004,6 +1139,7 @@ def main():
         "consumers": consumers,
         "weighted": weighted,
         "autotune": autotune,
+        "split_inputs": split,
     }
     # HBM bytes the timed (pruned) step moves, per query from rocprofv3
     # counters on the same sources and data, over the measured step time
@@ -1025,6 +1161,13 @@ def main():
         # one thread, as the paper's single-threaded Java measurements
         rec["cpu_single_thread"] = cpu_baseline(rows, n, nw, r, queries, args.cpu_seconds / 3, threads=1)
     tq.tq_destroy(ctx)
+    if args.workload == "large" and not args.no_summaries:
+        del pool, rows, out
+        torch.cuda.empty_cache()
+        t0 = time.perf_counter()
+        print("summaries of the other workloads ...", file=sys.stderr, flush=True)
+        rec["other_workloads"] = summaries(args)
+        rec["other_workloads"]["seconds"] = round(time.perf_counter() - t0, 1)
     print(json.dumps(rec), flush=True)
 
 

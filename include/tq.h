@@ -120,6 +120,10 @@ const char* tq_status_string(int status);
                                          starts on the device (0, the default: none); see
                                          tq_batch_submit.  Value in [0, 2^40] */
 
+#define TQ_OPTION_SPLIT 8  /* value 1 (default): dense queries over bitmaps too short to fill the device
+                              split their inputs over workgroups (see tq_threshold); 0: never.
+                              Results are identical either way. */
+
 /* Set a context option; TQ_EINVAL for an unknown option. */
 tq_status tq_set_option(tq_ctx* ctx, int option, int64_t value);
 
@@ -165,6 +169,13 @@ tq_status tq_ctx_check(tq_ctx* ctx, hipStream_t stream);
  * n in [1, TQ_MAX_INPUTS].  theta may be any value: theta == 0 gives all ones
  * on [0, r_bits) and theta > n gives all zeros.  r_bits == 0 writes nothing.
  * d_out: ceil(r_bits/64) device words, overwritten.
+ * Bitmaps too short to fill the device with 64-word column groups (fewer
+ * groups, ceil(r_bits/4096), than compute units) with at least 256 inputs
+ * and 4 MiB of input words are counted in parts of at least 32 inputs on
+ * separate workgroups (TQ_OPTION_SPLIT), whose partial counts (adding binary
+ * counts, section 4.4.2) go through the context's workspace: such calls on
+ * one context must be ordered (one stream, or synchronised by the caller), as
+ * the compressed-input calls.  The same holds for tq_symmetric.
  */
 tq_status tq_threshold(tq_ctx* ctx, const uint64_t* const* ptrs, uint32_t n, uint64_t r_bits,
                        uint32_t theta, uint64_t* d_out, hipStream_t stream);

@@ -197,6 +197,7 @@ TQ_OPTION_AUTOTUNE = 3
 TQ_OPTION_RLE_COUNTERS = 4
 TQ_OPTION_LOOPED = 5
 TQ_OPTION_BATCH_BYTES = 6
+TQ_OPTION_SPLIT = 8
 TQ_OPTION_BATCH_DEADLINE_US = 7
 
 

@@ -211,6 +211,137 @@ __global__ __launch_bounds__(kReduceBlock) void count_reduce_kernel(const T* __r
   }
 }
 
+// Inputs split over workgroups (bitmaps too short to fill the device with
+// column groups, many inputs): adding binary counts, section 4.4.2.
+//
+// Pass 1: one wave per (column group, part of the inputs) counts its part
+// into KP planes and stores them, plane by plane, into the partial area:
+// part[(p * KP + k) * stride + w] for part p, plane k and word w (stride =
+// column groups * 64, so every wave writes whole 512-byte rows).
+template <int KP>
+__global__ __launch_bounds__(64) void dense_part_kernel(const uint64_t* const* __restrict__ ptrs, uint32_t n,
+                                                       uint32_t per, uint64_t nwords, uint64_t* __restrict__ part,
+                                                       uint64_t stride, uint64_t group0) {
+  const int lane = threadIdx.x;
+  const uint32_t p = blockIdx.y;
+  const uint64_t base = (group0 + blockIdx.x) * 64;
+  const uint64_t w = base + lane;
+  const uint32_t i0 = p * per;
+  const uint32_t i1 = i0 + per < n ? i0 + per : n;
+  Vec<1> P[KP];
+#pragma unroll
+  for (int k = 0; k < KP; ++k) P[k].w[0] = 0;
+  if (base + 64 <= nwords)
+    accumulate<KP, 1, false>(P, ptrs, i0, i1, w, nwords);
+  else
+    accumulate<KP, 1, true>(P, ptrs, i0, i1, w, nwords);
+#pragma unroll
+  for (int k = 0; k < KP; ++k)
+    __builtin_nontemporal_store(P[k].w[0], part + ((uint64_t)p * KP + k) * stride + w);
+}
+
+// Pass 2: one workgroup of kCombineWaves waves per column group.  Wave v
+// adds parts v, v + kCombineWaves, ... to its K-plane counter (each part a
+// kp-bit number: a ripple of full adders from plane 0), the waves' counters
+// are added in LDS, and wave 0 applies the epilogue and stores the word.
+constexpr int kCombineWaves = 8;
+
+template <int K>
+__global__ __launch_bounds__(64 * kCombineWaves) void dense_combine_kernel(
+    const uint64_t* __restrict__ part, uint32_t parts, uint32_t kp, uint64_t stride, uint32_t n, uint64_t nwords,
+    uint64_t tail_mask, uint64_t* __restrict__ out, EpiParams epi, uint64_t group0) {
+  extern __shared__ uint64_t lds[];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint64_t w = (group0 + blockIdx.x) * 64 + lane;
+  uint32_t* lds_table = reinterpret_cast<uint32_t*>(lds);
+  uint64_t* red = lds;
+  if (epi.kind == EPI_TABLE) {
+    for (uint32_t t = threadIdx.x; t < epi.table_words; t += blockDim.x) lds_table[t] = epi.table[t];
+    red = lds + (epi.table_words + 1) / 2;
+  }
+  Vec<1> P[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) P[k].w[0] = 0;
+  // two parts per step, their loads issued together
+  for (uint32_t p = wave; p < parts; p += 2 * kCombineWaves) {
+    const uint32_t q = p + kCombineWaves;
+    uint64_t x[K], y[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      x[k] = (uint32_t)k < kp ? part[((uint64_t)p * kp + k) * stride + w] : 0;
+      y[k] = ((uint32_t)k < kp && q < parts) ? part[((uint64_t)q * kp + k) * stride + w] : 0;
+    }
+    uint64_t c = 0, d = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const uint64_t a = P[k].w[0];
+      const uint64_t s1 = xor3(a, x[k], c);
+      c = maj3(a, x[k], c);
+      P[k].w[0] = xor3(s1, y[k], d);
+      d = maj3(s1, y[k], d);
+    }
+  }
+  if (wave != 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) red[((wave - 1) * K + k) * 64 + lane] = P[k].w[0];
+  }
+  __syncthreads();
+  if (wave != 0) return;
+#pragma unroll
+  for (int v = 0; v < kCombineWaves - 1; ++v) {
+    uint64_t c = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const uint64_t a = P[k].w[0], b = red[(v * K + k) * 64 + lane];
+      P[k].w[0] = xor3(a, b, c);
+      c = maj3(a, b, c);
+    }
+  }
+  if (w >= nwords) return;
+  uint64_t v = epilogue<K, 1>(P, epi, n, lds_table).w[0];
+  if (w == nwords - 1) v &= tail_mask;
+  out[w] = v;
+}
+
+typedef void (*PartFn)(const uint64_t* const*, uint32_t, uint32_t, uint64_t, uint64_t*, uint64_t, uint64_t);
+typedef void (*CombineFn)(const uint64_t*, uint32_t, uint32_t, uint64_t, uint32_t, uint64_t, uint64_t, uint64_t*,
+                          EpiParams, uint64_t);
+
+PartFn pick_part(int K) {
+  switch (K) {
+    case 4: return dense_part_kernel<4>;
+    case 5: return dense_part_kernel<5>;
+    case 6: return dense_part_kernel<6>;
+    case 7: return dense_part_kernel<7>;
+    case 8: return dense_part_kernel<8>;
+    case 9: return dense_part_kernel<9>;
+    case 10: return dense_part_kernel<10>;
+    case 11: return dense_part_kernel<11>;
+    case 12: return dense_part_kernel<12>;
+    case 13: return dense_part_kernel<13>;
+    case 16: return dense_part_kernel<16>;
+  }
+  return nullptr;
+}
+
+CombineFn pick_combine(int K) {
+  switch (K) {
+    case 4: return dense_combine_kernel<4>;
+    case 5: return dense_combine_kernel<5>;
+    case 6: return dense_combine_kernel<6>;
+    case 7: return dense_combine_kernel<7>;
+    case 8: return dense_combine_kernel<8>;
+    case 9: return dense_combine_kernel<9>;
+    case 10: return dense_combine_kernel<10>;
+    case 11: return dense_combine_kernel<11>;
+    case 12: return dense_combine_kernel<12>;
+    case 13: return dense_combine_kernel<13>;
+    case 16: return dense_combine_kernel<16>;
+  }
+  return nullptr;
+}
+
 typedef void (*DenseFn)(const uint64_t* const*, uint32_t, uint64_t, uint64_t, uint64_t*, EpiParams, Sink,
                         uint64_t);
 
@@ -332,6 +463,56 @@ hipError_t launch_fill_sink(uint64_t* d_out, uint64_t nwords, uint64_t value, ui
     hipLaunchKernelGGL(fill_sink_kernel, dim3((uint32_t)nb), dim3(kFillBlock), 0, stream, d_out, nwords, value,
                        tail_mask, sink, b0);
     const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+SplitPlan plan_split(uint32_t n, uint64_t nwords, int num_cus) {
+  SplitPlan sp;
+  const uint64_t groups = (nwords + 63) / 64;
+  const uint64_t target = (uint64_t)(num_cus > 0 ? num_cus : 1) * 8;
+  // worth it where even eight waves per column group leave most of the
+  // device idle, the inputs are large enough for their reading to outweigh
+  // a second launch (4 MiB), and every part keeps at least 32 inputs
+  if (groups == 0 || groups * 8 >= target || n < 256 || (uint64_t)n * nwords * 8 < (4ull << 20)) return sp;
+  uint64_t parts = (target + groups - 1) / groups;
+  if (parts > n / 32) parts = n / 32;
+  if (parts > 256) parts = 256;
+  if (parts < 8) return sp;
+  sp.per = (uint32_t)((n + parts - 1) / parts);
+  sp.parts = (n + sp.per - 1) / sp.per;
+  sp.kp = dense_planes_for(sp.per);
+  sp.stride = groups * 64;
+  return sp;
+}
+
+size_t split_workspace_bytes(const SplitPlan& sp) { return (size_t)sp.parts * sp.kp * sp.stride * 8; }
+
+hipError_t launch_dense_split(const SplitPlan& sp, const uint64_t* const* d_ptrs, uint32_t n, uint64_t nwords,
+                              uint64_t tail_mask, uint64_t* d_out, const EpiParams& epi, uint64_t* d_part,
+                              hipStream_t stream) {
+  const int K = dense_planes_for(n);
+  PartFn pf = pick_part(sp.kp);
+  CombineFn cf = pick_combine(K);
+  if (!pf || !cf || sp.parts == 0 || sp.parts > 65535) return hipErrorInvalidValue;
+  const uint64_t groups = sp.stride / 64;
+  // grid x below 2^31 work-items per launch for both passes
+  const uint64_t per_launch = kMaxLaunchItems / (64ull * kCombineWaves);
+  for (uint64_t g0 = 0; g0 < groups; g0 += per_launch) {
+    const uint64_t ng = groups - g0 < per_launch ? groups - g0 : per_launch;
+    hipLaunchKernelGGL(pf, dim3((uint32_t)ng, sp.parts), dim3(64), 0, stream, d_ptrs, n, sp.per, nwords, d_part,
+                       sp.stride, g0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  size_t lds = (size_t)(kCombineWaves - 1) * K * 64 * 8;
+  if (epi.kind == EPI_TABLE) lds += ((size_t)epi.table_words + 1) / 2 * 8;
+  for (uint64_t g0 = 0; g0 < groups; g0 += per_launch) {
+    const uint64_t ng = groups - g0 < per_launch ? groups - g0 : per_launch;
+    hipLaunchKernelGGL(cf, dim3((uint32_t)ng), dim3(64 * kCombineWaves), lds, stream, d_part, sp.parts, sp.kp,
+                       sp.stride, n, nwords, tail_mask, d_out, epi, g0);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

@@ -339,6 +339,9 @@ tq_status tq_set_option(tq_ctx* ctx, int option, int64_t value) {
     case TQ_OPTION_LOOPED:
       ctx->looped = value ? 1 : 0;
       return TQ_OK;
+    case TQ_OPTION_SPLIT:
+      ctx->split = value ? 1 : 0;
+      return TQ_OK;
     case TQ_OPTION_BATCH_BYTES:
       if (value < 1) return TQ_EINVAL;
       ctx->batch_bytes = (uint64_t)value;
@@ -487,6 +490,19 @@ tq_status run_dense(tq_ctx* ctx, const uint64_t* const* ptrs, uint32_t n, uint64
     blob_used(ctx, pb, stream);
     if (tb) blob_used(ctx, tb, stream);
     return st;
+  }
+  // short bitmaps with many inputs: the inputs are split over workgroups
+  // and their partial counts added by a second kernel (no consumers)
+  if (!fused && ctx->split) {
+    const SplitPlan sp = plan_split(n, nw, ctx->num_cus);
+    if (sp.parts) {
+      uint64_t* part = static_cast<uint64_t*>(workspace(ctx, split_workspace_bytes(sp), stream));
+      if (!part) return staging_error(ctx, TQ_ENOMEM);
+      tq_status st = record_hip(ctx, launch_dense_split(sp, dp, n, nw, tmask, d_out, epi, part, stream));
+      blob_used(ctx, pb, stream);
+      if (tb) blob_used(ctx, tb, stream);
+      return st;
+    }
   }
   const DenseConfig cfg = dense_shape(
       ctx, n, nw, epi, aligned16,

@@ -87,6 +87,22 @@ hipError_t launch_dense(const DenseConfig& cfg, const uint64_t* const* d_ptrs, u
 hipError_t launch_fill(uint64_t* d_out, uint64_t nwords, uint64_t value, uint64_t tail_mask,
                        hipStream_t stream);
 
+// Inputs split over workgroups (adding binary counts, section 4.4.2): for
+// bitmaps too short to fill the device with column groups, `parts` parts of
+// `per` inputs each are counted by their own waves into kp-plane partial
+// counters in workspace (split_workspace_bytes), which a second kernel adds
+// before the epilogue.  parts == 0: not worth it for this shape.
+struct SplitPlan {
+  uint32_t parts = 0, per = 0;
+  int kp = 0;
+  uint64_t stride = 0;   // words per partial plane (column groups * 64)
+};
+SplitPlan plan_split(uint32_t n, uint64_t nwords, int num_cus);
+size_t split_workspace_bytes(const SplitPlan& sp);
+hipError_t launch_dense_split(const SplitPlan& sp, const uint64_t* const* d_ptrs, uint32_t n, uint64_t nwords,
+                              uint64_t tail_mask, uint64_t* d_out, const EpiParams& epi, uint64_t* d_part,
+                              hipStream_t stream);
+
 // Saturating counters for theta <= 3, or theta >= n - 2 on the complemented
 // inputs (Looped, section 4.5; complement identity, section 2.3).
 bool looped_applies(uint32_t n, uint32_t theta, uint32_t* t, bool* comp);
@@ -255,6 +271,7 @@ struct tq_ctx {
   int rle_counters = 0;        // TQ_OPTION_RLE_COUNTERS (0: automatic, 1: bit planes, 2: SWAR)
   int autotune = 0;            // TQ_OPTION_AUTOTUNE
   int looped = 1;              // TQ_OPTION_LOOPED
+  int split = 1;               // TQ_OPTION_SPLIT
   uint64_t batch_bytes = 1ull << 30;   // TQ_OPTION_BATCH_BYTES: device bytes of batches in flight
   uint64_t batch_deadline_us = 0;      // TQ_OPTION_BATCH_DEADLINE_US (0: none)
   void* tuner = nullptr;       // tuned launch shapes by shape class
