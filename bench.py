@@ -213,6 +213,21 @@ def bench_rle(args):
             b.record(stream)
             torch.cuda.synchronize()
             sym_ms[name] = round(a.elapsed_time(b) / args.steps, 4)
+    # the same queries with no checkpoint index supplied: the library builds
+    # the missing indexes (one launch, one wave per stream) into its
+    # workspace before the tile kernel
+    noidx = [(pool[offs[j]:], lens[j], None) for j in range(n)]
+    noidx_ms = {}
+    with torch.cuda.stream(stream):
+        for t in thetas:
+            tq.tq_threshold_rle_dense(ctx, noidx, r, t, dout, stream)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(args.steps):
+                tq.tq_threshold_rle_dense(ctx, noidx, r, t, dout, stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+            noidx_ms[str(t)] = round(a.elapsed_time(b) / args.steps, 4)
     # fused consumer: the count of each threshold result, nothing stored
     count_ms = {}
     cnt = torch.zeros(1, dtype=torch.int64, device="cuda:0")
@@ -252,6 +267,7 @@ def bench_rle(args):
         "tile_kernel_ms": [round(sum(tile_ms[i::q]) / args.steps, 4) for i in range(q)],
         "symmetric_query_ms": sym_ms,
         "count_only_query_ms": count_ms,
+        "no_index_dense_query_ms": noidx_ms,
         "roofline": {"bound": "hbm", "achieved": round(alg / tile_s / 1e9, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(alg / tile_s / 1e9 / HBM_PEAK_GBS, 4),
                      "traffic": load_traffic("rle_tile_kernel/rle-thresholds"),
@@ -801,6 +817,7 @@ def summaries(args):
     r = bench_rle(a)
     out["rle"] = {"metric": r["metric"], "value": r["value"], "unit": r["unit"],
                   "per_query_ms": r["per_query_ms"], "tile_kernel_ms": r["tile_kernel_ms"],
+                  "no_index_dense_query_ms": r["no_index_dense_query_ms"],
                   "compressed_input_GBps": r["compressed_input_GBps"],
                   "roofline": {k: r["roofline"][k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")}}
     torch.cuda.empty_cache()
