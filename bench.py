@@ -271,7 +271,7 @@ def bench_rle(args):
         "roofline": {"bound": "hbm", "achieved": round(alg / tile_s / 1e9, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(alg / tile_s / 1e9 / HBM_PEAK_GBS, 4),
                      "traffic": load_traffic("rle_tile_kernel/rle-thresholds"),
-                     "kernel": "rle_tile_kernel (theta 2: 3 saturating planes; 64: 8; 256: 10 planes)",
+                     "kernel": "rle_tile_kernel (bit_length(theta - 1) exact planes and a sticky one: theta 2: 2 planes; 64: 7; 256: 9)",
                      "mean_launch_us": round(tile_s * 1e6, 2),
                      "alg_bytes_per_launch": alg,
                      "alg_bytes_note": "all compressed input words + one index entry per tile per input + dense output"},

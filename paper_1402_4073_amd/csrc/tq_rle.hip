@@ -67,6 +67,21 @@ __device__ __forceinline__ T wave_inclusive_scan(T v) {
   return v;
 }
 
+// The same for 32-bit values, with the permute indices derived from a lane
+// number the compiler cannot hoist: in the tile loop the hoisted indices of
+// the six steps would stay live across the stream walks and spill.
+template <>
+__device__ __forceinline__ int32_t wave_inclusive_scan<int32_t>(int32_t v) {
+  int lane = threadIdx.x & 63;
+  asm volatile("" : "+v"(lane));
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int32_t o = __builtin_amdgcn_ds_bpermute((lane - off) << 2, v);
+    if (lane >= off) v += o;
+  }
+  return v;
+}
+
 template <typename T, int WAVES>
 __device__ __forceinline__ T block_exclusive_scan(T v, T* wave_tot, T* total) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -249,8 +264,12 @@ struct SectorReader {
     const uint32_t g = off + p;
     const uint32_t sec = g >> 3;
     if (sec != cur) {
-      const uint4* q = reinterpret_cast<const uint4*>(base + (uint64_t)sec * 8);
-      const uint4 v0 = q[0], v1 = q[1], v2 = q[2], v3 = q[3];
+      // global address space: the loads wait on the vector memory counter
+      // only, not on LDS operations still in flight
+      typedef unsigned int U32x4 __attribute__((ext_vector_type(4)));
+      typedef const __attribute__((address_space(1))) U32x4 GlobalSector;
+      GlobalSector* q = (GlobalSector*)(base + (uint64_t)sec * 8);
+      const U32x4 v0 = q[0], v1 = q[1], v2 = q[2], v3 = q[3];
       b0 = v0.x | ((uint64_t)v0.y << 32);
       b1 = v0.z | ((uint64_t)v0.w << 32);
       b2 = v1.x | ((uint64_t)v1.y << 32);
@@ -280,13 +299,13 @@ struct DirectReader {
 // Decode the marker at wk.pos and check it against the stream and the bitmap;
 // on success w1 / w2 are the ends of its fill and literal runs.
 template <typename Reader>
-__device__ __forceinline__ bool read_marker(const RleDesc& dsc, Reader& rd, const Walk& wk, uint32_t nwords,
+__device__ __forceinline__ bool read_marker(uint32_t len, Reader& rd, const Walk& wk, uint32_t nwords,
                                             uint64_t& m, uint32_t& w1, uint32_t& w2) {
-  if (wk.pos >= dsc.len) return false;
+  if (wk.pos >= len) return false;
   m = rd.at(wk.pos);
   const uint64_t run = (m >> 1) & 0xFFFFFFFFull, lits = m >> 33;
   const uint64_t e1 = (uint64_t)wk.w + run, e2 = e1 + lits;
-  if (e2 > nwords || lits > dsc.len - wk.pos - 1) return false;
+  if (e2 > nwords || lits > len - wk.pos - 1) return false;
   w1 = (uint32_t)e1;
   w2 = (uint32_t)e2;
   return true;
@@ -297,26 +316,26 @@ __device__ __forceinline__ bool read_marker(const RleDesc& dsc, Reader& rd, cons
 // the column counters right away (the one-pass form of a tile).  On return
 // `next` is the entry state of the following tile (the marker covering t1).
 template <typename Add, typename Reader>
-__device__ __forceinline__ void walk_markers(const RleDesc& dsc, Reader& rd, Walk wk, uint32_t t0, uint32_t t1,
+__device__ __forceinline__ void walk_markers(uint32_t len, Reader& rd, Walk wk, uint32_t t0, uint32_t t1,
                                              uint32_t nwords, int32_t* kd, int* status, bool lits,
                                              const Add& add, Walk& next) {
   next = wk;
   while (wk.w < t1) {
     uint64_t m;
     uint32_t w1, w2;
-    if (!read_marker(dsc, rd, wk, nwords, m, w1, w2)) { set_status(status, TQ_EFORMAT); break; }
+    if (!read_marker(len, rd, wk, nwords, m, w1, w2)) { set_status(status, TQ_EFORMAT); break; }
     if ((m & 1) && w1 > wk.w) {
       const uint32_t a = wk.w > t0 ? wk.w : t0, b = w1 < t1 ? w1 : t1;
       if (a < b) {
         atomicAdd(&kd[a - t0], 1);
-        atomicAdd(&kd[b - t0], -1);
+        atomicSub(&kd[b - t0], 1);
       }
     }
     if (w2 > w1) {
       const uint32_t a = w1 > t0 ? w1 : t0, b = w2 < t1 ? w2 : t1;
       if (a < b) {
         atomicAdd(&kd[a - t0], 65536);
-        atomicAdd(&kd[b - t0], -65536);
+        atomicSub(&kd[b - t0], 65536);
         if (lits)
           for (uint32_t col = a; col < b; ++col)
             add((int)(col - t0), rd.at(wk.pos + 1 + (col - w1)));
@@ -335,12 +354,12 @@ __device__ __forceinline__ void walk_markers(const RleDesc& dsc, Reader& rd, Wal
 
 // Literal words of the undecided columns of [t0, t1) into the LDS counters.
 template <typename Add, typename Reader>
-__device__ __forceinline__ void walk_literals(const RleDesc& dsc, Reader& rd, Walk wk, uint32_t t0, uint32_t t1,
+__device__ __forceinline__ void walk_literals(uint32_t len, Reader& rd, Walk wk, uint32_t t0, uint32_t t1,
                                               uint32_t nwords, const int32_t* kd, const Add& add) {
   while (wk.w < t1) {
     uint64_t m;
     uint32_t w1, w2;
-    if (!read_marker(dsc, rd, wk, nwords, m, w1, w2)) break;
+    if (!read_marker(len, rd, wk, nwords, m, w1, w2)) break;
     const uint32_t a = w1 > t0 ? w1 : t0, b = w2 < t1 ? w2 : t1;
     for (uint32_t col = a; col < b; ++col) {
       const int c = (int)(col - t0);
@@ -380,15 +399,15 @@ __device__ __forceinline__ void for_dense_words(const uint64_t* const* dense, ui
 // evaluated on k plus the counted dirty bits.  Swar = true: SWAR column
 // counters, every tile in one pass; otherwise K bit-sliced planes in the
 // form Form: kSaturating makes the top plane sticky (see ripple_lds_sat), so
-// K = bit_length(theta) + 1 planes suffice for a threshold, and
+// K = bit_length(theta - 1) + 1 planes suffice for a threshold, and
 // bit_length(tail_from) + 1 for a symmetric f constant from tail_from on;
 // kParityPlane (the parity function and its complement) keeps one plane, the
-// count modulo 2.  With K <= 4 planes (K <= 7 for plain thresholds, K <= 5
+// count modulo 2.  With K <= 4 planes (K <= 9 for plain thresholds, K <= 5
 // for symmetric functions) the kernel is built for 8 waves per SIMD, which
-// its LDS footprint allows, at the cost of 13 to 16 spilled registers,
-// reloaded once per tile (measured: faster there, where literal words are
-// counted; level or slower for larger K, where the fills decide most columns
-// or the spills grow).
+// its LDS footprint allows; the plain-threshold builds fit in those 64
+// registers without spilling (each lane keeps only its stream's length and
+// reader, and is entered through the index once per range), the others
+// spill a few registers, reloaded once per tile.
 //
 // Fused = true: consumers of each result word (sink): AND with a filter, and a
 // count; each thread sums the popcounts of its words over the range, and each
@@ -399,7 +418,7 @@ __device__ __forceinline__ void for_dense_words(const uint64_t* const* dense, ui
 // n_dense and keep no registers for it.
 template <int K, bool Sym, bool Swar, int Form = kFullPlanes, bool Fused = false, bool Hybrid = false>
 __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(
-    ((Form != kFullPlanes && K <= 4) || (!Swar && !Fused && !Hybrid && K <= (Sym ? 5 : 7))) ? 8 : 6))) void rle_tile_kernel(
+    ((Form != kFullPlanes && K <= 4) || (!Swar && !Fused && !Hybrid && K <= (Sym ? 5 : 9))) ? 8 : 6))) void rle_tile_kernel(
     const RleDesc* __restrict__ descs, uint32_t n_rle, const uint64_t* const* __restrict__ dense,
     uint32_t n_dense_arg, uint32_t nwords, uint64_t tail_mask, uint32_t theta, const RleSym* __restrict__ sym,
     uint32_t tiles_per_group,
@@ -438,15 +457,20 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(
   const uint32_t tile_end = tiles - tile_begin > tiles_per_group ? tile_begin + tiles_per_group : tiles;
   const int tid = threadIdx.x;
   const bool own = (uint32_t)tid < n_rle;   // this lane carries input tid
-  RleDesc mine = {};
+  // The lane's stream is entered once, at the range start; a bad entry
+  // leaves the lane out of the whole range (the launch reports TQ_EFORMAT).
+  uint32_t my_len = 0;
   Walk carry = {0, 0};
   bool carry_ok = false;
   SectorReader rd;
   DirectReader rx;
   rd.reset(nullptr, 0);
   if (own) {
-    mine = descs[tid];
+    const RleDesc mine = descs[tid];
+    my_len = (uint32_t)mine.len;
     rd.reset(mine.words, mine.len);
+    carry_ok = seek(mine, tile_begin, tile_begin * kTile, carry);
+    if (!carry_ok) set_status(status, TQ_EFORMAT);
   }
   // Tiles whose literal words are mostly needed are done in one pass (the
   // marker walk adds every literal word to the counters), saving the second
@@ -464,25 +488,15 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(
     __syncthreads();
 
     // 1. markers only: difference array of (ones fills) + 65536 * (dirty)
-    Walk entry = {0, 0};
-    bool entry_ok = false;
-    if (own) {
-      if (carry_ok) {
-        entry = carry;
-        entry_ok = true;
-      } else {
-        entry_ok = seek(mine, tile, t0, entry);
-        if (!entry_ok) set_status(status, TQ_EFORMAT);
-      }
-      if (entry_ok) walk_markers(mine, rd, entry, t0, t1, nwords, kd, status, one_pass, add, carry);
-      carry_ok = entry_ok;
-    }
+    const Walk entry = carry;
+    const bool entry_ok = carry_ok;
+    if (entry_ok) walk_markers(my_len, rd, entry, t0, t1, nwords, kd, status, one_pass, add, carry);
     for (uint32_t j = tid + kTileThreads; j < n_rle; j += kTileThreads) {
       const RleDesc dsc = descs[j];
       Walk wk, unused;
       if (!seek(dsc, tile, t0, wk)) { set_status(status, TQ_EFORMAT); continue; }
       rx.reset(dsc.words, dsc.len);
-      walk_markers(dsc, rx, wk, t0, t1, nwords, kd, status, one_pass, add, unused);
+      walk_markers((uint32_t)dsc.len, rx, wk, t0, t1, nwords, kd, status, one_pass, add, unused);
     }
     __syncthreads();
 
@@ -513,19 +527,22 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(
 
     // 3. literal words of undecided columns into the per-column LDS counters
     if (walk_again) {
-      if (own && entry_ok) walk_literals(mine, rd, entry, t0, t1, nwords, kd, add);
+      if (entry_ok) walk_literals(my_len, rd, entry, t0, t1, nwords, kd, add);
       for (uint32_t j = tid + kTileThreads; j < n_rle; j += kTileThreads) {
         const RleDesc dsc = descs[j];
         Walk wk;
         if (!seek(dsc, tile, t0, wk)) continue;
         rx.reset(dsc.words, dsc.len);
-        walk_literals(dsc, rx, wk, t0, t1, nwords, kd, add);
+        walk_literals((uint32_t)dsc.len, rx, wk, t0, t1, nwords, kd, add);
       }
     }
     __syncthreads();
 
     // 4. one column per thread: decide, or count and compare
-    const int c = tid;
+    // (the column's LDS addresses are derived here, not kept live across the
+    // walks, where the registers are needed)
+    int c = tid;
+    asm volatile("" : "+v"(c));
     if (c < (int)(t1 - t0)) {
       const int32_t v = kd[c];
       int k, d;
@@ -890,11 +907,14 @@ TileFn pick_tile_k(int K) {
   return nullptr;
 }
 
-// thresholds with bit_length(theta) exact planes and a sticky one, or
+// thresholds with bit_length(theta - 1) exact planes and a sticky one, or
 // symmetric functions with bit_length(tail_from) exact planes and a sticky one
 template <bool Sym, bool Fused, bool Hybrid>
 TileFn pick_sat_k(int K) {
   switch (K) {
+    case 1:
+      if constexpr (!Sym) return rle_tile_kernel<1, false, false, kSaturating, Fused, Hybrid>;
+      return nullptr;
     case 2: return rle_tile_kernel<2, Sym, false, kSaturating, Fused, Hybrid>;
     case 3: return rle_tile_kernel<3, Sym, false, kSaturating, Fused, Hybrid>;
     case 4: return rle_tile_kernel<4, Sym, false, kSaturating, Fused, Hybrid>;
@@ -931,11 +951,14 @@ TileChoice choose_tile(int K, uint32_t theta, const RleSym* sym, bool swar) {
   }
   c.fn = sym ? pick_tile_k<true, Fused, Hybrid>(K) : pick_tile_k<false, Fused, Hybrid>(K);
   c.key = K + (sym ? 17 : 0);
-  // A threshold compares each column's count with theta - k <= theta, so
-  // bit_length(theta) exact planes and a sticky one decide it: less LDS per
-  // workgroup, and more workgroups per CU, when that is fewer planes.
+  // A threshold asks of an undecided column whether its counted bits exceed
+  // a = theta - k - 1 < theta.  Planes exact below 2^(K-1) and a sticky top
+  // plane ("at least 2^(K-1)") answer that whenever 2^(K-1) > theta - 1, so
+  // bit_length(theta - 1) exact planes and a sticky one decide it (theta = 1:
+  // the sticky plane alone, "at least one"): less LDS per workgroup, and more
+  // workgroups per CU, when that is fewer planes.
   if (!sym && theta >= 1) {
-    const int ks = bit_length(theta) + 1;
+    const int ks = bit_length(theta - 1) + 1;
     if (ks < K && ks <= 13) {
       c.K = ks;
       c.fn = pick_sat_k<false, Fused, Hybrid>(ks);
