@@ -438,7 +438,7 @@ def test_more_inputs_than_lanes(ctx, tiles_option, tiles):
 
 @pytest.mark.parametrize("n_rle,n_dense,tiles", [(300, 0, 0), (300, 0, 2), (40, 30, 0), (600, 0, 0)])
 def test_threshold_counts_beyond_narrow_counters(ctx, tiles_option, n_rle, n_dense, tiles):
-    """Small thresholds keep bit_length(theta) exact counter planes and a
+    """Small thresholds keep bit_length(theta - 1) exact counter planes and a
     sticky one, so columns where hundreds of inputs are dirty overflow the
     exact planes many times over: every theta around the powers of two (and
     its complement-side neighbours) must still equal the oracle, with dense
@@ -461,7 +461,8 @@ def test_threshold_counts_beyond_narrow_counters(ctx, tiles_option, n_rle, n_den
     inputs, keep = rle_inputs(ctx, dense[:n_rle], r)
     drows = [to_dev(d) for d in dense[n_rle:]]
     n = n_rle + n_dense
-    for theta in (1, 2, 3, 4, 5, 7, 8, 9, 15, 16, 17, 31, 32, 63, 64, 65, 127, 128, n // 2, n - 1, n):
+    for theta in (1, 2, 3, 4, 5, 7, 8, 9, 15, 16, 17, 31, 32, 63, 64, 65, 127, 128, 129, 255, 256, 257,
+                  n // 2, n - 1, n):
         out = empty_words(nw)
         if n_dense:
             tq.tq_threshold_hybrid(ctx, inputs, drows, r, theta, out)
