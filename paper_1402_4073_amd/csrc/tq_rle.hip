@@ -812,56 +812,134 @@ __global__ void enc_index_kernel(EncArgs a, uint64_t nchk) {
 }
 
 // ------------------------------------------------------ index building
-// One wave per stream walks its marker chain.  The stream is pulled in
-// 256-word chunks (four words per lane, coalesced); each marker is read with
-// readlane from the chunk, so the walk itself is scalar work.
+// One wave per stream decodes the stream's markers 64 words at a time.  A
+// chunk is one coalesced load (the next one is requested before the current
+// one is decoded).  The markers of a chunk form a chain: each says where the
+// next one is, one word further plus its literal count.  With next(i) = i +
+// 1 + literals(word i) for every lane i (64: not in this chunk), the powers
+// next^(2^b) follow from five rounds of cross-lane permutes (pointer
+// doubling), and lane m composes them along the bits of m to find the
+// position of the chunk's m-th marker; the words the markers cover (run +
+// literals) are summed along the chain by the same doubling, which gives
+// each marker's first uncompressed word.  The checkpoints
+// a marker covers (multiples of kTile in [start, end)) are its index
+// entries.  Chunks that hold only literal words are skipped.
 __device__ __forceinline__ uint64_t readlane64(uint64_t v, int lane) {
   const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, lane);
   const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
   return (uint64_t)lo | ((uint64_t)hi << 32);
 }
 
-// One wave walks the marker chain of one stream (the walk is sequential:
-// each marker says where the next one is).
+// value v of lane src (src in [0, 63]); every lane of the wave takes part
+__device__ __forceinline__ uint32_t lane_get(uint32_t v, uint32_t src) {
+  return (uint32_t)__builtin_amdgcn_ds_bpermute((int)(src << 2), (int)v);
+}
+__device__ __forceinline__ uint64_t lane_get64(uint64_t v, uint32_t src) {
+  return (uint64_t)lane_get((uint32_t)v, src) | ((uint64_t)lane_get((uint32_t)(v >> 32), src) << 32);
+}
+
+typedef const __attribute__((address_space(1))) uint64_t GlobalWord;
+
 __device__ __forceinline__ void build_index_wave(const uint64_t* __restrict__ s, uint64_t len, uint64_t nwords,
                                                  uint64_t* __restrict__ index, int* __restrict__ status) {
-  const int lane = threadIdx.x & 63;
+  const uint32_t lane = threadIdx.x & 63;
   const uint64_t nchk = (nwords + kTile - 1) / kTile;
-  uint64_t base = ~(uint64_t)0;
-  uint64_t chunk[4] = {0, 0, 0, 0};
-  uint64_t pos = 0, w = 0, c = 0;
-  bool bad = false;
-  while (pos < len) {
-    if (base == ~(uint64_t)0 || pos >= base + 256) {
-      base = pos;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const uint64_t p = base + (uint64_t)q * 64 + lane;
-        chunk[q] = p < len ? s[p] : 0;
-      }
-    }
-    const uint64_t off = pos - base;
-    const int q = (int)(off >> 6);
-    const int ln = (int)(off & 63);
-    uint64_t m;
-    if (q == 0) m = readlane64(chunk[0], ln);
-    else if (q == 1) m = readlane64(chunk[1], ln);
-    else if (q == 2) m = readlane64(chunk[2], ln);
-    else m = readlane64(chunk[3], ln);
-    const uint64_t run = (m >> 1) & 0xFFFFFFFFull, lits = m >> 33;
-    const uint64_t end = w + run + lits;
-    if (end > nwords || lits > len - pos - 1) { bad = true; break; }
-    while (c < nchk && c * kTile < end) {
-      if (lane == 0) {
-        index[2 * c] = pos;
-        index[2 * c + 1] = w;
-      }
-      ++c;
-    }
-    pos += 1 + lits;
-    w = end;
+  if (len == 0) {   // only an empty bitmap has an empty stream (and no checkpoint)
+    if (nwords != 0 && lane == 0) set_status(status, TQ_EFORMAT);
+    return;
   }
-  if (bad || w != nwords || pos != len) {
+  GlobalWord* words = (GlobalWord*)s;
+  // every lane loads (addresses clamped into the stream, words past its end
+  // taken as zero), so no branch separates a load from its use
+  const uint64_t last = len - 1;
+  auto load = [&](uint64_t cb) {
+    const uint64_t p = 64 * cb + lane;
+    const uint64_t w = words[p < last ? p : last];
+    return p < len ? w : (uint64_t)0;
+  };
+  uint64_t c = 0;          // chunk: stream words [64c, 64c + 64)
+  uint64_t next_pos = 0;   // stream position of the next marker
+  uint64_t wnext = 0;      // uncompressed word where its run starts
+  bool bad = false;
+  uint64_t x = load(0);
+  while (next_pos < len) {
+    const uint64_t xn = load(c + 1);       // requested before this chunk is decoded
+    const uint64_t avail = len - 64 * c;   // stream words from the chunk start
+    const uint64_t first = next_pos - 64 * c;
+
+    // chunk positions of the markers: lane m gets the m-th one's (64: none)
+    // and the words the first m of them cover (run + literals, summed along
+    // the chain by the same doubling)
+    const uint64_t nx = (uint64_t)lane + 1 + (x >> 33);
+    uint32_t P[6];
+    uint64_t S[6];
+    P[0] = ((uint64_t)lane < avail && nx < 64) ? (uint32_t)nx : 64;
+    S[0] = ((x >> 1) & 0xFFFFFFFFull) + (x >> 33);
+#pragma unroll
+    for (int b = 1; b < 6; ++b) {
+      const uint32_t q = P[b - 1] & 63;
+      const uint32_t v = lane_get(P[b - 1], q);
+      const uint64_t t = lane_get64(S[b - 1], q);
+      P[b] = P[b - 1] >= 64 ? 64 : v;
+      S[b] = P[b - 1] >= 64 ? S[b - 1] : S[b - 1] + t;
+    }
+    uint32_t o = first < 64 ? (uint32_t)first : 64;
+    uint64_t acc = 0;
+#pragma unroll
+    for (int b = 0; b < 6; ++b) {
+      const uint32_t v = lane_get(P[b], o & 63);
+      const uint64_t t = lane_get64(S[b], o & 63);
+      if ((lane >> b) & 1) {
+        acc += o >= 64 ? 0 : t;
+        o = o >= 64 ? 64 : v;
+      }
+    }
+    const bool is_m = o < 64 && (uint64_t)o < avail;
+    const uint64_t mask = __ballot(is_m);
+    const uint64_t mw = lane_get64(x, o & 63);
+    const uint64_t run = is_m ? (mw >> 1) & 0xFFFFFFFFull : 0;
+    const uint64_t lits = is_m ? mw >> 33 : 0;
+    const uint64_t wm = wnext + acc;
+    const uint64_t end = wm + run + lits;
+    const uint64_t mpos = 64 * c + o;
+    // a marker must stay inside the bitmap and its literals inside the stream
+    if (__ballot(is_m && (end > nwords || lits > len - mpos - 1))) {
+      bad = true;
+      break;
+    }
+    // index entries: checkpoints k with k * kTile in [wm, end), written by
+    // the marker's lane; a marker covering more than 64 (a long fill) is
+    // written by the whole wave
+    const uint64_t k0 = (wm + kTile - 1) / kTile;
+    uint64_t k1 = (end + kTile - 1) / kTile;
+    if (k1 > nchk) k1 = nchk;
+    const bool many = is_m && k1 > k0 + 64;
+    if (is_m && !many)
+      for (uint64_t k = k0; k < k1; ++k) {
+        index[2 * k] = mpos;
+        index[2 * k + 1] = wm;
+      }
+    for (uint64_t mm = __ballot(many); mm; mm &= mm - 1) {
+      const int jl = __ffsll((unsigned long long)mm) - 1;
+      const uint64_t jk0 = readlane64(k0, jl), jk1 = readlane64(k1, jl);
+      const uint64_t jpos = readlane64(mpos, jl), jw = readlane64(wm, jl);
+      for (uint64_t k = jk0 + lane; k < jk1; k += 64) {
+        index[2 * k] = jpos;
+        index[2 * k + 1] = jw;
+      }
+    }
+    // the next marker follows the chunk's last one (every chunk decoded
+    // holds one: it is the chunk of next_pos)
+    const int lm = 63 - __clzll(mask);
+    next_pos = readlane64(mpos, lm) + 1 + readlane64(lits, lm);
+    wnext = readlane64(end, lm);
+    // the chunk holding it (literal-only chunks between are not read)
+    const uint64_t cn = next_pos >> 6;
+    if (cn == c + 1) x = xn;
+    else if (next_pos < len) x = load(cn);
+    c = cn;
+  }
+  if (bad || next_pos != len || wnext != nwords) {
     if (lane == 0) set_status(status, TQ_EFORMAT);
   }
 }

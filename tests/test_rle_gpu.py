@@ -159,9 +159,95 @@ def test_build_index_canonical_and_not(ctx):
     assert np.array_equal(to_host(idx), expected_index(s, r))
 
 
+def random_stream(rng, nw, max_run, max_lits, p_empty=0.05):
+    """A valid, generally non-canonical stream over nw words: markers with
+    random fills, runs and literal counts (empty markers among them), the
+    last one cut so that the runs end exactly at nw."""
+    parts, w = [], 0
+    while w < nw:
+        if rng.random() < p_empty:
+            parts.append(mk(int(rng.integers(0, 2)), 0, 0))
+            continue
+        run = int(rng.integers(0, max_run + 1))
+        lits = int(rng.integers(0, max_lits + 1))
+        if w + run + lits > nw:
+            run = min(run, nw - w)
+            lits = nw - w - run
+        parts.append(mk(int(rng.integers(0, 2)), run, lits))
+        parts += [int(x) for x in rng.integers(1, 1 << 62, lits, dtype=np.int64)]
+        w += run + lits
+    return np.array(parts, dtype=np.uint64)
+
+
+@pytest.mark.parametrize("case", range(10))
+def test_build_index_structures(ctx, case):
+    """Index building decodes each stream 64 words at a time: streams whose
+    markers sit at chunk boundaries, literal runs spanning several chunks
+    (chunks of literal words only are skipped), fills covering hundreds of
+    checkpoints (index entries written in several rounds), dense runs of
+    empty markers, and streams whose length is a multiple of 64, all against
+    the index by its definition."""
+    rng = np.random.default_rng(900 + case)
+    nw = [64 * STRIDE + 1, 300 * STRIDE, 5000, 64, 2 * STRIDE + 63, 4 * STRIDE, 77 * STRIDE + 5, 7000,
+          3 * STRIDE, 20 * STRIDE][case]
+    r = nw * 64 - (case % 3)
+    streams = {
+        0: random_stream(rng, nw, 600, 3),
+        1: np.array([mk(1, nw, 0)], dtype=np.uint64),                     # one fill, 300 entries
+        2: random_stream(rng, nw, 40, 200),                                # long literal runs
+        3: np.array([mk(0, 0, 0)] * 63 + [mk(1, 64, 0)], dtype=np.uint64),  # 64 markers in one chunk
+        4: random_stream(rng, nw, 3, 1, p_empty=0.3),                      # a marker every word or two
+        5: random_stream(rng, nw, 2 * STRIDE, 62),
+        6: random_stream(rng, nw, 5 * STRIDE, 70),
+        7: random_stream(rng, nw, 64, 64),
+        8: None,
+        9: random_stream(rng, nw, STRIDE, 0),
+    }
+    st = streams[case]
+    if st is None:
+        # the last literal word of each marker ends a 64-word chunk
+        parts, w = [], 0
+        while w < nw:
+            lits = min(63 - (len(parts) % 64), nw - w)
+            parts.append(mk(0, 0, lits))
+            parts += [5] * lits
+            w += lits
+            if w < nw:
+                run = min(int(rng.integers(1, 900)), nw - w)
+                parts.append(mk(1, run, 0))
+                w += run
+        st = np.array(parts, dtype=np.uint64)
+    assert np.array_equal(oracle.rle_decode(st, r).size, (r + 63) // 64)   # a valid stream
+    idx = torch.full((tq.tq_rle_index_words(r),), -1, dtype=torch.int64, device="cuda")
+    tq.tq_rle_build_index(ctx, to_dev(st), len(st), r, idx)
+    assert tq.tq_ctx_check(ctx) == 0
+    assert np.array_equal(to_host(idx), expected_index(st, r))
+
+
+def test_indexes_built_by_a_query(ctx):
+    """A query whose inputs bring no index builds all of them in one launch
+    (one wave per stream): varied streams, including non-canonical ones,
+    against the oracle's threshold of the decoded inputs."""
+    rng = np.random.default_rng(77)
+    nw = 40 * STRIDE + 17
+    r = nw * 64
+    streams = [random_stream(rng, nw, int(m), int(l)) for m, l in
+               zip(rng.integers(1, 3000, 24), rng.integers(0, 90, 24))]
+    streams += [oracle.rle_encode(d, r) for d in markov_bitmaps(17, 8, r, 60.0, 900.0)]
+    dense = [oracle.rle_decode(x, r) for x in streams]
+    inputs = [(to_dev(x), len(x), None) for x in streams]
+    for theta in (1, 2, 9, len(streams)):
+        out = empty_words(nw)
+        tq.tq_threshold_rle_dense(ctx, inputs, r, theta, out)
+        assert tq.tq_ctx_check(ctx) == 0
+        assert np.array_equal(to_host(out), oracle.threshold(dense, r, theta)), theta
+
+
 def test_build_index_rejects_malformed(ctx):
     r = 64 * 1000
-    for parts in ([mk(0, 999, 0)], [mk(0, 1001, 0)], [mk(0, 998, 3), 1, 2, 3], [mk(0, 990, 5), 1, 2]):
+    for parts in ([mk(0, 999, 0)], [mk(0, 1001, 0)], [mk(0, 998, 3), 1, 2, 3], [mk(0, 990, 5), 1, 2],
+                  [mk(0, 1000, 0), mk(0, 5, 0)], [mk(0, 10, 0)] * 99 + [mk(0, 9, 70)] + [3] * 60,
+                  [mk(0, 0, 0)] * 130 + [mk(1, 999, 0)]):
         s = np.array(parts, dtype=np.uint64)
         idx = torch.zeros(tq.tq_rle_index_words(r), dtype=torch.int64, device="cuda")
         tq.tq_rle_build_index(ctx, to_dev(s), len(s), r, idx)
