@@ -20,6 +20,40 @@ namespace var {
 // inputs).  Comp reads the complemented inputs.
 constexpr int kLoopedBlock = 8;
 
+typedef const __attribute__((address_space(1))) uint64_t GlobalInputWord;
+
+// Words w of inputs i .. i + kLoopedBlock - 1 (zero past the last input, and
+// past the bitmap when Guard).  A full block takes its pointers in one go
+// and issues all its loads before any is used.
+template <bool Comp, bool Guard, typename PtrArr>
+__device__ __forceinline__ void looped_load(uint64_t (&x)[kLoopedBlock], PtrArr ptrs, uint32_t i, uint32_t n,
+                                            uint64_t w, uint64_t nwords) {
+  if (i + kLoopedBlock <= n) {
+    const uint64_t* p[kLoopedBlock];
+#pragma unroll
+    for (int u = 0; u < kLoopedBlock; ++u) p[u] = ptrs[i + u];
+#pragma unroll
+    for (int u = 0; u < kLoopedBlock; ++u) {
+      uint64_t v = 0;
+      if (!Guard || w < nwords) v = __builtin_nontemporal_load((GlobalInputWord*)p[u] + w);
+      x[u] = Comp ? ~v : v;
+    }
+    if (Guard && w >= nwords)
+#pragma unroll
+      for (int u = 0; u < kLoopedBlock; ++u) x[u] = 0;
+    return;
+  }
+#pragma unroll
+  for (int u = 0; u < kLoopedBlock; ++u) {
+    uint64_t v = 0;
+    if (i + u < n && (!Guard || w < nwords)) {
+      v = __builtin_nontemporal_load((GlobalInputWord*)ptrs[i + u] + w);
+      if (Comp) v = ~v;
+    }
+    x[u] = v;
+  }
+}
+
 template <int T, bool Comp, bool Guard, typename PtrArr>
 __device__ __forceinline__ void looped_accumulate(uint64_t (&B)[T], PtrArr ptrs, uint32_t n, uint64_t w,
                                                   uint64_t nwords, uint64_t valid, bool prune) {
@@ -27,15 +61,7 @@ __device__ __forceinline__ void looped_accumulate(uint64_t (&B)[T], PtrArr ptrs,
   for (uint32_t i = 0; i < n; i += kLoopedBlock) {
     if (alive) {
       uint64_t x[kLoopedBlock];
-#pragma unroll
-      for (int u = 0; u < kLoopedBlock; ++u) {
-        uint64_t v = 0;
-        if (i + u < n && (!Guard || w < nwords)) {
-          v = __builtin_nontemporal_load(ptrs[i + u] + w);
-          if (Comp) v = ~v;
-        }
-        x[u] = v;
-      }
+      looped_load<Comp, Guard>(x, ptrs, i, n, w, nwords);
 #pragma unroll
       for (int u = 0; u < kLoopedBlock; ++u) {
 #pragma unroll
