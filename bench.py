@@ -58,7 +58,114 @@ def parse():
                     help="default workload only: skip the compact RLE, serving and selector summaries")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--record-traffic", metavar="PMC_DIR",
+                    help="write profiles/traffic.json from rocprofv3 counter runs under PMC_DIR (no GPU "
+                         "work): fetch/, write/, raw/ of the default step, cfetch/, cwrite/, craw/ of "
+                         "--copy-calibration, rle_fetch/, rle_write/ of --workload rle")
     return ap.parse_args()
+
+
+# ------------------------------------------------------------ traffic records
+# Sources each record is keyed on: a record counts only while every one of
+# them is unchanged (load_traffic compares their hash).
+DENSE_SOURCES = ["paper_1402_4073_amd/csrc/tq_dense.hip", "paper_1402_4073_amd/csrc/tq_csa.hpp",
+                 "paper_1402_4073_amd/csrc/tq_internal.h", "include/tq.h"]
+STEP_SOURCES = DENSE_SOURCES + ["paper_1402_4073_amd/csrc/tq_looped.hip", "paper_1402_4073_amd/csrc/tq_variants.hpp",
+                                "paper_1402_4073_amd/csrc/tq_host.hip", "paper_1402_4073_amd/csrc/tq_select.hip",
+                                "tqgen/__init__.py", "tqgen/gen.hip"]
+RLE_SOURCES = ["paper_1402_4073_amd/csrc/tq_rle.hip", "paper_1402_4073_amd/csrc/tq_csa.hpp",
+               "paper_1402_4073_amd/csrc/tq_internal.h", "include/tq.h"]
+STEP_QUERIES = ["theta 2", "theta 16", "theta 128", "theta 255", "2 <= count <= 10", "parity"]
+
+
+def source_sha(sources):
+    import hashlib
+    return hashlib.sha256(b"".join(open(os.path.join(ROOT, s), "rb").read() for s in sources)).hexdigest()[:16]
+
+
+def pmc_dispatches(d):
+    """(dispatch id, kernel name, {counter: value summed over the device})
+    from the counter_collection csv files of one rocprofv3 run."""
+    import csv
+    import glob
+    by = {}
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                k = int(r.get("Dispatch_Id") or r.get("Dispatch_ID"))
+                e = by.setdefault(k, {"kernel": r.get("Kernel_Name"), "c": {}})
+                e["c"][r["Counter_Name"]] = e["c"].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    return [(k, by[k]["kernel"], by[k]["c"]) for k in sorted(by)]
+
+
+def record_traffic(pmc_dir):
+    """HBM bytes per launch from FETCH_SIZE / WRITE_SIZE, each scaled by what
+    the same counter reads for a plain 1 GiB copy."""
+    def mean(v):
+        return sum(v) / len(v)
+    def copies(sub, ctr):
+        return [c[ctr] for _, n, c in pmc_dispatches(os.path.join(pmc_dir, sub)) if "copyBuffer" in n]
+    fscale = 1048576.0 / mean(copies("cfetch", "FETCH_SIZE"))
+    wscale = 1048576.0 / mean(copies("cwrite", "WRITE_SIZE"))
+    raw_copy = mean(copies("craw", "TCC_EA0_RDREQ_sum"))
+
+    def step(sub, ctr):
+        return [(n, c[ctr]) for _, n, c in pmc_dispatches(os.path.join(pmc_dir, sub))
+                if "looped_kernel" in n or "dense_kernel" in n]
+    F, W, R = step("fetch", "FETCH_SIZE"), step("write", "WRITE_SIZE"), step("raw", "TCC_EA0_RDREQ_sum")
+    # bench.py --steps 1 --warmup 1 --no-consumers --no-summaries: the pruned step twice (warm-up and
+    # timed, six queries each), then the unpruned roofline pass twice
+    if not (len(F) == len(W) == len(R) == 24):
+        raise SystemExit("expected 24 dense/looped dispatches per run, got %d/%d/%d" % (len(F), len(W), len(R)))
+    queries = []
+    for i, name in enumerate(STEP_QUERIES):
+        fk = mean([F[s * 6 + i][1] for s in (0, 1)])
+        wk = mean([W[s * 6 + i][1] for s in (0, 1)])
+        rq = mean([R[s * 6 + i][1] for s in (0, 1)])
+        kern = F[6 + i][0].replace("void tq::(anonymous namespace)::", "").split("(")[0]
+        queries.append({"query": name, "kernel": kern, "fetch_kib": fk, "write_kib": wk, "rdreq": rq,
+                        "bytes": int(round(fk * 1024 * fscale + wk * 1024 * wscale))})
+    uf = mean([f for _, f in F[12:]])
+    uw = mean([w for _, w in W[12:]])
+    rec = {}
+    rec["dense_kernel<K=9>/large"] = {
+        "source_sha": source_sha(DENSE_SOURCES),
+        "bytes_per_launch": int(round(uf * 1024 * fscale + uw * 1024 * wscale)),
+        "fetch_kib_per_dispatch": round(uf, 2), "write_kib_per_dispatch": round(uw, 2),
+        "fetch_scale": fscale, "write_scale": wscale,
+        "note": "launches with pruning off (12 dispatches); FETCH_SIZE/WRITE_SIZE (KiB per dispatch) scaled by "
+                "what they read for a plain 1 GiB copy; see hbm_counter_calibration.md",
+        "sources": DENSE_SOURCES}
+    rec["dense_step/large-pruned"] = {
+        "source_sha": source_sha(STEP_SOURCES), "bytes_per_query": [q["bytes"] for q in queries],
+        "queries": queries, "fetch_scale": fscale, "write_scale": wscale,
+        "note": "default step (pruning and Looped on, registered inputs read by cardinality): HBM bytes per "
+                "query from FETCH_SIZE and WRITE_SIZE per dispatch, mean of the two steps of the run, scaled "
+                "as the dense kernel's",
+        "sources": STEP_SOURCES}
+    # threshold launches of the tile kernel: compressed inputs only, no consumers, bit planes
+    rf = [(n, c["FETCH_SIZE"]) for _, n, c in pmc_dispatches(os.path.join(pmc_dir, "rle_fetch"))
+          if "rle_tile_kernel" in n and ", false, false, 1, false, false>" in n]
+    rw = [(n, c["WRITE_SIZE"]) for _, n, c in pmc_dispatches(os.path.join(pmc_dir, "rle_write"))
+          if "rle_tile_kernel" in n and ", false, false, 1, false, false>" in n]
+    if not rf or len(rf) != len(rw):
+        raise SystemExit("RLE threshold dispatches: %d fetch, %d write" % (len(rf), len(rw)))
+    f, w = mean([v for _, v in rf]), mean([v for _, v in rw])
+    rec["rle_tile_kernel/rle-thresholds"] = {
+        "source_sha": source_sha(RLE_SOURCES),
+        "bytes_per_launch": int(round(f * 1024 * fscale + w * 1024 * wscale)),
+        "fetch_kib_per_dispatch": round(f, 1), "write_kib_per_dispatch": round(w, 1),
+        "fetch_scale": fscale, "write_scale": wscale,
+        "note": "threshold launches (thetas 2, 64, 256 with RLE and dense output, %d dispatches averaged); same "
+                "scaling as the dense kernel" % len(rf),
+        "sources": RLE_SOURCES}
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    with open(path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps({"copy_fetch_scale": fscale, "copy_write_scale": wscale, "copy_rdreq": raw_copy,
+                      "dense_bytes_per_launch": rec["dense_kernel<K=9>/large"]["bytes_per_launch"],
+                      "step_bytes": sum(q["bytes"] for q in queries),
+                      "rle_bytes_per_launch": rec["rle_tile_kernel/rle-thresholds"]["bytes_per_launch"]}))
 
 
 def copy_calibration():
@@ -1019,6 +1126,9 @@ def main():
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
+    if args.record_traffic:
+        record_traffic(args.record_traffic)
+        return
     if args.copy_calibration:
         copy_calibration()
         return
