@@ -43,6 +43,9 @@ constexpr int kTileThreads = 512;
 // columns needing literal words in a tile from which on the next tile is done
 // in one pass
 constexpr int kOnePassColumns = kTile / 16;
+// tiles whose k and d one marker walk gathers (spans without literal words)
+constexpr int kSpan = 8;
+static_assert(kTile == kTileThreads && kTile % kSpan == 0, "phase 2 gives each thread kSpan columns of one tile");
 constexpr int kEncBlock = 256;
 constexpr int kEncPerThread = 8;
 constexpr int kEncWords = kEncBlock * kEncPerThread;
@@ -84,7 +87,9 @@ __device__ __forceinline__ int32_t wave_inclusive_scan<int32_t>(int32_t v) {
 
 template <typename T, int WAVES>
 __device__ __forceinline__ T block_exclusive_scan(T v, T* wave_tot, T* total) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // (lane and wave derived here, not hoisted out of the tile loop of the caller)
+  int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  asm volatile("" : "+v"(lane), "+v"(wave));
   T inc = wave_inclusive_scan(v);
   if (lane == 63) wave_tot[wave] = inc;
   __syncthreads();
@@ -428,7 +433,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(
   extern __shared__ uint64_t lds[];
   constexpr int kCounterWords = Swar ? 16 : K;
   uint64_t* planes = lds;                                         // kCounterWords x kTile
-  int32_t* kd = reinterpret_cast<int32_t*>(lds + kCounterWords * kTile);   // kTile + 1 packed (k | d << 16)
+  int32_t* kd = reinterpret_cast<int32_t*>(lds + kCounterWords * kTile);   // kSpan * kTile + 1 packed (k | d << 16)
   constexpr bool Sat = Form == kSaturating, Par = Form == kParityPlane;
   static_assert(!Sat || !Swar, "saturating planes are bit planes");
   static_assert(!Par || (Sym && !Swar && K == 1), "the parity plane serves the parity function only");
@@ -439,6 +444,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(
   const Add add{planes};
   __shared__ int32_t wave_tot[kTileThreads / 64];
   __shared__ int32_t total;
+  __shared__ int32_t needs[kSpan];   // undecided columns with literal words, per tile of the span
 
   // Workgroups are dealt to the eight XCDs round robin; give each XCD a
   // contiguous block of ranges so that the cache lines two neighbouring
@@ -475,68 +481,123 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(
   // Tiles whose literal words are mostly needed are done in one pass (the
   // marker walk adds every literal word to the counters), saving the second
   // walk at the cost of counting literal words of decided columns too.  The
-  // choice follows the previous tile of the range: neighbouring tiles of a
-  // bitmap tend to look alike.
+  // others are taken kSpan at a time: one marker walk over the span fills
+  // k and d of all its columns (a lane waits at a barrier once per span, not
+  // once per tile, so streams with more markers in one tile and fewer in the
+  // next even out), and only tiles with undecided columns walk again for
+  // their literal words, entering each stream through the index.  The choice
+  // follows the previous span of the range: neighbouring tiles of a bitmap
+  // tend to look alike.
   bool one_pass = Swar;
 
-  for (uint32_t tile = tile_begin; tile < tile_end; ++tile) {
-    const uint32_t t0 = tile * kTile;
-    const uint32_t t1 = nwords - t0 > (uint32_t)kTile ? t0 + kTile : nwords;
-    if (tile != tile_begin) __syncthreads();   // the previous tile's phase 4 is done with the LDS
+  for (uint32_t ta = tile_begin; ta < tile_end;) {
+    // (the first tile of a range, whose kind is not known yet, goes alone)
+    const uint32_t nb = (one_pass || ta == tile_begin) ? 1
+                                                       : (tile_end - ta < (uint32_t)kSpan ? tile_end - ta : (uint32_t)kSpan);
+    const uint32_t lo = ta * kTile;
+    const uint32_t hi = nwords - lo > nb * kTile ? lo + nb * kTile : nwords;
+    const uint32_t ncols = hi - lo;
+    if (ta != tile_begin) __syncthreads();   // the previous span's phase 4 is done with the LDS
     for (int i = tid; i < kCounterWords * kTile; i += kTileThreads) planes[i] = 0;
-    for (int i = tid; i <= kTile; i += kTileThreads) kd[i] = 0;
+    for (int i = tid; i <= (int)ncols; i += kTileThreads) kd[i] = 0;
+    if (tid < kSpan) needs[tid] = 0;
     __syncthreads();
 
     // 1. markers only: difference array of (ones fills) + 65536 * (dirty)
     const Walk entry = carry;
     const bool entry_ok = carry_ok;
-    if (entry_ok) walk_markers(my_len, rd, entry, t0, t1, nwords, kd, status, one_pass, add, carry);
+    if (entry_ok) walk_markers(my_len, rd, entry, lo, hi, nwords, kd, status, one_pass, add, carry);
     for (uint32_t j = tid + kTileThreads; j < n_rle; j += kTileThreads) {
       const RleDesc dsc = descs[j];
       Walk wk, unused;
-      if (!seek(dsc, tile, t0, wk)) { set_status(status, TQ_EFORMAT); continue; }
+      if (!seek(dsc, ta, lo, wk)) { set_status(status, TQ_EFORMAT); continue; }
       rx.reset(dsc.words, dsc.len);
-      walk_markers((uint32_t)dsc.len, rx, wk, t0, t1, nwords, kd, status, one_pass, add, unused);
+      walk_markers((uint32_t)dsc.len, rx, wk, lo, hi, nwords, kd, status, one_pass, add, unused);
     }
     __syncthreads();
 
-    // 2. prefix sum: kd[c] = k + 65536 * d for column c, flagged if undecided
-    int undecided = 0;
+    // 2. prefix sum: kd[c] = k + 65536 * d for column c, flagged if undecided;
+    // thread i takes columns [kSpan * i, kSpan * i + kSpan), all in one tile
+    // (addresses derived from a thread number the compiler cannot hoist)
     {
-      const int32_t v = tid < kTile ? kd[tid] : 0;
-      const int32_t ex = block_exclusive_scan<int32_t, kTileThreads / 64>(v, wave_tot, &total);
-      bool und = false;
-      if (tid < (int)(t1 - t0)) {
-        int k, d;
-        unpack_kd(ex + v, k, d);
-        if constexpr (Sym) {
-          und = (uint32_t)(k + d) + n_dense > sym->run_end[k];
-        } else {
-          const int tp = (int)theta - k;
-          und = tp >= 1 && tp <= d + (int)n_dense;
+      int me = tid;
+      asm volatile("" : "+v"(me));
+      int32_t v[kSpan];
+      int32_t sum = 0;
+#pragma unroll
+      for (int q = 0; q < kSpan; ++q) {
+        const uint32_t col = (uint32_t)me * kSpan + q;
+        v[q] = col < ncols ? kd[col] : 0;
+        sum += v[q];
+      }
+      int32_t run = block_exclusive_scan<int32_t, kTileThreads / 64>(sum, wave_tot, &total);
+      int undecided = 0;
+#pragma unroll
+      for (int q = 0; q < kSpan; ++q) {
+        const uint32_t col = (uint32_t)me * kSpan + q;
+        run += v[q];
+        if (col < ncols) {
+          int k, d;
+          unpack_kd(run, k, d);
+          bool und;
+          if constexpr (Sym) {
+            und = (uint32_t)(k + d) + n_dense > sym->run_end[k];
+          } else {
+            const int tp = (int)theta - k;
+            und = tp >= 1 && tp <= d + (int)n_dense;
+          }
+          // literal words matter where the column is undecided and has some
+          undecided += (und && d > 0) ? 1 : 0;
+          kd[col] = run | (und ? (int32_t)0x80000000 : 0);
         }
-        // literal words matter where the column is undecided and has some
-        undecided = (und && d > 0) ? 1 : 0;
       }
-      if (tid < kTile) kd[tid] = (ex + v) | (und ? (int32_t)0x80000000 : 0);
-    }
-    // a tile whose columns the fills alone decide needs no literal word
-    const int need = __syncthreads_count(undecided);
-    const bool walk_again = need > 0 && !one_pass;
-    one_pass = Swar || need >= kOnePassColumns;
-
-    // 3. literal words of undecided columns into the per-column LDS counters
-    if (walk_again) {
-      if (entry_ok) walk_literals(my_len, rd, entry, t0, t1, nwords, kd, add);
-      for (uint32_t j = tid + kTileThreads; j < n_rle; j += kTileThreads) {
-        const RleDesc dsc = descs[j];
-        Walk wk;
-        if (!seek(dsc, tile, t0, wk)) continue;
-        rx.reset(dsc.words, dsc.len);
-        walk_literals((uint32_t)dsc.len, rx, wk, t0, t1, nwords, kd, add);
-      }
+      if (undecided) atomicAdd(&needs[(me * kSpan) / kTile], undecided);
     }
     __syncthreads();
+    int need = 0;
+    for (uint32_t b = 0; b < nb; ++b) need += needs[b];
+    const bool span_one_pass = one_pass;
+    one_pass = Swar || need >= kOnePassColumns * (int)nb;
+
+    bool planes_used = false;   // the counters hold literal words of an earlier tile of the span
+    for (uint32_t b = 0; b < nb; ++b) {
+      const uint32_t tile = ta + b;
+      const uint32_t t0 = lo + b * kTile;
+      const uint32_t t1 = hi - t0 > (uint32_t)kTile ? t0 + kTile : hi;
+      int32_t* const tkd = kd + (t0 - lo);
+      // a tile whose columns the fills alone decide needs no literal word
+      const bool walk_again = !span_one_pass && needs[b] > 0;
+      if (planes_used) {
+        __syncthreads();   // the previous tile's phase 4 is done with the counters
+        for (int i = tid; i < kCounterWords * kTile; i += kTileThreads) planes[i] = 0;
+        __syncthreads();
+        planes_used = false;
+      }
+
+      // 3. literal words of undecided columns into the per-column LDS counters
+      if (walk_again) {
+        if (entry_ok) {
+          Walk e = entry;
+          bool ok = true;
+          if (b > 0) {
+            // (the descriptor's address derived here, not held across the walks)
+            int me = tid;
+            asm volatile("" : "+v"(me));
+            ok = seek(descs[me], tile, t0, e);
+            if (!ok) set_status(status, TQ_EFORMAT);
+          }
+          if (ok) walk_literals(my_len, rd, e, t0, t1, nwords, tkd, add);
+        }
+        for (uint32_t j = tid + kTileThreads; j < n_rle; j += kTileThreads) {
+          const RleDesc dsc = descs[j];
+          Walk wk;
+          if (!seek(dsc, tile, t0, wk)) continue;
+          rx.reset(dsc.words, dsc.len);
+          walk_literals((uint32_t)dsc.len, rx, wk, t0, t1, nwords, tkd, add);
+        }
+        planes_used = true;
+      }
+      __syncthreads();
 
     // 4. one column per thread: decide, or count and compare
     // (the column's LDS addresses are derived here, not kept live across the
@@ -544,7 +605,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(
     int c = tid;
     asm volatile("" : "+v"(c));
     if (c < (int)(t1 - t0)) {
-      const int32_t v = kd[c];
+      const int32_t v = tkd[c];
       int k, d;
       unpack_kd(v, k, d);
       uint64_t res;
@@ -634,6 +695,8 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(
         out[(uint64_t)t0 + c] = word;
       }
     }
+    }
+    ta += nb;
   }
   if constexpr (Fused) {
     if (sink.partial64) {
@@ -1065,7 +1128,7 @@ TileChoice choose_tile(int K, uint32_t theta, const RleSym* sym, bool swar) {
 }  // namespace
 
 size_t rle_tile_lds_bytes(int K, bool swar) {
-  return (size_t)(swar ? 16 : K) * kTile * 8 + (size_t)(kTile + 2) * 4;
+  return (size_t)(swar ? 16 : K) * kTile * 8 + (size_t)(kSpan * kTile + 2) * 4;
 }
 
 hipError_t launch_rle_tile(const RleDesc* d_descs, uint32_t n_rle, const uint64_t* const* d_dense,
