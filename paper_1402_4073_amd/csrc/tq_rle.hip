@@ -45,6 +45,10 @@ constexpr int kTileThreads = 512;
 constexpr int kOnePassColumns = kTile / 16;
 // tiles whose k and d one marker walk gathers (spans without literal words)
 constexpr int kSpan = 8;
+// tiles a one-pass walk covers when the counters are at most 2 planes (their
+// LDS then holds the counters of that many tiles)
+constexpr int kOnePassSpan = 4;
+__host__ __device__ constexpr int plane_tiles(int K, bool swar) { return (!swar && K <= 2) ? kOnePassSpan : 1; }
 static_assert(kTile == kTileThreads && kTile % kSpan == 0, "phase 2 gives each thread kSpan columns of one tile");
 constexpr int kEncBlock = 256;
 constexpr int kEncPerThread = 8;
@@ -199,16 +203,24 @@ __device__ __forceinline__ uint64_t greater_than_lds(const uint64_t* planes, int
 // Bit-sliced: K planes per column; a word is added by a ripple of atomic
 // XORs whose returned old values give the carries (see ripple_lds).  K x 4 KiB
 // per tile, but each addition waits for its LDS round trips.
+//
+// Column c of a walk counts from the first tile of the walk; the counters of
+// each tile are a block of their own (K x kTile words), so a walk over several
+// tiles (one-pass spans) addresses block c / kTile.
 template <int K>
 struct SlicedAdd {
   uint64_t* planes;
-  __device__ __forceinline__ void operator()(int c, uint64_t x) const { ripple_lds<K>(planes, c, x); }
+  __device__ __forceinline__ void operator()(int c, uint64_t x) const {
+    ripple_lds<K>(planes + (c / kTile) * (K * kTile), c % kTile, x);
+  }
 };
 
 template <int K>
 struct SaturatingAdd {
   uint64_t* planes;
-  __device__ __forceinline__ void operator()(int c, uint64_t x) const { ripple_lds_sat<K>(planes, c, x); }
+  __device__ __forceinline__ void operator()(int c, uint64_t x) const {
+    ripple_lds_sat<K>(planes + (c / kTile) * (K * kTile), c % kTile, x);
+  }
 };
 
 // Parity needs only bit 0 of each count: one plane, one XOR per word, and no
@@ -432,8 +444,10 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(
   const uint32_t n_dense = Hybrid ? n_dense_arg : 0;
   extern __shared__ uint64_t lds[];
   constexpr int kCounterWords = Swar ? 16 : K;
-  uint64_t* planes = lds;                                         // kCounterWords x kTile
-  int32_t* kd = reinterpret_cast<int32_t*>(lds + kCounterWords * kTile);   // kSpan * kTile + 1 packed (k | d << 16)
+  constexpr int kPlaneTiles = plane_tiles(K, Swar);
+  // counters: a block of kCounterWords x kTile words per tile of a one-pass span
+  uint64_t* planes = lds;
+  int32_t* kd = reinterpret_cast<int32_t*>(lds + kCounterWords * kTile * kPlaneTiles);   // kSpan * kTile + 1 packed (k | d << 16)
   constexpr bool Sat = Form == kSaturating, Par = Form == kParityPlane;
   static_assert(!Sat || !Swar, "saturating planes are bit planes");
   static_assert(!Par || (Sym && !Swar && K == 1), "the parity plane serves the parity function only");
@@ -492,13 +506,13 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(
 
   for (uint32_t ta = tile_begin; ta < tile_end;) {
     // (the first tile of a range, whose kind is not known yet, goes alone)
-    const uint32_t nb = (one_pass || ta == tile_begin) ? 1
-                                                       : (tile_end - ta < (uint32_t)kSpan ? tile_end - ta : (uint32_t)kSpan);
+    const uint32_t span = one_pass ? (uint32_t)kPlaneTiles : (ta == tile_begin ? 1u : (uint32_t)kSpan);
+    const uint32_t nb = tile_end - ta < span ? tile_end - ta : span;
     const uint32_t lo = ta * kTile;
     const uint32_t hi = nwords - lo > nb * kTile ? lo + nb * kTile : nwords;
     const uint32_t ncols = hi - lo;
     if (ta != tile_begin) __syncthreads();   // the previous span's phase 4 is done with the LDS
-    for (int i = tid; i < kCounterWords * kTile; i += kTileThreads) planes[i] = 0;
+    for (int i = tid; i < kCounterWords * kTile * (one_pass ? (int)nb : 1); i += kTileThreads) planes[i] = 0;
     for (int i = tid; i <= (int)ncols; i += kTileThreads) kd[i] = 0;
     if (tid < kSpan) needs[tid] = 0;
     __syncthreads();
@@ -567,6 +581,8 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(
       int32_t* const tkd = kd + (t0 - lo);
       // a tile whose columns the fills alone decide needs no literal word
       const bool walk_again = !span_one_pass && needs[b] > 0;
+      // the tile's counters (one block per tile of a one-pass span)
+      const uint64_t* tplanes = planes + (span_one_pass ? b * (kCounterWords * kTile) : 0);
       if (planes_used) {
         __syncthreads();   // the previous tile's phase 4 is done with the counters
         for (int i = tid; i < kCounterWords * kTile; i += kTileThreads) planes[i] = 0;
@@ -620,7 +636,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(
       } else if constexpr (Swar) {
         uint64_t C[16];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) C[q] = planes[q * kTile + c];
+        for (int q = 0; q < 16; ++q) C[q] = tplanes[q * kTile + c];
         const uint64_t col = (uint64_t)t0 + c;
         if constexpr (Hybrid)
           for_dense_words(dense, n_dense, col, [&](uint64_t x) {
@@ -641,11 +657,11 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(
           }
         }
       } else if (!Sym && !Hybrid) {
-        res = greater_than_lds<K>(planes, c, theta - (uint32_t)k - 1);
+        res = greater_than_lds<K>(tplanes, c, theta - (uint32_t)k - 1);
       } else {
         uint64_t P[K];
 #pragma unroll
-        for (int q = 0; q < K; ++q) P[q] = planes[q * kTile + c];
+        for (int q = 0; q < K; ++q) P[q] = tplanes[q * kTile + c];
         const uint64_t col = (uint64_t)t0 + c;
         if constexpr (Hybrid)
           for_dense_words(dense, n_dense, col, [&](uint64_t x) {
@@ -1128,7 +1144,7 @@ TileChoice choose_tile(int K, uint32_t theta, const RleSym* sym, bool swar) {
 }  // namespace
 
 size_t rle_tile_lds_bytes(int K, bool swar) {
-  return (size_t)(swar ? 16 : K) * kTile * 8 + (size_t)(kSpan * kTile + 2) * 4;
+  return (size_t)(swar ? 16 : K) * kTile * 8 * plane_tiles(K, swar) + (size_t)(kSpan * kTile + 2) * 4;
 }
 
 hipError_t launch_rle_tile(const RleDesc* d_descs, uint32_t n_rle, const uint64_t* const* d_dense,
