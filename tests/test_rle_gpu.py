@@ -471,6 +471,60 @@ def test_tiles_option_range(ctx, tiles_option):
     assert tiles_option(0) == tq.TQ_OK
 
 
+def undecided_per_tile(dense, r, theta):
+    """Columns of each tile where the fills do not decide theta (RBMrg's
+    middle case) and some input is dirty, counted from the words."""
+    words = np.stack(dense)
+    ones = (words == np.uint64(0xFFFFFFFFFFFFFFFF)).sum(axis=0)
+    dirty = ((words != 0) & (words != np.uint64(0xFFFFFFFFFFFFFFFF))).sum(axis=0)
+    tp = theta - ones.astype(np.int64)
+    und = (tp >= 1) & (tp <= dirty) & (dirty > 0)
+    nt = (words.shape[1] + STRIDE - 1) // STRIDE
+    return np.array([int(und[t * STRIDE:(t + 1) * STRIDE].sum()) for t in range(nt)])
+
+
+@pytest.mark.parametrize("tiles", [0, 11, 3, 1 << 20])
+def test_spans_with_few_undecided_columns(ctx, tiles_option, tiles):
+    """Tiles the fills nearly decide are taken several at a time: one marker
+    walk over the span, then a literal walk only for the tiles of the span
+    that have undecided columns, each stream entered through the index at
+    that tile.  Thresholds are picked so that some tiles have a few
+    undecided columns and others none (the mixed spans), with ranges that
+    end in a partial span, with and without indexes, and hybrid inputs."""
+    r = 64 * STRIDE * 26 + 41                      # 27 tiles, the last one short
+    n = 160
+    dense = markov_bitmaps(710, n, r, 64.0, 1500.0)
+    counts = {t: undecided_per_tile(dense, r, t) for t in range(2, n)}
+    # thresholds with undecided columns in some tiles, fewer than 32 in every
+    # tile, and none in others
+    mixed = [t for t, u in counts.items() if u.max() < 32 and (u > 0).sum() >= 3 and (u == 0).sum() >= 3]
+    assert mixed, "no threshold leaves a few undecided columns in some tiles"
+    picks = sorted({mixed[0], mixed[len(mixed) // 2], mixed[-1]})
+    assert tiles_option(tiles) == tq.TQ_OK
+    for with_index in (True, False):
+        inputs, keep = rle_inputs(ctx, dense, r, with_index=with_index)
+        for theta in picks + [n // 2, n]:
+            out = empty_words((r + 63) // 64)
+            tq.tq_threshold_rle_dense(ctx, inputs, r, theta, out)
+            assert tq.tq_ctx_check(ctx) == 0
+            assert np.array_equal(to_host(out), oracle.threshold(dense, r, theta)), (with_index, theta)
+    inputs, keep = rle_inputs(ctx, dense[:100], r)
+    pool = dev_pool(dense[100:])
+    for theta in picks:
+        out = empty_words((r + 63) // 64)
+        tq.tq_threshold_hybrid(ctx, inputs, [pool[j] for j in range(n - 100)], r, theta, out)
+        assert tq.tq_ctx_check(ctx) == 0
+        assert np.array_equal(to_host(out), oracle.threshold(dense, r, theta)), ("hybrid", theta)
+    # symmetric functions whose run table leaves as few columns undecided
+    inputs, keep = rle_inputs(ctx, dense, r)
+    for t in picks:
+        for f in (oracle.truth_interval(n, t, n), oracle.truth_interval(n, t - 1, n - 1)):
+            out = empty_words((r + 63) // 64)
+            tq.tq_symmetric_rle_dense(ctx, inputs, r, f, out)
+            assert tq.tq_ctx_check(ctx) == 0
+            assert np.array_equal(to_host(out), oracle.symmetric(dense, r, f)), ("symmetric", t)
+
+
 @pytest.mark.parametrize("tiles", [1, 2, 3, 7, 1 << 20, 0])
 def test_tile_ranges(ctx, tiles_option, tiles):
     """A workgroup that walks several tiles in a row carries every stream's
