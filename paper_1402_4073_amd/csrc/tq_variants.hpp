@@ -16,35 +16,38 @@ namespace var {
 // this bit": adding an input word x is B[t] |= B[t-1] & x from the top plane
 // down, then B[0] |= x (no carries).  A position is decided once B[T-1] is
 // set; the planes only grow, so a lane whose positions are all decided stops
-// reading and the wave ends once no lane reads (tested every kLoopedBlock
-// inputs).  Comp reads the complemented inputs.
-constexpr int kLoopedBlock = 8;
+// reading and the wave ends once no lane reads (tested every
+// looped_block<Comp>() inputs).  Comp reads the complemented inputs.
+// Inputs per test: 8, and 4 on the complemented inputs, where a lane is
+// typically decided within the first few (theta >= N - 2 needs only T zeros).
+template <bool Comp>
+constexpr int looped_block() { return Comp ? 4 : 8; }
 
 typedef const __attribute__((address_space(1))) uint64_t GlobalInputWord;
 
-// Words w of inputs i .. i + kLoopedBlock - 1 (zero past the last input, and
+// Words w of inputs i .. i + KB - 1 (zero past the last input, and
 // past the bitmap when Guard).  A full block takes its pointers in one go
 // and issues all its loads before any is used.
-template <bool Comp, bool Guard, typename PtrArr>
-__device__ __forceinline__ void looped_load(uint64_t (&x)[kLoopedBlock], PtrArr ptrs, uint32_t i, uint32_t n,
-                                            uint64_t w, uint64_t nwords) {
-  if (i + kLoopedBlock <= n) {
-    const uint64_t* p[kLoopedBlock];
+template <int KB, bool Comp, bool Guard, typename PtrArr>
+__device__ __forceinline__ void looped_load(uint64_t (&x)[KB], PtrArr ptrs, uint32_t i, uint32_t n, uint64_t w,
+                                            uint64_t nwords) {
+  if (i + KB <= n) {
+    const uint64_t* p[KB];
 #pragma unroll
-    for (int u = 0; u < kLoopedBlock; ++u) p[u] = ptrs[i + u];
+    for (int u = 0; u < KB; ++u) p[u] = ptrs[i + u];
 #pragma unroll
-    for (int u = 0; u < kLoopedBlock; ++u) {
+    for (int u = 0; u < KB; ++u) {
       uint64_t v = 0;
       if (!Guard || w < nwords) v = __builtin_nontemporal_load((GlobalInputWord*)p[u] + w);
       x[u] = Comp ? ~v : v;
     }
     if (Guard && w >= nwords)
 #pragma unroll
-      for (int u = 0; u < kLoopedBlock; ++u) x[u] = 0;
+      for (int u = 0; u < KB; ++u) x[u] = 0;
     return;
   }
 #pragma unroll
-  for (int u = 0; u < kLoopedBlock; ++u) {
+  for (int u = 0; u < KB; ++u) {
     uint64_t v = 0;
     if (i + u < n && (!Guard || w < nwords)) {
       v = __builtin_nontemporal_load((GlobalInputWord*)ptrs[i + u] + w);
@@ -57,13 +60,14 @@ __device__ __forceinline__ void looped_load(uint64_t (&x)[kLoopedBlock], PtrArr 
 template <int T, bool Comp, bool Guard, typename PtrArr>
 __device__ __forceinline__ void looped_accumulate(uint64_t (&B)[T], PtrArr ptrs, uint32_t n, uint64_t w,
                                                   uint64_t nwords, uint64_t valid, bool prune) {
+  constexpr int KB = looped_block<Comp>();
   bool alive = true;   // this lane has positions that have not reached T
-  for (uint32_t i = 0; i < n; i += kLoopedBlock) {
+  for (uint32_t i = 0; i < n; i += KB) {
     if (alive) {
-      uint64_t x[kLoopedBlock];
-      looped_load<Comp, Guard>(x, ptrs, i, n, w, nwords);
+      uint64_t x[KB];
+      looped_load<KB, Comp, Guard>(x, ptrs, i, n, w, nwords);
 #pragma unroll
-      for (int u = 0; u < kLoopedBlock; ++u) {
+      for (int u = 0; u < KB; ++u) {
 #pragma unroll
         for (int t = T - 1; t >= 1; --t) B[t] |= B[t - 1] & x[u];
         B[0] |= x[u];
