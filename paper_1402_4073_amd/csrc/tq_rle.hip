@@ -420,11 +420,12 @@ __device__ __forceinline__ void for_dense_words(const uint64_t* const* dense, ui
 // bit_length(tail_from) + 1 for a symmetric f constant from tail_from on;
 // kParityPlane (the parity function and its complement) keeps one plane, the
 // count modulo 2.  With K <= 4 planes (K <= 9 for plain thresholds, K <= 5
-// for symmetric functions) the kernel is built for 8 waves per SIMD, which
-// its LDS footprint allows; the plain-threshold builds fit in those 64
-// registers without spilling (each lane keeps only its stream's length and
-// reader, and is entered through the index once per range), the others
-// spill a few registers, reloaded once per tile.
+// for symmetric functions) the kernel is built for 8 waves per SIMD (how
+// many are resident is then set by the LDS footprint: 3 or 4 workgroups per
+// CU); the plain-threshold builds fit in those 64 registers without spilling
+// (each lane keeps only its stream's length and reader, and is entered
+// through the index once per range), the others spill a few registers,
+// reloaded once per tile.
 //
 // Fused = true: consumers of each result word (sink): AND with a filter, and a
 // count; each thread sums the popcounts of its words over the range, and each
