@@ -259,49 +259,61 @@ struct SwarAdd {
 // Sequential reader of one stream.  A lane walking its stream one marker at a
 // time would keep a cache line of its own open for the whole walk; with every
 // lane of the device doing so, the lines no longer fit in L2 and are fetched
-// again and again.  The reader instead loads the whole 64-byte sector holding
-// the word it needs into registers and serves the following words from
-// there, so each sector is fetched once per walk.  A sector never crosses a
-// page boundary, so loading all of it is safe whenever one of its words
-// belongs to the stream; words outside the stream are never returned.
+// again and again.  The reader instead loads the whole sector of W words
+// holding the word it needs into registers and serves the following words
+// from there, so each sector is fetched once per walk.  A sector never
+// crosses a page boundary, so loading all of it is safe whenever one of its
+// words belongs to the stream; words outside the stream are never returned.
+//
+// W = 8 (64 bytes) suits walks that mostly only read markers: a lane then
+// holds half of a 128-byte line, and the other half is often still in L2
+// when the walk gets there.  W = 4 (32 bytes) suits walks that count most
+// literal words: fewer registers and a shorter select per word, at the cost
+// of lines fetched more often (up to four times).
+template <int W>
 struct SectorReader {
-  const uint64_t* base;   // 64-byte aligned, at or below the stream start
-  uint32_t off;           // words from base to the stream start (0..7)
+  static_assert(W == 4 || W == 8, "sectors of 4 or 8 words");
+  const uint64_t* base;   // W * 8-byte aligned, at or below the stream start
+  uint32_t off;           // words from base to the stream start (0..W-1)
   uint32_t cur;           // sector held (counted from base); kNone if none
-  uint64_t b0, b1, b2, b3, b4, b5, b6, b7;
+  uint64_t b[W];
   static constexpr uint32_t kNone = 0xFFFFFFFFu;
 
   __device__ __forceinline__ void reset(const uint64_t* w, uint64_t) {
     const uintptr_t a = reinterpret_cast<uintptr_t>(w);
-    base = reinterpret_cast<const uint64_t*>(a & ~(uintptr_t)63);
-    off = (uint32_t)(a >> 3) & 7u;
+    base = reinterpret_cast<const uint64_t*>(a & ~(uintptr_t)(W * 8 - 1));
+    off = (uint32_t)(a >> 3) & (uint32_t)(W - 1);
     cur = kNone;
   }
   __device__ __forceinline__ uint64_t at(uint32_t p) {
     const uint32_t g = off + p;
-    const uint32_t sec = g >> 3;
+    const uint32_t sec = g / W;
     if (sec != cur) {
       // global address space: the loads wait on the vector memory counter
       // only, not on LDS operations still in flight
       typedef unsigned int U32x4 __attribute__((ext_vector_type(4)));
       typedef const __attribute__((address_space(1))) U32x4 GlobalSector;
-      GlobalSector* q = (GlobalSector*)(base + (uint64_t)sec * 8);
-      const U32x4 v0 = q[0], v1 = q[1], v2 = q[2], v3 = q[3];
-      b0 = v0.x | ((uint64_t)v0.y << 32);
-      b1 = v0.z | ((uint64_t)v0.w << 32);
-      b2 = v1.x | ((uint64_t)v1.y << 32);
-      b3 = v1.z | ((uint64_t)v1.w << 32);
-      b4 = v2.x | ((uint64_t)v2.y << 32);
-      b5 = v2.z | ((uint64_t)v2.w << 32);
-      b6 = v3.x | ((uint64_t)v3.y << 32);
-      b7 = v3.z | ((uint64_t)v3.w << 32);
+      GlobalSector* q = (GlobalSector*)(base + (uint64_t)sec * W);
+      U32x4 v[W / 2];
+#pragma unroll
+      for (int u = 0; u < W / 2; ++u) v[u] = q[u];
+#pragma unroll
+      for (int u = 0; u < W / 2; ++u) {
+        b[2 * u] = v[u].x | ((uint64_t)v[u].y << 32);
+        b[2 * u + 1] = v[u].z | ((uint64_t)v[u].w << 32);
+      }
       cur = sec;
     }
-    const unsigned i = g & 7u;
-    const uint64_t x01 = (i & 1) ? b1 : b0, x23 = (i & 1) ? b3 : b2;
-    const uint64_t x45 = (i & 1) ? b5 : b4, x67 = (i & 1) ? b7 : b6;
-    const uint64_t x03 = (i & 2) ? x23 : x01, x47 = (i & 2) ? x67 : x45;
-    return (i & 4) ? x47 : x03;
+    const unsigned i = g % W;
+    const uint64_t x01 = (i & 1) ? b[1] : b[0], x23 = (i & 1) ? b[3] : b[2];
+    const uint64_t x03 = (i & 2) ? x23 : x01;
+    if constexpr (W == 4) {
+      return x03;
+    } else {
+      const uint64_t x45 = (i & 1) ? b[5] : b[4], x67 = (i & 1) ? b[7] : b[6];
+      const uint64_t x47 = (i & 2) ? x67 : x45;
+      return (i & 4) ? x47 : x03;
+    }
   }
 };
 
@@ -483,7 +495,10 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(
   uint32_t my_len = 0;
   Walk carry = {0, 0};
   bool carry_ok = false;
-  SectorReader rd;
+  // 32-byte sectors for the plain symmetric builds of more than 2 planes,
+  // whose walks mostly count literal words (and which then spill no
+  // register); 64-byte sectors elsewhere
+  SectorReader<(!Swar && !Fused && !Hybrid && Sym && K > 2) ? 4 : 8> rd;
   DirectReader rx;
   rd.reset(nullptr, 0);
   if (own) {
