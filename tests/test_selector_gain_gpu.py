@@ -13,7 +13,15 @@ the paper's section 5.9) and below the summed time of always running the
 carry-save counter, the dispatch without a network.  Every variant's output
 equals the carry-save result word for word, and that result equals the
 oracle on a column sample.
+
+The weights come from timings taken at steady clocks.  Right after a
+sustained load (the full-size tests before this one) the clock stays lower
+for a while, which slows the vector-ALU-bound per-position counter more than
+the memory-bound variants and moves the exhaustive best; the test therefore
+starts after an idle of IDLE_S seconds.
 """
+import time
+
 import numpy as np
 import pytest
 import torch
@@ -27,6 +35,7 @@ pytestmark = pytest.mark.gpu
 
 HELD_OUT = range(2000, 2048)
 SAMPLE_COLS = 256
+IDLE_S = 15
 
 
 def median_ms(fn, reps=5):
@@ -43,6 +52,8 @@ def median_ms(fn, reps=5):
 
 
 def test_selector_beats_default_dispatch_within_regret():
+    torch.cuda.synchronize()
+    time.sleep(IDLE_S)
     ctx = tq.tq_create(0)
     try:
         selector.load_default(ctx)
