@@ -517,8 +517,10 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(
   // next even out), and only tiles with undecided columns walk again for
   // their literal words, entering each stream through the index.  The choice
   // follows the previous span of the range: neighbouring tiles of a bitmap
-  // tend to look alike.
-  bool one_pass = Swar;
+  // tend to look alike.  A range starts in one pass where that is the likely
+  // choice: parity needs the literal words of every column that has any,
+  // and thresholds up to 2 those of every column with fewer than 2 fills.
+  bool one_pass = Swar || Par || (!Sym && K <= 2);
 
   for (uint32_t ta = tile_begin; ta < tile_end;) {
     // (the first tile of a range, whose kind is not known yet, goes alone)
