@@ -523,7 +523,8 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(
   bool one_pass = Swar || Par || (!Sym && K <= 2);
 
   for (uint32_t ta = tile_begin; ta < tile_end;) {
-    // (the first tile of a range, whose kind is not known yet, goes alone)
+    // (a range starting in two passes takes its first tile alone: its kind
+    // is not known yet)
     const uint32_t span = one_pass ? (uint32_t)kPlaneTiles : (ta == tile_begin ? 1u : (uint32_t)kSpan);
     const uint32_t nb = tile_end - ta < span ? tile_end - ta : span;
     const uint32_t lo = ta * kTile;
