@@ -410,7 +410,8 @@ namespace {
 // else the default rule.
 DenseConfig dense_shape(tq_ctx* ctx, uint32_t n, uint64_t nw, const EpiParams& epi, bool aligned16,
                         const std::function<hipError_t(const DenseConfig&)>& launch, hipStream_t stream) {
-  const DenseConfig dflt = choose_dense_config(n, nw, aligned16, ctx->num_cus);
+  const bool can_prune = epi.kind == EPI_THRESH && epi.prune && epi.theta >= 1 && epi.theta <= n;
+  const DenseConfig dflt = choose_dense_config(n, nw, aligned16, ctx->num_cus, can_prune);
   if (!ctx->autotune) return dflt;
   TuneClass c;
   c.family = kTuneDense;

@@ -61,7 +61,9 @@ bool dense_config_valid(const DenseConfig& c);
 
 int dense_planes_for(uint32_t n);
 
-DenseConfig choose_dense_config(uint32_t n, uint64_t nwords, bool aligned16, int num_cus);
+// can_prune: the query is a threshold the kernel may stop reading early for
+// (which needs one wave per column group)
+DenseConfig choose_dense_config(uint32_t n, uint64_t nwords, bool aligned16, int num_cus, bool can_prune = true);
 
 // Work-items of one launch stay below this: the dispatch packet holds the
 // grid size in 32 bits, and a larger launch is silently cut short.  Longer
