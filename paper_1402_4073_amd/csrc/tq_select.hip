@@ -142,18 +142,25 @@ void csa_input_order(const tq_bitmap* in, uint32_t n, uint64_t r_bits, uint32_t 
   // inputs left run out).  Dense first when theta is below half the expected
   // count, else sparse first; equal cardinalities keep the caller's order.
   // The result does not depend on the order.
-  std::vector<uint32_t> order(n);
-  for (uint32_t j = 0; j < n; ++j) order[j] = j;
-  if (prune && r_bits > 0) {
-    double total = 0;
-    for (uint32_t j = 0; j < n; ++j) total += (double)in[j].ones;
-    const bool dense_first = 2.0 * (double)theta < total / (double)r_bits;
-    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
-      return dense_first ? in[a].ones > in[b].ones : in[a].ones < in[b].ones;
-    });
+  dense->resize(n);
+  if (!(prune && r_bits > 0) || n > TQ_MAX_INPUTS) {   // (more inputs are rejected by the query)
+    for (uint32_t j = 0; j < n; ++j) (*dense)[j] = in[j].dense;
+    return;
   }
-  dense->clear();
-  for (uint32_t j = 0; j < n; ++j) dense->push_back(in[order[j]].dense);
+  double total = 0;
+  for (uint32_t j = 0; j < n; ++j) total += (double)in[j].ones;
+  const bool dense_first = 2.0 * (double)theta < total / (double)r_bits;
+  // one 64-bit key per input: its cardinality (complemented for dense first;
+  // at most 2^47, above any bitmap the library admits) above its position
+  // (n <= 65535), so a plain sort of the keys gives the stable order
+  constexpr uint64_t kMaxOnes = (1ull << 48) - 1;
+  std::vector<uint64_t> key(n);
+  for (uint32_t j = 0; j < n; ++j) {
+    const uint64_t c = in[j].ones < kMaxOnes ? in[j].ones : kMaxOnes;
+    key[j] = ((dense_first ? kMaxOnes - c : c) << 16) | j;
+  }
+  std::sort(key.begin(), key.end());
+  for (uint32_t j = 0; j < n; ++j) (*dense)[j] = in[(uint32_t)(key[j] & 0xFFFF)].dense;
 }
 
 void selector_destroy(tq_ctx* ctx) {
