@@ -519,8 +519,10 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(
   // follows the previous span of the range: neighbouring tiles of a bitmap
   // tend to look alike.  A range starts in one pass where that is the likely
   // choice: parity needs the literal words of every column that has any,
-  // and thresholds up to 2 those of every column with fewer than 2 fills.
-  bool one_pass = Swar || Par || (!Sym && K <= 2);
+  // thresholds up to 2 those of every column with fewer than 2 fills, and a
+  // symmetric f constant only from a small count on (at most 5 planes)
+  // those of most columns of sparse inputs (and adds them cheaply).
+  bool one_pass = Swar || Par || (!Sym && K <= 2) || (Sym && K <= 5);
 
   for (uint32_t ta = tile_begin; ta < tile_end;) {
     // (a range starting in two passes takes its first tile alone: its kind
